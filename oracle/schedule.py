@@ -1,0 +1,213 @@
+"""Revolve schedule oracle (test infrastructure only: never imported by the product path).
+
+The checkpointed reversal of Sec. "Checkpointing performance model" of the paper:
+classic Revolve (Griewank) with one memory level and a fixed number of steps.
+
+Mapping used here.  The forward states are x_0..x_N with x_k = (u^k, u^{k-1});
+reverse step k (k = N..1) needs x_k.  This is Griewank's chain with l = N + 1
+steps and c = M checkpoint slots, x_0 held in one of them; Griewank's last
+reverse step (it needs x_0) is dropped, because u^0 = 0 contributes nothing to
+the gradient.
+
+Three independent routes to the forward-step count are provided so that each
+pins the others:
+  * ``p_recurrence``: recurrence (3) of the paper, read as
+        p(l, 1) = l(l-1)/2,  p(1, c) = 0,
+        p(l, c) = min_{1 <= k <= l-1} { k + p(k, c) + p(l-k, c-1) }
+    (the printed range 1 <= k <= l would make p(l, c) refer to itself);
+  * ``p_closed``: Griewank's binomial closed form
+        t(l, c) = r l - beta(c+1, r-1),  beta(c, r) = C(c+r, c),
+        r = min{ r : beta(c, r) >= l };
+  * ``brute_force_min``: exhaustive shortest-path search over every schedule
+    for tiny l.
+The recomputation count of eq. (2) is p(N+1, M) - N: zero iff M >= N, as the
+paper remarks after eq. (3).
+
+``schedule(N, M)`` emits the action list of the recursion with the smallest
+optimal first advance k (ties broken towards the left).  Actions are int32
+triples (op, a, b):
+  1 ADVANCE x_a -> x_b, 2 STORE x_a in slot b, 3 RESTORE x_a from slot b,
+  4 FREE slot b (holding x_a), 5 REVERSE step a.
+Slot 0 holds x_0 (the state at rest) for the whole run; slots are used as a
+stack (slot b is the b-th nested checkpoint).  A RESTORE is emitted only when
+the working state is not already the one needed.
+"""
+from __future__ import annotations
+
+import heapq
+import sys
+from math import comb
+
+import numpy as np
+
+ADVANCE, STORE, RESTORE, FREE, REVERSE = 1, 2, 3, 4, 5
+
+
+def beta(c: int, r: int) -> int:
+    if r < 0 or c < 0:
+        return 0
+    return comb(c + r, c)
+
+
+def p_closed(l: int, c: int) -> int:
+    """Griewank's minimal number of forward steps to reverse l steps with c slots."""
+    if l <= 1:
+        return 0
+    if c < 1:
+        raise ValueError("need at least one slot")
+    r = 0
+    while beta(c, r) < l:
+        r += 1
+    return r * l - beta(c + 1, r - 1)
+
+
+def p_recurrence_table(L: int, C: int) -> tuple[np.ndarray, np.ndarray]:
+    """Recurrence (3) for all 1 <= l <= L, 1 <= c <= C.
+
+    Returns (p, kmin) with p[c, l] the minimum and kmin[c, l] the smallest
+    minimising first advance (0 where undefined)."""
+    p = np.zeros((C + 1, L + 1), dtype=np.int64)
+    kmin = np.zeros((C + 1, L + 1), dtype=np.int64)
+    ls = np.arange(L + 1, dtype=np.int64)
+    p[1, :] = ls * (ls - 1) // 2
+    for c in range(2, C + 1):
+        p[c, 1] = 0
+        for l in range(2, L + 1):
+            k = np.arange(1, l, dtype=np.int64)
+            cost = k + p[c, 1:l] + p[c - 1, l - k]
+            j = int(np.argmin(cost))          # first occurrence = smallest k
+            p[c, l] = cost[j]
+            kmin[c, l] = k[j]
+    return p, kmin
+
+
+def p_recurrence(l: int, c: int) -> int:
+    p, _ = p_recurrence_table(l, c)
+    return int(p[c, l])
+
+
+def _closed_vec(ls: np.ndarray, c: int) -> np.ndarray:
+    """p_closed over an array of chain lengths (exact integers)."""
+    out = np.zeros(ls.shape, dtype=np.int64)
+    if c == 1:
+        return ls * (ls - 1) // 2
+    bet = [beta(c, r) for r in range(0, 64)]
+    bet1 = [beta(c + 1, r) for r in range(0, 64)]
+    for i, l in enumerate(ls.tolist()):
+        if l <= 1:
+            out[i] = 0
+            continue
+        r = 0
+        while bet[r] < l:
+            r += 1
+        out[i] = r * l - (bet1[r - 1] if r >= 1 else 0)
+    return out
+
+
+def _first_advance(l: int, c: int) -> int:
+    """Smallest k minimising k + p(k, c) + p(l-k, c-1) (recurrence (3))."""
+    if c >= l - 1:
+        return 1
+    k = np.arange(1, l, dtype=np.int64)
+    cost = k + _closed_vec(k, c) + _closed_vec(l - k, c - 1)
+    return int(k[int(np.argmin(cost))])
+
+
+def schedule(N: int, M: int) -> np.ndarray:
+    """Action list (int32, shape (n, 3)) reversing N steps with M slots."""
+    if N < 0 or M < 1:
+        raise ValueError("need N >= 0 and M >= 1")
+    acts: list[tuple[int, int, int]] = []
+    state = {"wm": 0, "depth": 0}
+
+    def need(s: int, slot: int) -> None:
+        if state["wm"] != s:
+            acts.append((RESTORE, s, slot))
+            state["wm"] = s
+
+    def reverse(k: int) -> None:
+        acts.append((REVERSE, k, 0))
+
+    def rev(s: int, l: int, c: int, slot: int) -> None:
+        # x_s is held in `slot`; reverse steps s+l-1 .. s (step 0 dropped)
+        if l == 1:
+            if s > 0:
+                need(s, slot)
+                reverse(s)
+            return
+        if c == 1:
+            for i in range(l - 1, -1, -1):
+                if s + i == 0:
+                    break
+                need(s, slot)
+                if i > 0:
+                    acts.append((ADVANCE, s, s + i))
+                    state["wm"] = s + i
+                reverse(s + i)
+            return
+        k = _first_advance(l, c)
+        need(s, slot)
+        acts.append((ADVANCE, s, s + k))
+        state["wm"] = s + k
+        state["depth"] += 1
+        ns = state["depth"]
+        acts.append((STORE, s + k, ns))
+        rev(s + k, l - k, c - 1, ns)
+        acts.append((FREE, s + k, ns))
+        state["depth"] -= 1
+        rev(s, k, c, slot)
+
+    old = sys.getrecursionlimit()
+    sys.setrecursionlimit(max(old, 20 * (N + M) + 1000))
+    try:
+        rev(0, N + 1, M, 0)
+    finally:
+        sys.setrecursionlimit(old)
+    return np.asarray(acts, dtype=np.int32).reshape(-1, 3)
+
+
+def counts(acts: np.ndarray) -> dict:
+    """advances (forward steps), stores, restores, reverses, peak slot depth."""
+    a = np.asarray(acts)
+    adv = a[a[:, 0] == ADVANCE]
+    st = a[a[:, 0] == STORE]
+    return {
+        "advances": int((adv[:, 2] - adv[:, 1]).sum()) if len(adv) else 0,
+        "stores": int(len(st)),
+        "restores": int((a[:, 0] == RESTORE).sum()),
+        "reverses": int((a[:, 0] == REVERSE).sum()),
+        "max_slot": int(st[:, 2].max()) if len(st) else 0,
+    }
+
+
+def brute_force_min(N: int, M: int) -> int:
+    """Exhaustive search: fewest forward steps over all schedules that run the
+    reverse steps N..1 with at most M checkpoints held (x_0 counts as one)."""
+    start = (0, frozenset([0]), N)        # (working state, stored set, next reverse)
+    dist = {start: 0}
+    heap = [(0, 0, frozenset([0]), N)]
+    while heap:
+        d, wm, S, nr = heapq.heappop(heap)
+        if dist.get((wm, S, nr), 1 << 60) < d:
+            continue
+        if nr == 0:
+            return d
+        moves = []
+        if wm == nr:
+            moves.append((0, wm, S, nr - 1))
+        if wm < nr:
+            moves.append((1, wm + 1, S, nr))
+        if wm not in S and len(S) < M:
+            moves.append((0, wm, S | {wm}, nr))
+        for s in S:
+            if s != wm:
+                moves.append((0, s, S, nr))
+            if s != 0:
+                moves.append((0, wm, S - {s}, nr))
+        for cost, w2, S2, n2 in moves:
+            key = (w2, S2, n2)
+            nd = d + cost
+            if nd < dist.get(key, 1 << 60):
+                dist[key] = nd
+                heapq.heappush(heap, (nd, w2, S2, n2))
+    raise RuntimeError("no schedule found")

@@ -1,0 +1,93 @@
+"""Pins of the Revolve schedule oracle (Sec. "Checkpointing performance model", eqs. (2)-(3))."""
+import numpy as np
+import pytest
+
+from oracle import schedule as SC
+
+
+def test_recurrence_equals_closed_form():
+    L, Cmax = 120, 14
+    p, _ = SC.p_recurrence_table(L, Cmax)
+    for c in range(1, Cmax + 1):
+        for l in range(1, L + 1):
+            assert p[c, l] == SC.p_closed(l, c), (l, c)
+
+
+@pytest.mark.parametrize("l,c", [(l, c) for l in range(2, 11) for c in range(1, 5)])
+def test_recurrence_is_optimal_by_exhaustive_search(l, c):
+    assert SC.brute_force_min(l - 1, c) == SC.p_closed(l, c)
+
+
+def test_recompute_zero_iff_enough_slots():
+    """p(N+1, M) - N is the recomputation count: zero iff M >= N (remark after eq. (3))."""
+    for N in range(1, 60):
+        for M in range(1, 70):
+            rec = SC.p_closed(N + 1, M) - N
+            assert (rec == 0) == (M >= N)
+            assert rec >= 0
+
+
+def test_single_slot_is_quadratic():
+    for N in range(1, 40):
+        assert SC.p_closed(N + 1, 1) == N * (N + 1) // 2
+
+
+PINNED = [  # N, M, forward steps t(N+1, M), stores W
+    (500, 10, 1640, 346),
+    (1000, 20, 2750, 847),
+    (3000, 31, 8442, 2674),
+    (3000, 312, 5688, 2927),
+    (3000, 1250, 4750, 2941),
+    (3000, 3000, 3000, 2999),
+]
+
+
+@pytest.mark.parametrize("N,M,t,Wn", PINNED)
+def test_pinned_counts(N, M, t, Wn):
+    acts = SC.schedule(N, M)
+    c = SC.counts(acts)
+    assert c["advances"] == t == SC.p_closed(N + 1, M)
+    assert c["stores"] == Wn
+    assert c["reverses"] == N
+    assert c["max_slot"] <= M - 1
+
+
+def simulate(acts, N, M):
+    """Execute an action list symbolically; return the reverse order and check every rule."""
+    wm, stack, held, order = 0, [], {0: 0}, []
+    for op, a, b in acts.tolist():
+        if op == SC.ADVANCE:
+            assert wm == a and b > a
+            wm = b
+        elif op == SC.STORE:
+            assert wm == a and b == len(stack) + 1 and b <= M - 1
+            stack.append(a)
+            held[b] = a
+        elif op == SC.RESTORE:
+            assert held.get(b) == a and wm != a
+            wm = a
+        elif op == SC.FREE:
+            assert stack and stack[-1] == a and b == len(stack)
+            stack.pop()
+            del held[b]
+        elif op == SC.REVERSE:
+            assert wm == a
+            order.append(a)
+        else:
+            raise AssertionError(op)
+    assert not stack
+    return order
+
+
+@pytest.mark.parametrize("N,M", [(1, 1), (2, 1), (7, 2), (30, 3), (64, 5), (100, 7), (250, 16), (40, 40), (40, 100)])
+def test_schedule_is_valid(N, M):
+    acts = SC.schedule(N, M)
+    assert simulate(acts, N, M) == list(range(N, 0, -1))
+    assert SC.counts(acts)["advances"] == SC.p_closed(N + 1, M)
+
+
+def test_first_advance_is_smallest_optimal():
+    p, kmin = SC.p_recurrence_table(60, 8)
+    for c in range(2, 9):
+        for l in range(2, 61):
+            assert SC._first_advance(l, c) == kmin[c, l]
