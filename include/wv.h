@@ -1,0 +1,237 @@
+/*
+ * wv.h -- checkpointed, compressed adjoint acoustic gradients on MI355X (gfx950).
+ *
+ * C ABI of the library libwv.so.  Plain pointers and sizes only.
+ *
+ * Method: Kukreja, Hueckelheim, Louboutin, Hovland, Gorman, "Combining
+ * checkpointing and data compression to accelerate adjoint-based optimization
+ * problems".  The problem solved per shot is the one stated in Sec. "Problem and
+ * test case": the acoustic wave equation, eq. (7), m u_tt - lap u = q with
+ * m = 1/c^2, the misfit of eq. (8), phi = 1/2 ||d_sim - d_obs||^2, and its
+ * adjoint-state gradient.  The reversal is checkpointed with classic Revolve
+ * (Sec. "Checkpointing performance model", eqs. (2)-(3)) and, when a tolerance
+ * is given, every stored checkpoint passes through a ZFP-kind fixed-accuracy
+ * (absolute error) block-transform codec (Sec. "Lossy Compression",
+ * Sec. "Performance model including compression", eq. (6)).
+ *
+ * Discretisation (the paper gives only the continuous problem):
+ *   - grid: n[a] interior points per axis plus nbl absorbing cells on each side;
+ *     axis 0 (x) is contiguous, the last axis is depth; arrays are C order
+ *     [z][y][x] (3-D) or [z][x] (2-D); P = prod(n[a] + 2 nbl);
+ *   - centred space_order-th order second differences (space_order = 2K,
+ *     K = 1..8), zero halo outside the padded grid;
+ *   - damping a(x) = dt/2 sum_a smax_a (delta_a/nbl)^2,
+ *     smax_a = 3 vmax ln(1000) / (2 nbl h[a]), delta_a = cells into the layer;
+ *   - OT2 leapfrog: u^{n+1} = [2u^n - (1-a)u^{n-1} + dt^2 c^2 (lap u^n + s^n)]/(1+a),
+ *     u^0 = u^{-1} = 0, n = 0..nt-1; data d^n = R u^n, n = 0..nt;
+ *     s^n = S^T q^n (multilinear spreading of the wavelet sample q^n);
+ *   - gradient with respect to m = 1/c^2 (the paper's model parameter):
+ *       g = -(1/dt^2) sum_{k=1..nt} u^k [(1+a)lam^{k-1} - 2lam^k + (1-a)lam^{k+1}]
+ *     with the discrete adjoint lam (exact transpose of the recursion above).
+ *
+ * Precision: wavefields are binary32; the gradient accumulates in binary64;
+ * misfit and other reductions are binary64.
+ *
+ * Conventions for every call:
+ *   - device pointers are caller-owned; the library never allocates device
+ *     memory: every call takes a caller workspace `ws` of at least the size the
+ *     matching *_workspace_bytes query returns (256-byte aligned);
+ *   - inputs are read-only; outputs are fully overwritten;
+ *   - all device work is enqueued on `stream` (a hipStream_t, NULL = default);
+ *     calls synchronise the stream only where a status must be read back
+ *     (noted per call); one call per stream at a time;
+ *   - return value: WV_OK or a negative WV_E* code (wv_strerror).
+ */
+#ifndef WV_H
+#define WV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WV_OK 0
+#define WV_EINVAL (-1)     /* bad argument, dims, geometry, non-finite or out-of-range velocity */
+#define WV_ECFL (-2)       /* dt above the stability limit wv_cfl_dt */
+#define WV_EBUDGET (-3)    /* mem_budget below one checkpoint */
+#define WV_EARENA (-4)     /* compressed checkpoints overflowed mem_budget (ratio estimate too optimistic) */
+#define WV_ENOMEM (-5)     /* workspace too small */
+#define WV_EHIP (-6)       /* a HIP runtime call failed */
+#define WV_EUNSTABLE (-7)  /* non-finite wavefield detected */
+#define WV_ENOTIMPL (-8)
+#define WV_ECAP (-9)       /* codec output buffer too small */
+
+typedef struct {
+    int ndim;            /* 2 or 3 */
+    int n[3];            /* interior points per axis, axis 0 fastest, last = depth */
+    double h[3];         /* grid spacing per axis, metres */
+    int nbl;             /* absorbing cells on each side (>= 0) */
+    int space_order;     /* 2, 4, ..., 16 */
+    int nt;              /* number of time steps N (>= 1) */
+    double dt;           /* time step, seconds; must satisfy dt <= wv_cfl_dt(...) */
+    double vmax;         /* m/s: upper bound of vel; sets the damping strength and CFL check */
+    const float *vel;    /* device [P] padded velocity, m/s, 0 < vel <= vmax */
+} wv_model;
+
+typedef struct {
+    int nsrc;                /* >= 1 point sources sharing one wavelet */
+    const double *src_xyz;   /* host [nsrc][ndim], metres from the first interior point, (x[,y],z) */
+    const float *wavelet;    /* device [nt] wavelet samples q^n */
+    int nrec;                /* >= 1 receivers */
+    const double *rec_xyz;   /* host [nrec][ndim], same convention */
+} wv_geom;
+
+typedef struct {
+    int timing;          /* input: non-zero = time every schedule action with HIP events */
+    long advances;       /* forward steps executed (first sweep + recomputation) */
+    long stores;         /* checkpoints written */
+    long restores;       /* checkpoints read back */
+    long reverses;       /* adjoint steps */
+    long slots;          /* M: checkpoint slots of the schedule (x_0 included) */
+    double bytes_stored; /* sum of bytes written to checkpoint memory */
+    double peak_bytes;   /* peak checkpoint memory in use */
+    double ratio;        /* achieved compression ratio (uncompressed bytes / stored bytes), 1 if tol = 0 */
+    double ratio_planned;/* ratio the slot count M was planned with */
+    double misfit;       /* phi (wv_misfit_gradient only) */
+    double ms_total;     /* device time of the call, ms (HIP events) */
+    double ms_forward;   /* with timing: device ms in forward steps (stencil + source injection) */
+    double ms_adjoint;   /* with timing: device ms in adjoint steps (stencil + gradient + residual injection) */
+    double ms_store;     /* with timing: device ms writing checkpoints (copies or encodes) */
+    double ms_restore;   /* with timing: device ms reading checkpoints (copies or decodes) */
+} wv_stats;
+
+/* ------------------------------------------------------------------ queries */
+
+/* Stability limit of the OT2 scheme with this stencil (von Neumann):
+ *   dt_max = 2 / (vmax sqrt(sum_a S / h[a]^2)),  S = |a_0| + 2 sum_k |a_k|.
+ * Host only; returns <= 0 on bad arguments. */
+double wv_cfl_dt(int ndim, const double *h, int space_order, double vmax);
+
+/* Operation selectors for wv_workspace_bytes. */
+#define WV_OP_FORWARD 0
+#define WV_OP_GRADIENT 1
+
+/* Workspace bytes needed by wv_forward (op = WV_OP_FORWARD, mem_budget ignored)
+ * or by wv_gradient / wv_misfit_gradient / wv_adjoint_src (op = WV_OP_GRADIENT;
+ * the checkpoint arena of mem_budget bytes is part of the workspace).  Returns 0
+ * on invalid arguments.  Host only. */
+size_t wv_workspace_bytes(const wv_model *model, const wv_geom *geom, int op, size_t mem_budget);
+
+/* ------------------------------------------------------------------ solver */
+
+/* Forward modelling, eq. (7): data[n][r] = (R u^n)_r for n = 0..nt (row 0 is 0).
+ *   data       device [nt+1][nrec] float, overwritten
+ *   state_out  device [2][P] float or NULL: receives (u^nt, u^{nt-1})
+ * Synchronises the stream once after set-up to validate the velocity. */
+int wv_forward(const wv_model *model, const wv_geom *geom, float *data, float *state_out,
+               void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint-state gradient with respect to m for a given data residual r = d_sim - d_obs,
+ * reversed with Revolve checkpointing inside mem_budget bytes of checkpoint memory.
+ *   residual    device [nt+1][nrec] float (row 0 unused)
+ *   mem_budget  bytes available for checkpoints (SI bytes); the slot count is
+ *               M = min(nt, 1 + floor(mem_budget / (S / F))), S = 8 P bytes per
+ *               uncompressed checkpoint (u^k and its increment u^k - u^{k-1}),
+ *               F = 1 if tol == 0, else ratio_hint if > 0, else the ratio measured
+ *               on the final state of a probe forward run (the paper uses the
+ *               last time step as the worst-case compressibility);
+ *   tol         0: checkpoints are exact copies; > 0: absolute error bound of the codec
+ *   grad_m      device [P] double, overwritten (layer cells included)
+ *   stats       host, may be NULL
+ * Returns WV_EARENA if the compressed checkpoints did not fit (retry with a smaller
+ * ratio_hint); the gradient is then invalid.  Synchronises the stream at the end. */
+int wv_gradient(const wv_model *model, const wv_geom *geom, const float *residual, size_t mem_budget,
+                double tol, double ratio_hint, double *grad_m, wv_stats *stats,
+                void *ws, size_t ws_bytes, void *stream);
+
+/* One checkpointed sweep for misfit and gradient: the first forward pass of the
+ * schedule produces d_sim, then r = d_sim - d_obs (binary64 difference),
+ * phi = 1/2 sum r^2 (eq. (8), binary64), then the reversal as in wv_gradient.
+ *   d_obs   device [nt+1][nrec] float
+ *   misfit  host double, receives phi
+ *   d_sim   device [nt+1][nrec] float or NULL */
+int wv_misfit_gradient(const wv_model *model, const wv_geom *geom, const float *d_obs, size_t mem_budget,
+                       double tol, double ratio_hint, double *misfit, double *grad_m, float *d_sim,
+                       wv_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint source (dot-product test hook): src_adj[n] = sum_s (S lam^n)_s for
+ * n = 0..nt-1, the derivative of <d, r> with respect to the wavelet sample q^n.
+ *   residual device [nt+1][nrec] float; src_adj device [nt] float. */
+int wv_adjoint_src(const wv_model *model, const wv_geom *geom, const float *residual, float *src_adj,
+                   void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ velocity helpers (autograd) */
+
+/* vel_padded = interior velocity extended into the absorbing layer by the nearest
+ * interior value.  vel_interior device [prod n] float, vel_padded device [P] float. */
+int wv_pad_velocity(int ndim, const int *n, int nbl, const float *vel_interior, float *vel_padded, void *stream);
+
+/* Gradient with respect to the interior velocity from the gradient with respect to
+ * m on the padded grid: chain rule dm/dc = -2/c^3, then the adjoint of the edge
+ * padding (layer cells summed into the interior cell they copy).
+ *   vel_padded device [P] float, grad_m device [P] double, grad_vel device [prod n] double. */
+int wv_velocity_gradient(int ndim, const int *n, int nbl, const float *vel_padded, const double *grad_m,
+                         double *grad_vel, void *stream);
+
+/* ------------------------------------------------------------------ codec (test hooks) */
+
+/* Stream format (one stream per binary32 field, little endian):
+ *   header 64 B: u32 magic 0x4B50465A, u32 version 1, u32 ndim, u32 dims[3] (axis 0 fastest,
+ *     2-D dims[2] = 1), f64 tol, u32 nblocks, u32 nchunks, u32 256, u32 0, u64 data_words,
+ *     u64 total_bytes, 8 zero bytes;
+ *   u64 chunk_word_offset[nchunks]; u16 block_bits[nblocks] zero-padded to 8 B; u64 data[].
+ * Blocks of 4^d values in C order of block coordinates; chunks of 256 blocks start at a
+ * word boundary; inside a chunk blocks follow at consecutive bit offsets, LSB first.
+ * Per block: emax (max frexp exponent, >= -126), prec = clamp(emax - floor(log2 tol) + 2(d+1),
+ * 0, 32); a single 0 bit if the block is zero or prec = 0, else 1, emax+127 in 8 bits,
+ * then bit planes 31..32-prec of the negabinary sequency-ordered coefficients of the
+ * separable lifting transform of trunc(x 2^(30-emax)), with group tests.
+ * Guarantees |x - decode(encode(x))| <= tol where binary32 can resolve tol. */
+
+/* Device scratch bytes wv_zfpk_encode needs (chunk status words). */
+size_t wv_zfpk_workspace_bytes(int ndim, const int *dims);
+
+/* Upper bound of the stream size for these dims (any tolerance). */
+size_t wv_zfpk_max_bytes(int ndim, const int *dims);
+
+/* Encode field (device [dims[2]][dims[1]][dims[0]] or [dims[1]][dims[0]] float) at
+ * absolute tolerance tol > 0 into out (device, cap bytes, 8-byte aligned).
+ * *nbytes (host) receives the stream size.  Synchronises the stream.
+ * WV_ECAP if cap is too small, WV_EINVAL for a non-finite value or bad arguments. */
+int wv_zfpk_encode(const float *field, int ndim, const int *dims, double tol, void *out, size_t cap,
+                   size_t *nbytes, void *ws, size_t ws_bytes, void *stream);
+
+/* Decode a stream made by wv_zfpk_encode into field (device, same dims). */
+int wv_zfpk_decode(const void *in, int ndim, const int *dims, float *field, void *stream);
+
+/* ------------------------------------------------------------------ schedule (host) */
+
+/* Action list of the Revolve reversal of nt steps with M slots (x_0 held in slot 0),
+ * the same schedule the gradient calls execute.  Actions are int32 triples (op, a, b):
+ *   1 ADVANCE x_a -> x_b, 2 STORE x_a in slot b, 3 RESTORE x_a from slot b,
+ *   4 FREE slot b (holding x_a), 5 REVERSE step a.
+ * The first advance of every split is the smallest optimal one (Griewank's
+ * binomial interval).  actions: host [cap][3]; *n_actions receives the count;
+ * WV_ECAP if cap is too small (the count is still returned). */
+int wv_schedule(int nt, int M, int32_t *actions, size_t cap, size_t *n_actions);
+
+/* Forward steps of that schedule: t(nt+1, M) = r (nt+1) - C(M+1+r-1, r-1),
+ * r = min{r : C(M+r, r) >= nt+1}. */
+long wv_schedule_forward_steps(int nt, int M);
+
+const char *wv_strerror(int code);
+
+/* Detail of the last WV_EHIP returned on the calling thread: the failing runtime
+ * call, its source line and the HIP error string (empty if none). */
+const char *wv_last_error(void);
+
+/* Library version string. */
+const char *wv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WV_H */

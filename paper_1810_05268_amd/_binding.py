@@ -1,0 +1,267 @@
+"""ctypes binding of libwv.so (the C ABI declared in include/wv.h).
+
+Argument marshalling only: every step of the solver, schedule and codec runs in
+the library.  Device buffers are torch tensors on a ROCm device; their raw
+pointers and the current HIP stream are handed to the C functions.  The library
+must have been built (``paper_1810_05268_amd.build``); if it is missing this
+module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwv.so")
+
+WV_OK, WV_EINVAL, WV_ECFL, WV_EBUDGET, WV_EARENA, WV_ENOMEM, WV_EHIP, WV_EUNSTABLE, WV_ENOTIMPL, WV_ECAP = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
+OP_FORWARD, OP_GRADIENT = 0, 1
+ADVANCE, STORE, RESTORE, FREE, REVERSE = 1, 2, 3, 4, 5
+
+
+class WvError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        detail = ""
+        if code == WV_EHIP:
+            try:
+                detail = " [" + lib().wv_last_error().decode() + "]"
+            except Exception:    # noqa: BLE001 - formatting only
+                pass
+        super().__init__(f"{where}: {strerror(code)} ({code}){detail}")
+
+
+class WvModel(C.Structure):
+    _fields_ = [("ndim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double * 3), ("nbl", C.c_int),
+                ("space_order", C.c_int), ("nt", C.c_int), ("dt", C.c_double), ("vmax", C.c_double),
+                ("vel", C.c_void_p)]
+
+
+class WvGeom(C.Structure):
+    _fields_ = [("nsrc", C.c_int), ("src_xyz", C.POINTER(C.c_double)), ("wavelet", C.c_void_p),
+                ("nrec", C.c_int), ("rec_xyz", C.POINTER(C.c_double))]
+
+
+class WvStats(C.Structure):
+    _fields_ = [("timing", C.c_int), ("advances", C.c_long), ("stores", C.c_long), ("restores", C.c_long),
+                ("reverses", C.c_long), ("slots", C.c_long), ("bytes_stored", C.c_double),
+                ("peak_bytes", C.c_double), ("ratio", C.c_double), ("ratio_planned", C.c_double),
+                ("misfit", C.c_double), ("ms_total", C.c_double), ("ms_forward", C.c_double),
+                ("ms_adjoint", C.c_double), ("ms_store", C.c_double), ("ms_restore", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# every symbol include/wv.h declares
+SYMBOLS = ["wv_cfl_dt", "wv_workspace_bytes", "wv_forward", "wv_gradient", "wv_misfit_gradient", "wv_adjoint_src",
+           "wv_pad_velocity", "wv_velocity_gradient", "wv_zfpk_workspace_bytes", "wv_zfpk_max_bytes",
+           "wv_zfpk_encode", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_strerror",
+           "wv_last_error", "wv_version"]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                               "(python -m paper_1810_05268_amd.build)")
+        # torch ships its own HIP runtime under the same soname; load it first so that
+        # the library and torch share one runtime (and one device context) in the process
+        import torch  # noqa: F401
+        L = C.CDLL(LIB_PATH)
+        vp, dp, ip, sz = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_size_t
+        mp, gp, stp = C.POINTER(WvModel), C.POINTER(WvGeom), C.POINTER(WvStats)
+        L.wv_cfl_dt.argtypes = [C.c_int, dp, C.c_int, C.c_double]
+        L.wv_cfl_dt.restype = C.c_double
+        L.wv_workspace_bytes.argtypes = [mp, gp, C.c_int, sz]
+        L.wv_workspace_bytes.restype = sz
+        L.wv_forward.argtypes = [mp, gp, vp, vp, vp, sz, vp]
+        L.wv_gradient.argtypes = [mp, gp, vp, sz, C.c_double, C.c_double, vp, stp, vp, sz, vp]
+        L.wv_misfit_gradient.argtypes = [mp, gp, vp, sz, C.c_double, C.c_double, dp, vp, vp, stp, vp, sz, vp]
+        L.wv_adjoint_src.argtypes = [mp, gp, vp, vp, vp, sz, vp]
+        L.wv_pad_velocity.argtypes = [C.c_int, ip, C.c_int, vp, vp, vp]
+        L.wv_velocity_gradient.argtypes = [C.c_int, ip, C.c_int, vp, vp, vp, vp]
+        L.wv_zfpk_workspace_bytes.argtypes = [C.c_int, ip]
+        L.wv_zfpk_workspace_bytes.restype = sz
+        L.wv_zfpk_max_bytes.argtypes = [C.c_int, ip]
+        L.wv_zfpk_max_bytes.restype = sz
+        L.wv_zfpk_encode.argtypes = [vp, C.c_int, ip, C.c_double, vp, sz, C.POINTER(C.c_size_t), vp, sz, vp]
+        L.wv_zfpk_decode.argtypes = [vp, C.c_int, ip, vp, vp]
+        L.wv_schedule.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int32), sz, C.POINTER(C.c_size_t)]
+        L.wv_schedule_forward_steps.argtypes = [C.c_int, C.c_int]
+        L.wv_schedule_forward_steps.restype = C.c_long
+        L.wv_strerror.argtypes = [C.c_int]
+        L.wv_strerror.restype = C.c_char_p
+        L.wv_version.restype = C.c_char_p
+        L.wv_last_error.restype = C.c_char_p
+        for name in SYMBOLS:
+            getattr(L, name)
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().wv_strerror(code).decode()
+    except Exception:        # noqa: BLE001 - used while formatting another error
+        return "error"
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != WV_OK:
+        raise WvError(rc, where)
+
+
+def _ptr(t) -> int | None:
+    """Raw device pointer of a torch tensor (or an int, or None)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int | None:
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dims(ndim, dims):
+    d = (C.c_int * 3)(*(list(dims) + [1] * (3 - len(dims))))
+    return d
+
+
+# ------------------------------------------------------------------ host-only calls
+
+def cfl_dt(ndim: int, h, space_order: int, vmax: float) -> float:
+    hh = (C.c_double * 3)(*(list(h)[:ndim] + [1.0] * (3 - ndim)))
+    return float(lib().wv_cfl_dt(ndim, hh, space_order, vmax))
+
+
+def schedule(nt: int, M: int) -> np.ndarray:
+    n = C.c_size_t(0)
+    lib().wv_schedule(nt, M, None, 0, C.byref(n))
+    out = np.zeros((max(n.value, 1), 3), dtype=np.int32)
+    _check(lib().wv_schedule(nt, M, out.ctypes.data_as(C.POINTER(C.c_int32)), n.value, C.byref(n)), "wv_schedule")
+    return out[: n.value]
+
+
+def schedule_forward_steps(nt: int, M: int) -> int:
+    return int(lib().wv_schedule_forward_steps(nt, M))
+
+
+def zfpk_max_bytes(ndim: int, dims) -> int:
+    return int(lib().wv_zfpk_max_bytes(ndim, _dims(ndim, dims)))
+
+
+def zfpk_workspace_bytes(ndim: int, dims) -> int:
+    return int(lib().wv_zfpk_workspace_bytes(ndim, _dims(ndim, dims)))
+
+
+# ------------------------------------------------------------------ model / geometry structs
+
+class Problem:
+    """C structs for one shot.  vel and wavelet are device tensors (float32);
+    src/rec are host float64 arrays (metres, axis order x[, y], z)."""
+
+    def __init__(self, ndim, n, h, nbl, space_order, nt, dt, vmax, vel, src, wavelet, rec):
+        self.model = WvModel()
+        self.model.ndim = ndim
+        for a in range(3):
+            self.model.n[a] = int(n[a]) if a < ndim else 1
+            self.model.h[a] = float(h[a]) if a < ndim else 1.0
+        self.model.nbl, self.model.space_order, self.model.nt = int(nbl), int(space_order), int(nt)
+        self.model.dt, self.model.vmax = float(dt), float(vmax)
+        self.vel = vel
+        self.model.vel = _ptr(vel)
+        self.src = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, ndim)
+        self.rec = np.ascontiguousarray(rec, dtype=np.float64).reshape(-1, ndim)
+        self.wavelet = wavelet
+        self.geom = WvGeom()
+        self.geom.nsrc = len(self.src)
+        self.geom.src_xyz = self.src.ctypes.data_as(C.POINTER(C.c_double))
+        self.geom.wavelet = _ptr(wavelet)
+        self.geom.nrec = len(self.rec)
+        self.geom.rec_xyz = self.rec.ctypes.data_as(C.POINTER(C.c_double))
+        self.ndim, self.nt, self.nrec = ndim, int(nt), len(self.rec)
+        self.padded = tuple(int(n[a]) + 2 * int(nbl) for a in range(ndim))
+        self.P = int(np.prod(self.padded))
+
+    def set_vel(self, vel) -> None:
+        self.vel = vel
+        self.model.vel = _ptr(vel)
+
+    def workspace_bytes(self, op: int, mem_budget: int = 0) -> int:
+        b = int(lib().wv_workspace_bytes(C.byref(self.model), C.byref(self.geom), op, int(mem_budget)))
+        if b == 0:
+            raise WvError(WV_EINVAL, "wv_workspace_bytes")
+        return b
+
+
+# ------------------------------------------------------------------ device calls
+
+def forward(pb: Problem, data, ws, state_out=None, stream=None) -> None:
+    _check(lib().wv_forward(C.byref(pb.model), C.byref(pb.geom), _ptr(data), _ptr(state_out), _ptr(ws),
+                            ws.numel() * ws.element_size(), _stream(stream)), "wv_forward")
+
+
+def gradient(pb: Problem, residual, mem_budget: int, tol: float, grad, ws, ratio_hint: float = 0.0,
+             stream=None, timing: bool = False) -> dict:
+    st = WvStats()
+    st.timing = 1 if timing else 0
+    _check(lib().wv_gradient(C.byref(pb.model), C.byref(pb.geom), _ptr(residual), int(mem_budget), float(tol),
+                             float(ratio_hint), _ptr(grad), C.byref(st), _ptr(ws), ws.numel() * ws.element_size(),
+                             _stream(stream)), "wv_gradient")
+    return st.as_dict()
+
+
+def misfit_gradient(pb: Problem, d_obs, mem_budget: int, tol: float, grad, ws, ratio_hint: float = 0.0,
+                    d_sim=None, stream=None, timing: bool = False) -> tuple[float, dict]:
+    st = WvStats()
+    st.timing = 1 if timing else 0
+    phi = C.c_double(0.0)
+    _check(lib().wv_misfit_gradient(C.byref(pb.model), C.byref(pb.geom), _ptr(d_obs), int(mem_budget), float(tol),
+                                    float(ratio_hint), C.byref(phi), _ptr(grad), _ptr(d_sim), C.byref(st), _ptr(ws),
+                                    ws.numel() * ws.element_size(), _stream(stream)), "wv_misfit_gradient")
+    return float(phi.value), st.as_dict()
+
+
+def adjoint_src(pb: Problem, residual, src_adj, ws, stream=None) -> None:
+    _check(lib().wv_adjoint_src(C.byref(pb.model), C.byref(pb.geom), _ptr(residual), _ptr(src_adj), _ptr(ws),
+                                ws.numel() * ws.element_size(), _stream(stream)), "wv_adjoint_src")
+
+
+def pad_velocity(ndim: int, n, nbl: int, vel_interior, vel_padded, stream=None) -> None:
+    _check(lib().wv_pad_velocity(ndim, _dims(ndim, n), nbl, _ptr(vel_interior), _ptr(vel_padded),
+                                 _stream(stream)), "wv_pad_velocity")
+
+
+def velocity_gradient(ndim: int, n, nbl: int, vel_padded, grad_m, grad_vel, stream=None) -> None:
+    _check(lib().wv_velocity_gradient(ndim, _dims(ndim, n), nbl, _ptr(vel_padded), _ptr(grad_m), _ptr(grad_vel),
+                                      _stream(stream)), "wv_velocity_gradient")
+
+
+def zfpk_encode(field, tol: float, out, ws, stream=None) -> int:
+    """Encode a device float32 field ([z][x] or [z][y][x]); returns the stream bytes."""
+    ndim = field.dim()
+    dims = list(reversed(field.shape))
+    nb = C.c_size_t(0)
+    _check(lib().wv_zfpk_encode(_ptr(field), ndim, _dims(ndim, dims), float(tol), _ptr(out),
+                                out.numel() * out.element_size(), C.byref(nb), _ptr(ws),
+                                ws.numel() * ws.element_size(), _stream(stream)), "wv_zfpk_encode")
+    return int(nb.value)
+
+
+def zfpk_decode(stream_buf, field, stream=None) -> None:
+    ndim = field.dim()
+    dims = list(reversed(field.shape))
+    _check(lib().wv_zfpk_decode(_ptr(stream_buf), ndim, _dims(ndim, dims), _ptr(field), _stream(stream)),
+           "wv_zfpk_decode")

@@ -1,0 +1,1019 @@
+// Host runtime and C ABI of libwv: validation, set-up tables, the Revolve schedule,
+// and the executor that runs a schedule as a stream of kernel launches.
+//
+// Paper: Kukreja et al., "Combining checkpointing and data compression to
+// accelerate adjoint-based optimization problems".  The executor follows the
+// checkpointing runtime model of Sec. "Checkpointing performance model": the
+// operator's working memory holds the current state; a store copies it into
+// separate checkpoint memory, a restore copies it back (eq. (4)); with a
+// tolerance the copies pass through the codec (eq. (6)) and the slot count grows
+// by the compression ratio.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "wv_internal.h"
+
+using namespace wv;
+
+namespace {
+
+constexpr int ADVANCE = 1, STORE = 2, RESTORE = 3, FREE = 4, REVERSE = 5;
+
+// ------------------------------------------------------------------ finite differences
+// a_k = 2(-1)^(k+1)/k^2 * prod_{i=1..k} (K-k+i)/(K+i), a_0 = -2 sum a_k
+// ((K!)^2 / ((K-k)!(K+k)!) written as a product of k ratios).
+void fd_weights(int K, double *a)
+{
+    double s = 0.0;
+    for (int k = 1; k <= K; ++k) {
+        double r = 1.0;
+        for (int i = 1; i <= k; ++i) r *= (double)(K - k + i) / (double)(K + i);
+        const double v = 2.0 * r / ((double)k * (double)k);
+        a[k] = (k & 1) ? v : -v;
+        s += a[k];
+    }
+    a[0] = -2.0 * s;
+}
+
+double cfl_limit(int ndim, const double *h, int order, double vmax)
+{
+    if (ndim < 2 || ndim > 3 || order < 2 || order > 16 || (order & 1) || !(vmax > 0)) return -1.0;
+    double a[kMaxK + 1];
+    const int K = order / 2;
+    fd_weights(K, a);
+    double S = std::fabs(a[0]);
+    for (int k = 1; k <= K; ++k) S += 2.0 * std::fabs(a[k]);
+    double q = 0.0;
+    for (int d = 0; d < ndim; ++d) {
+        if (!(h[d] > 0)) return -1.0;
+        q += S / (h[d] * h[d]);
+    }
+    return 2.0 / (vmax * std::sqrt(q));
+}
+
+// ------------------------------------------------------------------ schedule
+constexpr long long kSat = (long long)1 << 62;
+
+// C(c+r, c), saturating
+long long binom(int c, long long r)
+{
+    if (r < 0 || c < 0) return 0;
+    long long res = 1;
+    for (long long i = 1; i <= r; ++i) {
+        __int128 t = (__int128)res * (c + i);
+        t /= i;
+        if (t >= kSat) return kSat;
+        res = (long long)t;
+    }
+    return res;
+}
+
+int repetitions(long long l, int c)
+{
+    int r = 0;
+    while (binom(c, r) < l) ++r;
+    return r;
+}
+
+// smallest optimal first advance for a segment of l steps and c slots (c >= 2):
+// Griewank's optimal set is the interval
+// [max(beta(c,r-2), l-beta(c-1,r), 1), min(beta(c,r-1), l-beta(c-1,r-1), l-1)].
+long long first_advance(long long l, int c)
+{
+    if (c >= l - 1) return 1;
+    const int r = repetitions(l, c);
+    long long lo = binom(c, r - 2);
+    lo = std::max(lo, l - binom(c - 1, r));
+    return std::max(lo, 1LL);
+}
+
+long long forward_steps(long long nt, int M)
+{
+    const long long l = nt + 1;
+    if (l <= 1) return 0;
+    if (M <= 1) return l * (l - 1) / 2;
+    const int r = repetitions(l, M);
+    return r * l - binom(M + 1, r - 1);
+}
+
+struct Frame {
+    int s;
+    long long l;
+    int c, slot;
+    long long k;
+    int nslot, phase;
+};
+
+void make_schedule(int nt, int M, std::vector<int32_t> &out)
+{
+    out.clear();
+    int wm = 0, depth = 0;
+    auto emit = [&](int op, long long a, long long b) {
+        out.push_back(op);
+        out.push_back((int32_t)a);
+        out.push_back((int32_t)b);
+    };
+    auto need = [&](int s, int slot) {
+        if (wm != s) {
+            emit(RESTORE, s, slot);
+            wm = s;
+        }
+    };
+    std::vector<Frame> st;
+    st.push_back({0, (long long)nt + 1, M, 0, 0, 0, 0});
+    while (!st.empty()) {
+        const Frame f = st.back();
+        st.pop_back();
+        if (f.phase == 1) {           // right part done: release its checkpoint, then the left part
+            emit(FREE, f.s + f.k, f.nslot);
+            --depth;
+            st.push_back({f.s, f.k, f.c, f.slot, 0, 0, 0});
+            continue;
+        }
+        if (f.l == 1) {
+            if (f.s > 0) {
+                need(f.s, f.slot);
+                emit(REVERSE, f.s, 0);
+            }
+            continue;
+        }
+        if (f.c == 1) {
+            for (long long i = f.l - 1; i >= 0; --i) {
+                if (f.s + i == 0) break;
+                need(f.s, f.slot);
+                if (i > 0) {
+                    emit(ADVANCE, f.s, f.s + i);
+                    wm = (int)(f.s + i);
+                }
+                emit(REVERSE, f.s + i, 0);
+            }
+            continue;
+        }
+        const long long k = first_advance(f.l, f.c);
+        need(f.s, f.slot);
+        emit(ADVANCE, f.s, f.s + k);
+        wm = (int)(f.s + k);
+        ++depth;
+        emit(STORE, f.s + k, depth);
+        st.push_back({f.s, f.l, f.c, f.slot, k, depth, 1});
+        st.push_back({(int)(f.s + k), f.l - k, f.c - 1, depth, 0, 0, 0});
+    }
+}
+
+// ------------------------------------------------------------------ set-up
+thread_local char g_detail[256] = "";
+
+int hip_fail(hipError_t e, const char *what, int line)
+{
+    std::snprintf(g_detail, sizeof(g_detail), "%s (line %d): %s", what, line, hipGetErrorString(e));
+    return WV_EHIP;
+}
+
+#define HIPCHK(x)                                            \
+    do {                                                     \
+        const hipError_t e_ = (x);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #x, __LINE__); \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    size_t bk, U0, U1, D, L0, L1, MU, W;
+    size_t src_tab, rec_tab, tab_bytes;
+    size_t res, dsim, partials, flags, offs, arena;
+    size_t total;
+    size_t arena_bytes;
+    long long nchunks_max;
+    int offs_n;
+};
+
+constexpr size_t kBk = 4096;
+// bookkeeping words inside bk
+constexpr size_t kErr = 0, kTicket = 64, kMisfit = 128, kStats = 192, kZero = 256, kProbeNext = 264, kScal = 320;
+constexpr int kParts = 1024;
+
+struct Setup {
+    Grid g;
+    long long P = 0;
+    int ndim = 0, N[3] = {1, 1, 1};
+    int nc = 4;
+    // host tables, packed
+    std::vector<int> src_gidx, rec_gidx, src_pts, src_start, src_col, rec_pts, rec_start, rec_col;
+    std::vector<float> src_gwt, rec_gwt, src_swt, rec_swt;
+};
+
+int validate_model(const wv_model *m, Setup &su)
+{
+    if (!m || (m->ndim != 2 && m->ndim != 3)) return WV_EINVAL;
+    if (m->space_order < 2 || m->space_order > 16 || (m->space_order & 1)) return WV_EINVAL;
+    if (m->nbl < 0 || m->nt < 1 || !(m->dt > 0) || !(m->vmax > 0) || !std::isfinite(m->vmax) || !m->vel)
+        return WV_EINVAL;
+    long long P = 1;
+    for (int a = 0; a < m->ndim; ++a) {
+        if (m->n[a] < 1 || !(m->h[a] > 0) || !std::isfinite(m->h[a])) return WV_EINVAL;
+        su.N[a] = m->n[a] + 2 * m->nbl;
+        P *= su.N[a];
+    }
+    if (P >= (1LL << 31)) return WV_EINVAL;
+    su.P = P;
+    su.ndim = m->ndim;
+    const double lim = cfl_limit(m->ndim, m->h, m->space_order, m->vmax);
+    if (!(lim > 0)) return WV_EINVAL;
+    if (m->dt > lim * (1.0 + 1e-12)) return WV_ECFL;
+    Grid &g = su.g;
+    std::memset(&g, 0, sizeof(g));
+    g.ndim = m->ndim;
+    g.K = m->space_order / 2;
+    g.P = P;
+    double a[kMaxK + 1];
+    fd_weights(g.K, a);
+    // array axes: x = model axis 0; 3-D: y = axis 1, z = axis 2; 2-D: z = axis 1
+    const int ax_y = m->ndim == 3 ? 1 : -1, ax_z = m->ndim == 3 ? 2 : 1;
+    g.nx = su.N[0];
+    g.ny = ax_y >= 0 ? su.N[ax_y] : 1;
+    g.nz = su.N[ax_z];
+    const int axes[3] = {0, ax_y, ax_z};
+    float *cc[3] = {g.cx, g.cy, g.cz};
+    float *dd[3] = {&g.dampx, &g.dampy, &g.dampz};
+    for (int t = 0; t < 3; ++t) {
+        const int ax = axes[t];
+        if (ax < 0) {
+            g.ix0[t] = 0;
+            g.ix1[t] = 0;
+            *dd[t] = 0.0f;
+            continue;
+        }
+        const double h = m->h[ax];
+        for (int k = 1; k <= g.K; ++k) cc[t][k] = (float)(a[k] / (h * h));
+        if (t > 0) cc[t][0] = (float)((m->h[0] * m->h[0]) / (h * h));
+        g.ix0[t] = m->nbl;
+        g.ix1[t] = m->nbl + m->n[ax] - 1;
+        if (m->nbl > 0) {
+            const double smax = 3.0 * m->vmax * std::log(1000.0) / (2.0 * m->nbl * h);
+            *dd[t] = (float)(0.5 * m->dt * smax / ((double)m->nbl * m->nbl));
+        } else {
+            *dd[t] = 0.0f;
+        }
+    }
+    return WV_OK;
+}
+
+// Multilinear weights of one position (metres from the first interior point).
+int point_weights(const wv_model *m, const Setup &su, const double *xyz, int *idx, float *wt)
+{
+    int i0[3] = {0, 0, 0};
+    double fr[3] = {0, 0, 0};
+    for (int d = 0; d < m->ndim; ++d) {
+        const double gpos = xyz[d] / m->h[d] + (double)m->nbl;
+        if (!(gpos >= 0.0) || gpos > (double)(su.N[d] - 1)) return WV_EINVAL;
+        int i = (int)std::floor(gpos);
+        if (i > su.N[d] - 2) i = su.N[d] - 2;
+        if (i < 0) i = 0;
+        i0[d] = i;
+        fr[d] = gpos - i;
+    }
+    const int nc = m->ndim == 3 ? 8 : 4;
+    for (int c = 0; c < nc; ++c) {
+        long long p = 0, stride = 1;
+        double w = 1.0;
+        for (int d = 0; d < m->ndim; ++d) {
+            const int bit = (c >> d) & 1;
+            const int ii = std::min(i0[d] + bit, su.N[d] - 1);
+            p += (long long)ii * stride;
+            stride *= su.N[d];
+            w *= bit ? fr[d] : 1.0 - fr[d];
+        }
+        idx[c] = (int)p;
+        wt[c] = (float)w;
+    }
+    return WV_OK;
+}
+
+// gather tables plus the transposed (scatter) table with unique points
+int build_sparse(const wv_model *m, const Setup &su, int npt, const double *xyz, bool shared_col,
+                 std::vector<int> &gidx, std::vector<float> &gwt, std::vector<int> &pts, std::vector<int> &start,
+                 std::vector<int> &col, std::vector<float> &swt)
+{
+    const int nc = m->ndim == 3 ? 8 : 4;
+    gidx.assign((size_t)npt * nc, 0);
+    gwt.assign((size_t)npt * nc, 0.0f);
+    for (int r = 0; r < npt; ++r) {
+        const int rc = point_weights(m, su, xyz + (size_t)r * m->ndim, &gidx[(size_t)r * nc], &gwt[(size_t)r * nc]);
+        if (rc) return rc;
+    }
+    // entries sorted by (point, column, corner) for a fixed summation order
+    struct E { int p, col, c; float w; };
+    std::vector<E> es;
+    es.reserve((size_t)npt * nc);
+    for (int r = 0; r < npt; ++r)
+        for (int c = 0; c < nc; ++c) es.push_back({gidx[(size_t)r * nc + c], shared_col ? 0 : r, c, gwt[(size_t)r * nc + c]});
+    std::sort(es.begin(), es.end(), [](const E &a, const E &b) {
+        if (a.p != b.p) return a.p < b.p;
+        if (a.col != b.col) return a.col < b.col;
+        return a.c < b.c;
+    });
+    pts.clear();
+    start.clear();
+    col.clear();
+    swt.clear();
+    for (size_t i = 0; i < es.size(); ++i) {
+        if (i == 0 || es[i].p != es[i - 1].p) {
+            pts.push_back(es[i].p);
+            start.push_back((int)col.size());
+        }
+        col.push_back(es[i].col);
+        swt.push_back(es[i].w);
+    }
+    start.push_back((int)col.size());
+    return WV_OK;
+}
+
+int prepare(const wv_model *m, const wv_geom *geo, Setup &su)
+{
+    // the launch wrappers report hipGetLastError(); drop any error a previous,
+    // unrelated runtime call of this thread left behind
+    (void)hipGetLastError();
+    int rc = validate_model(m, su);
+    if (rc) return rc;
+    if (!geo || geo->nsrc < 1 || geo->nrec < 1 || !geo->src_xyz || !geo->rec_xyz || !geo->wavelet)
+        return WV_EINVAL;
+    su.nc = m->ndim == 3 ? 8 : 4;
+    rc = build_sparse(m, su, geo->nsrc, geo->src_xyz, true, su.src_gidx, su.src_gwt, su.src_pts, su.src_start,
+                      su.src_col, su.src_swt);
+    if (rc) return rc;
+    return build_sparse(m, su, geo->nrec, geo->rec_xyz, false, su.rec_gidx, su.rec_gwt, su.rec_pts, su.rec_start,
+                        su.rec_col, su.rec_swt);
+}
+
+size_t tab_bytes(const Setup &su, bool rec)
+{
+    const size_t ng = rec ? su.rec_gidx.size() : su.src_gidx.size();
+    const size_t np = rec ? su.rec_pts.size() : su.src_pts.size();
+    const size_t ne = rec ? su.rec_col.size() : su.src_col.size();
+    return align_up(ng * 4, 256) * 2 + align_up(np * 4, 256) + align_up((np + 1) * 4, 256) +
+           align_up(ne * 4, 256) * 2;
+}
+
+Layout plan_layout(const wv_model *m, const wv_geom *geo, const Setup &su, int op, size_t budget)
+{
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const size_t fb = (size_t)su.P * 4;
+    L.bk = take(kBk);
+    L.U0 = take(fb);
+    L.U1 = take(fb);
+    L.D = take(fb);
+    L.W = take(fb);
+    L.src_tab = take(tab_bytes(su, false));
+    L.rec_tab = take(tab_bytes(su, true));
+    const size_t data_bytes = (size_t)(m->nt + 1) * geo->nrec * 4;
+    if (op == WV_OP_GRADIENT) {
+        L.L0 = take(fb);
+        L.L1 = take(fb);
+        L.MU = take(fb);
+        L.res = take(data_bytes);
+        L.dsim = take(data_bytes);
+        L.partials = take(kParts * 8);
+        const int dims[3] = {su.g.nx, su.g.ny, su.g.nz};
+        const int cdims[3] = {su.g.nx, su.ndim == 3 ? su.g.ny : su.g.nz, su.ndim == 3 ? su.g.nz : 1};
+        (void)dims;
+        const CodecDims cd = codec_dims(su.ndim, cdims);
+        L.nchunks_max = cd.nchunks;
+        L.flags = take((size_t)cd.nchunks * 8);
+        L.offs_n = 2 * (m->nt + 3);
+        L.offs = take((size_t)L.offs_n * 8);
+        L.arena_bytes = align_up(budget, 256);
+        L.arena = take(L.arena_bytes);
+    }
+    L.total = off;
+    return L;
+}
+
+struct Dev {
+    uint8_t *base;
+    Layout L;
+    Sparse src, rec;
+    float *U[2], *D, *Lm[2], *MU, *W;
+    unsigned *err, *ticket;
+    double *misfit;
+    unsigned long long *stats;
+    uint64_t *zero, *probe_next, *flags, *offs;
+    uint8_t *arena;
+    float *res, *dsim;
+    double *partials;
+};
+
+template <typename T>
+T *at(uint8_t *b, size_t o) { return reinterpret_cast<T *>(b + o); }
+
+int upload_tables(Dev &d, const Setup &su, hipStream_t s)
+{
+    // pack both tables into one host buffer, one copy
+    std::vector<uint8_t> host(d.L.src_tab < d.L.rec_tab ? (d.L.rec_tab - d.L.src_tab) + tab_bytes(su, true) : 0);
+    auto place = [&](size_t tab_off, bool rec, Sparse &sp) {
+        const std::vector<int> &gidx = rec ? su.rec_gidx : su.src_gidx;
+        const std::vector<float> &gwt = rec ? su.rec_gwt : su.src_gwt;
+        const std::vector<int> &pts = rec ? su.rec_pts : su.src_pts;
+        const std::vector<int> &start = rec ? su.rec_start : su.src_start;
+        const std::vector<int> &col = rec ? su.rec_col : su.src_col;
+        const std::vector<float> &swt = rec ? su.rec_swt : su.src_swt;
+        size_t o = tab_off - d.L.src_tab;
+        auto put = [&](const void *src, size_t bytes) {
+            std::memcpy(host.data() + o, src, bytes);
+            const size_t here = o;
+            o = align_up(o + bytes, 256);
+            return d.base + d.L.src_tab + here;
+        };
+        sp.n = (int)(gidx.size() / su.nc);
+        sp.nc = su.nc;
+        sp.g_idx = (const int *)put(gidx.data(), gidx.size() * 4);
+        sp.g_wt = (const float *)put(gwt.data(), gwt.size() * 4);
+        sp.npts = (int)pts.size();
+        sp.s_pts = (const int *)put(pts.data(), pts.size() * 4);
+        sp.s_start = (const int *)put(start.data(), start.size() * 4);
+        sp.s_col = (const int *)put(col.data(), col.size() * 4);
+        sp.s_wt = (const float *)put(swt.data(), swt.size() * 4);
+    };
+    place(d.L.src_tab, false, d.src);
+    place(d.L.rec_tab, true, d.rec);
+    HIPCHK(hipMemcpyAsync(d.base + d.L.src_tab, host.data(), host.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return WV_OK;
+}
+
+int bind(Dev &d, void *ws, size_t ws_bytes, const Layout &L, int op)
+{
+    if (!ws || ws_bytes < L.total) return WV_ENOMEM;
+    if (((uintptr_t)ws) & 255) return WV_EINVAL;
+    d.base = (uint8_t *)ws;
+    d.L = L;
+    d.U[0] = at<float>(d.base, L.U0);
+    d.U[1] = at<float>(d.base, L.U1);
+    d.D = at<float>(d.base, L.D);
+    d.W = at<float>(d.base, L.W);
+    d.err = at<unsigned>(d.base, L.bk + kErr);
+    d.ticket = at<unsigned>(d.base, L.bk + kTicket);
+    d.misfit = at<double>(d.base, L.bk + kMisfit);
+    d.stats = at<unsigned long long>(d.base, L.bk + kStats);
+    d.zero = at<uint64_t>(d.base, L.bk + kZero);
+    d.probe_next = at<uint64_t>(d.base, L.bk + kProbeNext);
+    if (op == WV_OP_GRADIENT) {
+        d.Lm[0] = at<float>(d.base, L.L0);
+        d.Lm[1] = at<float>(d.base, L.L1);
+        d.MU = at<float>(d.base, L.MU);
+        d.res = at<float>(d.base, L.res);
+        d.dsim = at<float>(d.base, L.dsim);
+        d.partials = at<double>(d.base, L.partials);
+        d.flags = at<uint64_t>(d.base, L.flags);
+        d.offs = at<uint64_t>(d.base, L.offs);
+        d.arena = at<uint8_t>(d.base, L.arena);
+    }
+    return WV_OK;
+}
+
+int read_err(Dev &d, hipStream_t s, unsigned *out)
+{
+    HIPCHK(hipMemcpyAsync(out, d.err, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return WV_OK;
+}
+
+// Common set-up: zero the bookkeeping block, compute w, validate the velocity.
+int start(Dev &d, const wv_model *m, const Setup &su, hipStream_t s)
+{
+    HIPCHK(launch_fill_u64(at<uint64_t>(d.base, d.L.bk), kBk / 8, 0, s));
+    int rc = upload_tables(d, su, s);
+    if (rc) return rc;
+    HIPCHK(launch_setup_w(m->vel, d.W, su.P, m->dt, m->vmax, d.err, s));
+    unsigned e = 0;
+    rc = read_err(d, s, &e);
+    if (rc) return rc;
+    return e ? WV_EINVAL : WV_OK;
+}
+
+struct Fwd {
+    Dev &d;
+    const Setup &su;
+    const wv_geom *geo;
+    int cur = 0;
+    hipStream_t s;
+    int step(int n, float *data_row)
+    {
+        HIPCHK(launch_fwd_step(su.g, d.U[cur], d.U[cur ^ 1], d.D, d.W, s));
+        HIPCHK(launch_inject_src(su.g, d.src, geo->wavelet, n, d.W, d.D, d.U[cur ^ 1], s));
+        cur ^= 1;
+        if (data_row) HIPCHK(launch_gather(d.rec, d.U[cur], data_row, s));
+        return WV_OK;
+    }
+};
+
+double gradient_scale(const wv_model *m) { return -1.0 / (m->dt * m->dt); }
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+const char *wv_strerror(int code)
+{
+    switch (code) {
+    case WV_OK: return "ok";
+    case WV_EINVAL: return "invalid argument";
+    case WV_ECFL: return "time step above the stability limit";
+    case WV_EBUDGET: return "memory budget below one checkpoint";
+    case WV_EARENA: return "compressed checkpoints overflowed the memory budget";
+    case WV_ENOMEM: return "workspace too small";
+    case WV_EHIP: return "HIP runtime error";
+    case WV_EUNSTABLE: return "non-finite wavefield";
+    case WV_ENOTIMPL: return "not implemented";
+    case WV_ECAP: return "output buffer too small";
+    default: return "unknown error";
+    }
+}
+
+const char *wv_version(void) { return "wv 0.1 gfx950"; }
+
+const char *wv_last_error(void) { return g_detail; }
+
+double wv_cfl_dt(int ndim, const double *h, int space_order, double vmax)
+{
+    if (!h) return -1.0;
+    return cfl_limit(ndim, h, space_order, vmax);
+}
+
+long wv_schedule_forward_steps(int nt, int M)
+{
+    if (nt < 0 || M < 1) return -1;
+    return (long)forward_steps(nt, M);
+}
+
+int wv_schedule(int nt, int M, int32_t *actions, size_t cap, size_t *n_actions)
+{
+    if (nt < 0 || M < 1 || !n_actions) return WV_EINVAL;
+    std::vector<int32_t> a;
+    make_schedule(nt, M, a);
+    *n_actions = a.size() / 3;
+    if (a.size() / 3 > cap) return WV_ECAP;
+    if (!a.empty()) std::memcpy(actions, a.data(), a.size() * 4);
+    return WV_OK;
+}
+
+size_t wv_workspace_bytes(const wv_model *m, const wv_geom *geo, int op, size_t mem_budget)
+{
+    Setup su;
+    if (prepare(m, geo, su)) return 0;
+    if (op != WV_OP_FORWARD && op != WV_OP_GRADIENT) return 0;
+    return plan_layout(m, geo, su, op, mem_budget).total;
+}
+
+int wv_forward(const wv_model *m, const wv_geom *geo, float *data, float *state_out, void *ws, size_t ws_bytes,
+               void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    Setup su;
+    int rc = prepare(m, geo, su);
+    if (rc) return rc;
+    if (!data) return WV_EINVAL;
+    const Layout L = plan_layout(m, geo, su, WV_OP_FORWARD, 0);
+    Dev d{};
+    if ((rc = bind(d, ws, ws_bytes, L, WV_OP_FORWARD))) return rc;
+    if ((rc = start(d, m, su, s))) return rc;
+    HIPCHK(launch_fill_f32(d.U[0], su.P, 0.0f, s));
+    HIPCHK(launch_fill_f32(d.D, su.P, 0.0f, s));
+    HIPCHK(launch_fill_f32(data, geo->nrec, 0.0f, s));
+    Fwd f{d, su, geo, 0, s};
+    for (int n = 0; n < m->nt; ++n)
+        if ((rc = f.step(n, data + (size_t)(n + 1) * geo->nrec))) return rc;
+    if (state_out) {
+        HIPCHK(hipMemcpyAsync(state_out, d.U[f.cur], (size_t)su.P * 4, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(state_out + su.P, d.U[f.cur ^ 1], (size_t)su.P * 4, hipMemcpyDeviceToDevice, s));
+    }
+    HIPCHK(launch_check_finite(d.U[f.cur], su.P, d.err, s));
+    unsigned e = 0;
+    if ((rc = read_err(d, s, &e))) return rc;
+    return (e & 8u) ? WV_EUNSTABLE : WV_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct GradRun {
+    const wv_model *m;
+    const wv_geom *geo;
+    const Setup &su;
+    Dev &d;
+    hipStream_t s;
+    double tol;
+    bool misfit_mode;       // compute d_sim and the residual in the first sweep
+    bool src_adj_mode;      // adjoint source only (no forward, no gradient)
+    const float *dobs = nullptr;
+    const float *residual = nullptr;   // given residual (gradient mode)
+    float *dsim_out = nullptr;
+    float *src_adj = nullptr;
+    double *G = nullptr;
+    CodecDims cd{};
+    size_t S = 0;                      // bytes of one uncompressed checkpoint
+    uint32_t epoch = 0;
+    long advances = 0, stores = 0, restores = 0, reverses = 0;
+    int max_depth = 0;
+
+    int encode_field(const float *f, uint64_t *base, uint64_t *next)
+    {
+        ++epoch;
+        HIPCHK(launch_encode(cd, f, tol, d.arena, d.L.arena_bytes, base, next, d.flags, d.ticket, epoch, d.err,
+                             d.stats, s));
+        return WV_OK;
+    }
+};
+
+// Per-action device timing: one event pair per schedule action, read after the final sync.
+struct ActionTimer {
+    bool on = false;
+    hipStream_t s = nullptr;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;
+    size_t used = 0;
+    ~ActionTimer()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    int begin(int k)
+    {
+        if (!on) return WV_OK;
+        if (used + 2 > ev.size()) {
+            for (int i = 0; i < 2; ++i) {
+                hipEvent_t e;
+                HIPCHK(hipEventCreate(&e));
+                ev.push_back(e);
+            }
+        }
+        kind.push_back(k);
+        HIPCHK(hipEventRecord(ev[used], s));
+        return WV_OK;
+    }
+    int end()
+    {
+        if (!on) return WV_OK;
+        HIPCHK(hipEventRecord(ev[used + 1], s));
+        used += 2;
+        return WV_OK;
+    }
+    // after a sync: accumulate per-kind milliseconds (kinds 1..5 = action codes)
+    int totals(double *ms)
+    {
+        for (size_t i = 0; i < used / 2; ++i) {
+            float t = 0.0f;
+            HIPCHK(hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]));
+            ms[kind[i]] += t;
+        }
+        return WV_OK;
+    }
+};
+
+int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, double *misfit_out)
+{
+    const wv_model *m = R.m;
+    Dev &d = R.d;
+    hipStream_t s = R.s;
+    const int N = m->nt;
+    const long long P = R.su.P;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, s));
+
+    float *data = R.misfit_mode ? (R.dsim_out ? R.dsim_out : d.dsim) : nullptr;
+    const float *res = R.misfit_mode ? d.res : R.residual;
+    Fwd f{d, R.su, R.geo, 0, s};
+    HIPCHK(launch_fill_f32(d.U[0], P, 0.0f, s));
+    HIPCHK(launch_fill_f32(d.D, P, 0.0f, s));
+    HIPCHK(launch_fill_f32(d.Lm[0], P, 0.0f, s));
+    HIPCHK(launch_fill_f32(d.MU, P, 0.0f, s));
+    if (R.G) HIPCHK(launch_fill_f64(R.G, P, 0.0, s));
+    HIPCHK(launch_fill_u64(d.offs, d.L.offs_n, 0, s));
+    HIPCHK(launch_fill_u64(d.flags, d.L.nchunks_max, 0, s));
+    if (data) HIPCHK(launch_fill_f32(data, R.geo->nrec, 0.0f, s));
+    int gathered = 0;
+    bool residual_ready = !R.misfit_mode;
+    int lc = 0;
+    const double gscale = gradient_scale(m);
+    std::vector<int32_t> acts;
+    if (R.src_adj_mode) {
+        for (int k = N; k >= 1; --k) acts.insert(acts.end(), {REVERSE, k, 0});
+    } else {
+        make_schedule(N, M, acts);
+    }
+    int rc = WV_OK;
+    const bool comp = R.tol > 0;
+    const size_t fb = (size_t)P * 4;
+    ActionTimer timer;
+    timer.on = stats && stats->timing;
+    timer.s = s;
+    for (size_t i = 0; i < acts.size() / 3 && rc == WV_OK; ++i) {
+        const int op = acts[3 * i], a = acts[3 * i + 1], b = acts[3 * i + 2];
+        if (op != FREE && (rc = timer.begin(op))) break;
+        switch (op) {
+        case ADVANCE:
+            for (int n = a; n < b; ++n) {
+                float *row = (data && n + 1 > gathered) ? data + (size_t)(n + 1) * R.geo->nrec : nullptr;
+                if ((rc = f.step(n, row))) break;
+                if (row) gathered = n + 1;
+            }
+            R.advances += b - a;
+            break;
+        case STORE:
+            if (comp) {
+                if ((rc = R.encode_field(d.U[f.cur], d.offs + 2 * b, d.offs + 2 * b + 1))) break;
+                if ((rc = R.encode_field(d.D, d.offs + 2 * b + 1, d.offs + 2 * b + 2))) break;
+            } else {
+                uint8_t *slot = d.arena + (size_t)(b - 1) * R.S;
+                HIPCHK(hipMemcpyAsync(slot, d.U[f.cur], fb, hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(slot + fb, d.D, fb, hipMemcpyDeviceToDevice, s));
+            }
+            R.stores++;
+            R.max_depth = std::max(R.max_depth, b);
+            break;
+        case RESTORE:
+            if (b == 0) {
+                HIPCHK(launch_fill_f32(d.U[f.cur], P, 0.0f, s));
+                HIPCHK(launch_fill_f32(d.D, P, 0.0f, s));
+            } else if (comp) {
+                HIPCHK(launch_decode(R.cd, d.arena, d.offs + 2 * b, d.L.arena_bytes, d.U[f.cur], s));
+                HIPCHK(launch_decode(R.cd, d.arena, d.offs + 2 * b + 1, d.L.arena_bytes, d.D, s));
+            } else {
+                const uint8_t *slot = d.arena + (size_t)(b - 1) * R.S;
+                HIPCHK(hipMemcpyAsync(d.U[f.cur], slot, fb, hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(d.D, slot + fb, fb, hipMemcpyDeviceToDevice, s));
+            }
+            R.restores++;
+            break;
+        case FREE:
+            break;
+        case REVERSE: {
+            if (!residual_ready) {
+                HIPCHK(launch_check_finite(d.U[f.cur], P, d.err, s));
+                HIPCHK(launch_residual_misfit(data, R.dobs, d.res, (long long)(N + 1) * R.geo->nrec, R.geo->nrec,
+                                              d.partials, kParts, d.misfit, s));
+                residual_ready = true;
+            }
+            const float *uk = R.G ? d.U[f.cur] : nullptr;
+            HIPCHK(launch_adj_step(R.su.g, d.Lm[lc], d.Lm[lc ^ 1], d.MU, d.W, uk, R.G, gscale, s));
+            HIPCHK(launch_inject_res(R.su.g, d.rec, res + (size_t)a * R.geo->nrec, d.W, d.MU, d.Lm[lc ^ 1], uk, R.G,
+                                     gscale, s));
+            lc ^= 1;
+            if (R.src_adj) HIPCHK(launch_gather_sum(d.src, d.Lm[lc], R.src_adj + (a - 1), s));
+            R.reverses++;
+            break;
+        }
+        default:
+            rc = WV_EINVAL;
+        }
+        if (rc == WV_OK && op != FREE) rc = timer.end();
+    }
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(e1, s));
+    unsigned e = 0;
+    unsigned long long st[2] = {0, 0};
+    double mis = 0.0;
+    HIPCHK(hipMemcpyAsync(st, d.stats, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&mis, d.misfit, sizeof(double), hipMemcpyDeviceToHost, s));
+    if ((rc = read_err(d, s, &e))) return rc;
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (misfit_out) *misfit_out = mis;
+    double kind_ms[6] = {0, 0, 0, 0, 0, 0};
+    if (timer.on && (rc = timer.totals(kind_ms))) return rc;
+    if (stats) {
+        const int timing = stats->timing;
+        std::memset(stats, 0, sizeof(*stats));
+        stats->timing = timing;
+        stats->ms_forward = kind_ms[ADVANCE];
+        stats->ms_adjoint = kind_ms[REVERSE];
+        stats->ms_store = kind_ms[STORE];
+        stats->ms_restore = kind_ms[RESTORE];
+        stats->advances = R.advances;
+        stats->stores = R.stores;
+        stats->restores = R.restores;
+        stats->reverses = R.reverses;
+        stats->slots = M;
+        stats->bytes_stored = comp ? (double)st[0] : (double)R.stores * (double)R.S;
+        stats->peak_bytes = comp ? (double)st[1] : (double)R.max_depth * (double)R.S;
+        stats->ratio = stats->bytes_stored > 0 ? (double)R.stores * (double)R.S / stats->bytes_stored : 1.0;
+        stats->ratio_planned = ratio_planned;
+        stats->misfit = mis;
+        stats->ms_total = ms;
+    }
+    if (e & 4u) return WV_EARENA;
+    if (e & 16u) return WV_EHIP;
+    if (e & (2u | 8u)) return WV_EUNSTABLE;
+    return WV_OK;
+}
+
+// Compression ratio of the final state of a plain forward run (the paper's
+// worst-case proxy): encode (u^N, d^N) at the start of the arena.
+int probe_ratio(GradRun &R, double *ratio)
+{
+    Dev &d = R.d;
+    hipStream_t s = R.s;
+    const long long P = R.su.P;
+    float *data = R.misfit_mode ? (R.dsim_out ? R.dsim_out : d.dsim) : nullptr;
+    Fwd f{d, R.su, R.geo, 0, s};
+    HIPCHK(launch_fill_f32(d.U[0], P, 0.0f, s));
+    HIPCHK(launch_fill_f32(d.D, P, 0.0f, s));
+    HIPCHK(launch_fill_u64(d.offs, d.L.offs_n, 0, s));
+    HIPCHK(launch_fill_u64(d.flags, d.L.nchunks_max, 0, s));
+    HIPCHK(launch_fill_u64(at<uint64_t>(d.base, d.L.bk + kStats), 2, 0, s));
+    for (int n = 0; n < R.m->nt; ++n) {
+        int rc = f.step(n, nullptr);
+        if (rc) return rc;
+    }
+    int rc;
+    if ((rc = R.encode_field(d.U[f.cur], d.offs + 2, d.offs + 3))) return rc;
+    if ((rc = R.encode_field(d.D, d.offs + 3, d.offs + 4))) return rc;
+    unsigned long long st[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(st, d.stats, sizeof(st), hipMemcpyDeviceToHost, s));
+    unsigned e = 0;
+    if ((rc = read_err(d, s, &e))) return rc;
+    (void)data;
+    if (e & 4u) {   // did not fit the whole arena: ratio below budget / S
+        *ratio = 1.0;
+        return WV_OK;
+    }
+    if (e) return WV_EUNSTABLE;
+    *ratio = st[0] > 0 ? (double)R.S / (double)st[0] : 1.0;
+    HIPCHK(launch_fill_u64(at<uint64_t>(d.base, d.L.bk), kBk / 8, 0, s));
+    return WV_OK;
+}
+
+int gradient_common(const wv_model *m, const wv_geom *geo, const float *residual, const float *dobs,
+                    size_t mem_budget, double tol, double ratio_hint, double *misfit, double *grad_m, float *d_sim,
+                    wv_stats *stats, void *ws, size_t ws_bytes, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    Setup su;
+    int rc = prepare(m, geo, su);
+    if (rc) return rc;
+    if (!grad_m || !(tol >= 0) || !std::isfinite(tol)) return WV_EINVAL;
+    const Layout L = plan_layout(m, geo, su, WV_OP_GRADIENT, mem_budget);
+    Dev d{};
+    if ((rc = bind(d, ws, ws_bytes, L, WV_OP_GRADIENT))) return rc;
+    if ((rc = start(d, m, su, s))) return rc;
+    GradRun R{m, geo, su, d, s, tol, dobs != nullptr, false};
+    R.dobs = dobs;
+    R.residual = residual;
+    R.dsim_out = d_sim;
+    R.G = grad_m;
+    const int cdims[3] = {su.g.nx, su.ndim == 3 ? su.g.ny : su.g.nz, su.ndim == 3 ? su.g.nz : 1};
+    R.cd = codec_dims(su.ndim, cdims);
+    R.S = (size_t)su.P * 8;
+    double F = 1.0;
+    if (tol > 0) {
+        if (ratio_hint > 0) F = ratio_hint;
+        else if ((rc = probe_ratio(R, &F))) return rc;
+    }
+    const int N = m->nt;
+    size_t slot_bytes = tol > 0 ? (size_t)((double)R.S / F) + 2 * (size_t)(R.cd.prefix_bytes + 256) : R.S;
+    if (slot_bytes < 1) slot_bytes = 1;
+    const size_t nslots = mem_budget / slot_bytes;
+    if (nslots < 1 && N > 1) return WV_EBUDGET;
+    const int M = (int)std::min<size_t>((size_t)N, nslots + 1);
+    return run_gradient(R, std::max(M, 1), F, stats, misfit);
+}
+
+}  // namespace
+
+extern "C" {
+
+int wv_gradient(const wv_model *m, const wv_geom *geo, const float *residual, size_t mem_budget, double tol,
+                double ratio_hint, double *grad_m, wv_stats *stats, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!residual) return WV_EINVAL;
+    return gradient_common(m, geo, residual, nullptr, mem_budget, tol, ratio_hint, nullptr, grad_m, nullptr, stats,
+                           ws, ws_bytes, stream);
+}
+
+int wv_misfit_gradient(const wv_model *m, const wv_geom *geo, const float *d_obs, size_t mem_budget, double tol,
+                       double ratio_hint, double *misfit, double *grad_m, float *d_sim, wv_stats *stats, void *ws,
+                       size_t ws_bytes, void *stream)
+{
+    if (!d_obs || !misfit) return WV_EINVAL;
+    return gradient_common(m, geo, nullptr, d_obs, mem_budget, tol, ratio_hint, misfit, grad_m, d_sim, stats, ws,
+                           ws_bytes, stream);
+}
+
+int wv_adjoint_src(const wv_model *m, const wv_geom *geo, const float *residual, float *src_adj, void *ws,
+                   size_t ws_bytes, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    Setup su;
+    int rc = prepare(m, geo, su);
+    if (rc) return rc;
+    if (!residual || !src_adj) return WV_EINVAL;
+    const Layout L = plan_layout(m, geo, su, WV_OP_GRADIENT, 0);
+    Dev d{};
+    if ((rc = bind(d, ws, ws_bytes, L, WV_OP_GRADIENT))) return rc;
+    if ((rc = start(d, m, su, s))) return rc;
+    GradRun R{m, geo, su, d, s, 0.0, false, true};
+    R.residual = residual;
+    R.src_adj = src_adj;
+    R.S = (size_t)su.P * 8;
+    return run_gradient(R, 1, 1.0, nullptr, nullptr);
+}
+
+int wv_pad_velocity(int ndim, const int *n, int nbl, const float *vin, float *vout, void *stream)
+{
+    if ((ndim != 2 && ndim != 3) || !n || nbl < 0 || !vin || !vout) return WV_EINVAL;
+    (void)hipGetLastError();
+    for (int a = 0; a < ndim; ++a)
+        if (n[a] < 1) return WV_EINVAL;
+    HIPCHK(launch_pad_velocity(ndim, n, nbl, vin, vout, (hipStream_t)stream));
+    return WV_OK;
+}
+
+int wv_velocity_gradient(int ndim, const int *n, int nbl, const float *vpad, const double *gm, double *gv,
+                         void *stream)
+{
+    if ((ndim != 2 && ndim != 3) || !n || nbl < 0 || !vpad || !gm || !gv) return WV_EINVAL;
+    (void)hipGetLastError();
+    for (int a = 0; a < ndim; ++a)
+        if (n[a] < 1) return WV_EINVAL;
+    HIPCHK(launch_velocity_gradient(ndim, n, nbl, vpad, gm, gv, (hipStream_t)stream));
+    return WV_OK;
+}
+
+// ------------------------------------------------------------------ codec entry points
+namespace {
+constexpr size_t kCodecBk = 512;   // err, ticket, base word, next word, stats[2]
+}
+
+size_t wv_zfpk_workspace_bytes(int ndim, const int *dims)
+{
+    if ((ndim != 2 && ndim != 3) || !dims) return 0;
+    const CodecDims cd = codec_dims(ndim, dims);
+    return kCodecBk + align_up((size_t)cd.nchunks * 8, 256);
+}
+
+size_t wv_zfpk_max_bytes(int ndim, const int *dims)
+{
+    if ((ndim != 2 && ndim != 3) || !dims) return 0;
+    return codec_max_bytes(codec_dims(ndim, dims));
+}
+
+int wv_zfpk_encode(const float *field, int ndim, const int *dims, double tol, void *out, size_t cap,
+                   size_t *nbytes, void *ws, size_t ws_bytes, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if ((ndim != 2 && ndim != 3) || !dims || !field || !out || !nbytes || !(tol > 0) || !std::isfinite(tol))
+        return WV_EINVAL;
+    for (int a = 0; a < ndim; ++a)
+        if (dims[a] < 1) return WV_EINVAL;
+    if (((uintptr_t)out) & 7) return WV_EINVAL;
+    const CodecDims cd = codec_dims(ndim, dims);
+    (void)hipGetLastError();
+    if (!ws || ws_bytes < wv_zfpk_workspace_bytes(ndim, dims) || (((uintptr_t)ws) & 255)) return WV_ENOMEM;
+    uint8_t *b = (uint8_t *)ws;
+    unsigned *err = (unsigned *)b;
+    unsigned *ticket = (unsigned *)(b + 64);
+    uint64_t *base = (uint64_t *)(b + 128);
+    uint64_t *next = (uint64_t *)(b + 136);
+    unsigned long long *st = (unsigned long long *)(b + 192);
+    uint64_t *flags = (uint64_t *)(b + kCodecBk);
+    HIPCHK(launch_fill_u64((uint64_t *)b, kCodecBk / 8, 0, s));
+    HIPCHK(launch_fill_u64(flags, cd.nchunks, 0, s));
+    HIPCHK(launch_encode(cd, field, tol, (uint8_t *)out, cap, base, next, flags, ticket, 1u, err, st, s));
+    unsigned e = 0;
+    unsigned long long tot[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(tot, st, 16, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *nbytes = (size_t)tot[0];
+    if (e & 4u) return WV_ECAP;
+    if (e & 2u) return WV_EINVAL;
+    if (e & 16u) return WV_EHIP;
+    return WV_OK;
+}
+
+int wv_zfpk_decode(const void *in, int ndim, const int *dims, float *field, void *stream)
+{
+    if ((ndim != 2 && ndim != 3) || !dims || !in || !field) return WV_EINVAL;
+    for (int a = 0; a < ndim; ++a)
+        if (dims[a] < 1) return WV_EINVAL;
+    const CodecDims cd = codec_dims(ndim, dims);
+    (void)hipGetLastError();
+    HIPCHK(launch_decode(cd, (const uint8_t *)in, nullptr, ~0ull, field, (hipStream_t)stream));
+    return WV_OK;
+}
+
+}  // extern "C"

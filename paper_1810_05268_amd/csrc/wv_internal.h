@@ -1,0 +1,97 @@
+// Internal declarations of libwv (GPU path).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/wv.h"
+
+namespace wv {
+
+constexpr int kMaxK = 8;            // space order up to 16
+constexpr int kBlocksPerChunk = 256; // codec: blocks per chunk (one workgroup)
+
+// Geometry and coefficients of one padded grid, as the stencil kernels see it.
+// Axes are named for the array layout: x contiguous, z slowest.  In 2-D, y is
+// absent (ny = 1) and the model's second axis is z.
+struct Grid {
+    int nx, ny, nz;          // padded extents
+    int ix0[3], ix1[3];      // interior index range [ix0, ix1] per array axis (x, y, z)
+    float cx[kMaxK + 1];     // a_k / h^2 per axis, k = 1..K;
+    float cy[kMaxK + 1];     // cy[0] = h_x^2/h_y^2 and cz[0] = h_x^2/h_z^2 (the 3-D kernel
+    float cz[kMaxK + 1];     // applies cx[k] on every axis and scales y, z by these)
+    float dampx, dampy, dampz; // 0.5 dt smax_axis / nbl^2; a = sum damp_axis * delta_axis^2
+    int K;
+    int ndim;
+    long long P;
+};
+
+// Sparse point operators (sources / receivers), built on the host.
+//   gather:  out[r] = sum_c wt[r*nc + c] * f[idx[r*nc + c]]
+//   scatter: unique points pts[i], entries [start[i], start[i+1]) of (col, wt)
+struct Sparse {
+    int n;            // number of sources or receivers
+    int nc;           // corners per point (4 or 8)
+    const int *g_idx; const float *g_wt;          // gather tables [n*nc]
+    int npts;         // unique grid points touched
+    const int *s_pts; const int *s_start;        // [npts], [npts+1]
+    const int *s_col; const float *s_wt;         // [nnz]
+};
+
+// ---------------------------------------------------------------- stencil launches (wv_stencil.hip)
+// Forward step in increment form: d <- ((1-a) d + w lap u)/(1+a), u_out = u_in + d.
+hipError_t launch_fwd_step(const Grid &g, const float *u_in, float *u_out, float *d, const float *w,
+                           hipStream_t s);
+// Adjoint step: mu <- ((1-a) mu + w lap lam)/(1+a), lam_out = lam_in + mu,
+// and (if G) G += gscale * uk * (w lap lam).
+hipError_t launch_adj_step(const Grid &g, const float *lam_in, float *lam_out, float *mu, const float *w,
+                           const float *uk, double *G, double gscale, hipStream_t s);
+// Source injection of sample q[n] (forward) at the unique source points.
+hipError_t launch_inject_src(const Grid &g, const Sparse &sp, const float *q, int n, const float *w,
+                             float *d, float *u_out, hipStream_t s);
+// Residual injection of row r_row (adjoint) at the unique receiver points; gradient term.
+hipError_t launch_inject_res(const Grid &g, const Sparse &sp, const float *r_row, const float *w, float *mu,
+                             float *lam_out, const float *uk, double *G, double gscale, hipStream_t s);
+// Receiver gather out[r] = (R f)_r.
+hipError_t launch_gather(const Sparse &sp, const float *f, float *out, hipStream_t s);
+// Sum over sources of the gathered field: out[0] = sum_s (S f)_s.
+hipError_t launch_gather_sum(const Sparse &sp, const float *f, float *out, hipStream_t s);
+// w = dt^2 vel^2 and validation; err bit 1: non-finite or out of (0, vmax].
+hipError_t launch_setup_w(const float *vel, float *w, long long P, double dt, double vmax, unsigned *err,
+                          hipStream_t s);
+hipError_t launch_fill_f32(float *p, long long n, float v, hipStream_t s);
+hipError_t launch_fill_f64(double *p, long long n, double v, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, long long n, uint64_t v, hipStream_t s);
+// r = (float)((double)dsim - (double)dobs) for rows 1..nt (row 0 = 0); partial sums of r^2 (binary64).
+hipError_t launch_residual_misfit(const float *dsim, const float *dobs, float *res, long long nrow_elems,
+                                  long long nrec, double *partials, int nparts, double *misfit, hipStream_t s);
+hipError_t launch_pad_velocity(int ndim, const int *n, int nbl, const float *vin, float *vout, hipStream_t s);
+hipError_t launch_velocity_gradient(int ndim, const int *n, int nbl, const float *vpad, const double *gm,
+                                    double *gv, hipStream_t s);
+hipError_t launch_check_finite(const float *f, long long n, unsigned *err, hipStream_t s);
+
+// ---------------------------------------------------------------- codec (wv_codec.hip)
+struct CodecDims {
+    int ndim;
+    int dims[3];       // axis 0 fastest; 2-D: dims[2] = 1
+    int nb[3];         // blocks per axis
+    long long nblocks;
+    long long nchunks;
+    long long prefix_bytes;  // header + chunk table + block lengths
+};
+CodecDims codec_dims(int ndim, const int *dims);
+size_t codec_max_bytes(const CodecDims &cd);
+// Encode field into out + *base (device offset), capacity cap bytes from `out`.
+// Writes *next = *base + stream bytes rounded up to 256.  flags: nchunks status words.
+// err: bit 2 = capacity overflow, bit 1 = non-finite input, bit 4 = look-back timeout.
+// stats[0] += stream bytes, stats[1] = max(stats[1], *next).
+hipError_t launch_encode(const CodecDims &cd, const float *field, double tol, uint8_t *out, uint64_t cap,
+                         const uint64_t *base, uint64_t *next, uint64_t *flags, unsigned *ticket, uint32_t epoch,
+                         unsigned *err, unsigned long long *stats, hipStream_t s);
+// Decode the stream at in + *base (base == nullptr: offset 0) into field; cap bytes
+// are readable from `in` (a stream that does not fit decodes to zeros).
+hipError_t launch_decode(const CodecDims &cd, const uint8_t *in, const uint64_t *base, uint64_t cap, float *field,
+                         hipStream_t s);
+
+}  // namespace wv

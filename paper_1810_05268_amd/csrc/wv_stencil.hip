@@ -1,0 +1,696 @@
+// Stencil kernels of the forward and adjoint acoustic solver (gfx950, wave64).
+//
+// The discrete problem is eq. (7) of the paper with the OT2 (second order in time)
+// leapfrog, written in increment form so that binary32 keeps the per-step change
+// at full relative precision:
+//   d^{n+1} = [(1-a) d^n + w (lap u^n + s^n)] / (1+a),   u^{n+1} = u^n + d^{n+1},
+// d^n = u^n - u^{n-1}, w = dt^2 c^2.  This is algebraically the three-level update
+// u^{n+1} = [2u^n - (1-a)u^{n-1} + w(lap u^n + s^n)]/(1+a).  The adjoint of the
+// three-level recursion has the same form run backward in time (lam, mu = lam^k -
+// lam^{k+1}) with the residual injected at the receivers; the gradient of the
+// misfit with respect to m accumulates -(1/dt^2) u^k w (lap lam^k + R^T r^k), which
+// equals -(1/dt^2) u^k [(1+a)lam^{k-1} - 2lam^k + (1-a)lam^{k+1}].
+//
+// The Laplacian is summed as sum_k c_k ((u_{+k} - u) + (u_{-k} - u)): for smooth
+// fields the differences are small and nearly exact, which keeps the binary32
+// rounding of the stencil far below the 1e-5 wavefield tolerance over thousands of
+// steps (a direct sum of the large weighted terms loses about two digits).
+//
+// Workgroup ids are remapped so that every XCD (each has its own L2) receives a
+// contiguous run of neighbouring tiles, whose halos then hit the same L2.
+#include "wv_internal.h"
+
+namespace wv {
+
+namespace {
+
+constexpr int kNumXcd = 8;
+
+__device__ __forceinline__ int xcd_remap(int bid, int nwg)
+{
+    // hardware dispatches workgroup i to XCD i % 8; give XCD j a contiguous range
+    int xcd = bid % kNumXcd, loc = bid / kNumXcd;
+    int q = nwg / kNumXcd, r = nwg % kNumXcd;
+    return xcd * q + (xcd < r ? xcd : r) + loc;
+}
+
+__device__ __forceinline__ int layer_depth(int i, int lo, int hi)
+{
+    int a = lo - i, b = i - hi;
+    return a > 0 ? a : (b > 0 ? b : 0);
+}
+
+__device__ __forceinline__ float damping(const Grid &g, int x, int y, int z)
+{
+    int dx = layer_depth(x, g.ix0[0], g.ix1[0]);
+    int dy = layer_depth(y, g.ix0[1], g.ix1[1]);
+    int dz = layer_depth(z, g.ix0[2], g.ix1[2]);
+    return g.dampx * (float)(dx * dx) + g.dampy * (float)(dy * dy) + g.dampz * (float)(dz * dz);
+}
+
+// d_new = ((1-a) d + wl) / (1+a)
+__device__ __forceinline__ float damped_increment(float a, float d, float wl)
+{
+    if (a == 0.0f) return d + wl;
+    return ((1.0f - a) * d + wl) / (1.0f + a);
+}
+
+// 3-D step.  A workgroup owns a 32 x 32 tile of the x-y plane and marches down z
+// over a chunk of planes; each lane owns four consecutive x points of one row.
+//   * z neighbours: a register queue of 2K+1 planes per point, shifted once per plane;
+//   * x, y neighbours: the centre plane staged in LDS with its halos (x halo padded to
+//     a multiple of four columns so that every LDS access is an aligned float4),
+//     double buffered, one barrier per plane;
+//   * software pipeline: while plane z is computed, every global load plane z+1
+//     needs (its point operands, the halo of the plane after it, the next queue
+//     front) is already in flight in a second register stage;
+//   * interior LDS values come from the queue, so HBM is read once per value
+//     (plus the 2K-plane warm-up of each z chunk); halos come from L2.
+// VEC: nx % 4 == 0, every float4 of a row is either inside or outside the grid.
+template <int K, bool GRAD, bool VEC>
+__global__ __launch_bounds__(256) void stencil3d(const Grid g, const float *__restrict__ fin,
+                                                 float *__restrict__ fout, float *__restrict__ inc,
+                                                 const float *__restrict__ w, const float *__restrict__ uk,
+                                                 double *__restrict__ G, double gscale, int tiles_x, int tiles_y,
+                                                 int zchunks, int zlen)
+{
+    constexpr int TX = 32, TY = 32;
+    constexpr int HX = (K + 3) / 4 * 4;          // x halo columns (>= K, multiple of 4)
+    constexpr int LX = TX + 2 * HX, LY = TY + 2 * K;
+    constexpr int NXV = 1 + 2 * ((K + 3) / 4);   // float4 reads for the x neighbours
+    constexpr int XC = 4 * ((K + 3) / 4);        // index of the lane's first point in them
+    constexpr int NHX = 2 * TY * (HX / 4);        // x-halo float4s per plane
+    constexpr int NH = NHX + 2 * K * (TX / 4);    // all halo float4s per plane (<= 256)
+    static_assert(NH <= 256, "one halo float4 per lane at most");
+    __shared__ __align__(16) float tile[2][LY][LX];
+
+    const int nwg = tiles_x * tiles_y * zchunks;
+    const int lid = xcd_remap(blockIdx.x, nwg);
+    const int tix = lid % tiles_x;
+    const int tiy = (lid / tiles_x) % tiles_y;
+    const int zc = lid / (tiles_x * tiles_y);
+    const int z0 = zc * zlen;
+    const int z1 = min(z0 + zlen, g.nz);
+
+    const int tid = threadIdx.x;
+    const int tx4 = tid & 7, ty = tid >> 3;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const long long sxy = (long long)nx * ny;
+    const int x0 = tix * TX + 4 * tx4;
+    const int y = tiy * TY + ty;
+    const bool rowin = y < ny;
+    const bool ptin = rowin && x0 < nx;
+    const long long rowoff = (long long)(rowin ? y : 0) * nx;
+
+    // halo float4 of this lane: source in the plane and place in the tile
+    int hrow = 0, hcol = 0, hgx = -1, hgy = -1;
+    if (tid < NHX) {
+        const int side = tid / (TY * (HX / 4));
+        const int rem = tid - side * (TY * (HX / 4));
+        const int r = rem / (HX / 4), c4 = rem - (rem / (HX / 4)) * (HX / 4);
+        hrow = r + K;
+        hcol = side ? (TX + HX + 4 * c4) : (4 * c4);
+        hgx = tix * TX - HX + hcol;
+        hgy = tiy * TY + r;
+    } else if (tid < NH) {
+        const int e = tid - NHX;
+        const int side = e / (K * (TX / 4));
+        const int rem = e - side * (K * (TX / 4));
+        const int r = rem / (TX / 4), c4 = rem - (rem / (TX / 4)) * (TX / 4);
+        hrow = side ? (TY + K + r) : r;
+        hcol = HX + 4 * c4;
+        hgx = tix * TX + 4 * c4;
+        hgy = tiy * TY - K + hrow;
+    }
+    const bool hact = tid < NH && hgy >= 0 && hgy < ny;
+    const long long hrowoff = (long long)(hact ? hgy : 0) * nx;
+
+    auto load4 = [&](const float *base, long long off, int gx, bool ok) -> float4 {
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (!ok) return v;
+        if constexpr (VEC) {
+            if (gx >= 0 && gx < nx) v = *reinterpret_cast<const float4 *>(base + off + gx);
+        } else {
+            if (gx + 0 >= 0 && gx + 0 < nx) v.x = base[off + gx + 0];
+            if (gx + 1 >= 0 && gx + 1 < nx) v.y = base[off + gx + 1];
+            if (gx + 2 >= 0 && gx + 2 < nx) v.z = base[off + gx + 2];
+            if (gx + 3 >= 0 && gx + 3 < nx) v.w = base[off + gx + 3];
+        }
+        return v;
+    };
+
+    struct Stage {
+        float4 d, w, u, h, f;
+    };
+    // loads that computing plane z needs: its point operands, the halo of plane z+1
+    // and the queue front of plane z+1+K
+    auto fill = [&](Stage &S, int z) {
+        const bool pin = ptin && z < z1;
+        const long long off = (long long)z * sxy + rowoff;
+        S.d = load4(inc, off, x0, pin);
+        S.w = load4(w, off, x0, pin);
+        if constexpr (GRAD) S.u = load4(uk, off, x0, pin);
+        const bool more = z + 1 < z1;
+        S.h = load4(fin, (long long)(z + 1) * sxy + hrowoff, hgx, hact && more);
+        const int zf = z + 1 + K;
+        S.f = load4(fin, (long long)zf * sxy + rowoff, x0, more && rowin && zf < nz);
+    };
+
+    // register queue: q[i][j] = u(x0+i, y, z-K+j)
+    float q[4][2 * K + 1];
+#pragma unroll
+    for (int j = 0; j < 2 * K + 1; ++j) {
+        const int z = z0 - K + j;
+        const float4 v = load4(fin, (long long)z * sxy + rowoff, x0, rowin && z >= 0 && z < nz);
+        q[0][j] = v.x; q[1][j] = v.y; q[2][j] = v.z; q[3][j] = v.w;
+    }
+    Stage A, B;
+    fill(A, z0);
+    {
+        const float4 hv = load4(fin, (long long)z0 * sxy + hrowoff, hgx, hact);
+        *reinterpret_cast<float4 *>(&tile[0][ty + K][HX + 4 * tx4]) = make_float4(q[0][K], q[1][K], q[2][K], q[3][K]);
+        if (tid < NH) *reinterpret_cast<float4 *>(&tile[0][hrow][hcol]) = hv;
+    }
+    __syncthreads();
+
+    const float c1 = g.cy[0], c2 = g.cz[0];   // h_x^2/h_y^2, h_x^2/h_z^2
+    auto step = [&](int z, Stage &S, Stage &N) {
+        // the binary64 gradient is read in the iteration that updates it (registers)
+        double gold[4] = {0.0, 0.0, 0.0, 0.0};
+        if constexpr (GRAD) {
+            const long long pg = (long long)z * sxy + rowoff + x0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (ptin && (VEC || x0 + i < nx)) gold[i] = G[pg + i];
+        }
+        fill(N, z + 1);
+        const int cur = (z - z0) & 1;
+        // x neighbours: NXV aligned float4 around the lane's four points
+        float xr[4 * NXV];
+        const float *trow = &tile[cur][ty + K][0];
+#pragma unroll
+        for (int v = 0; v < NXV; ++v) {
+            const float4 t = *reinterpret_cast<const float4 *>(trow + HX + 4 * tx4 - XC + 4 * v);
+            xr[4 * v + 0] = t.x; xr[4 * v + 1] = t.y; xr[4 * v + 2] = t.z; xr[4 * v + 3] = t.w;
+        }
+        float lap[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float c = q[i][K];
+            float sx = 0.0f, sz = 0.0f;
+#pragma unroll
+            for (int k = 1; k <= K; ++k) {
+                sx = fmaf(g.cx[k], (xr[XC + i + k] - c) + (xr[XC + i - k] - c), sx);
+                sz = fmaf(g.cx[k], (q[i][K + k] - c) + (q[i][K - k] - c), sz);
+            }
+            lap[i] = fmaf(c2, sz, sx);
+        }
+        float sy[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 1; k <= K; ++k) {
+            const float4 a = *reinterpret_cast<const float4 *>(&tile[cur][ty + K + k][HX + 4 * tx4]);
+            const float4 b = *reinterpret_cast<const float4 *>(&tile[cur][ty + K - k][HX + 4 * tx4]);
+            sy[0] = fmaf(g.cx[k], (a.x - q[0][K]) + (b.x - q[0][K]), sy[0]);
+            sy[1] = fmaf(g.cx[k], (a.y - q[1][K]) + (b.y - q[1][K]), sy[1]);
+            sy[2] = fmaf(g.cx[k], (a.z - q[2][K]) + (b.z - q[2][K]), sy[2]);
+            sy[3] = fmaf(g.cx[k], (a.w - q[3][K]) + (b.w - q[3][K]), sy[3]);
+        }
+        // damping a = dampx dx^2 + dampy dy^2 + dampz dz^2, update in increment form
+        const int dy_ = layer_depth(y, g.ix0[1], g.ix1[1]);
+        const int dz_ = layer_depth(z, g.ix0[2], g.ix1[2]);
+        const float ayz = g.dampy * (float)(dy_ * dy_) + g.dampz * (float)(dz_ * dz_);
+        const float din[4] = {S.d.x, S.d.y, S.d.z, S.d.w};
+        const float win[4] = {S.w.x, S.w.y, S.w.z, S.w.w};
+        const float uin[4] = {S.u.x, S.u.y, S.u.z, S.u.w};
+        float dn[4], on[4], wl[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int dx_ = layer_depth(x0 + i, g.ix0[0], g.ix1[0]);
+            const float a = fmaf(g.dampx, (float)(dx_ * dx_), ayz);
+            const float l = fmaf(c1, sy[i], lap[i]);
+            wl[i] = win[i] * l;
+            const float r = __builtin_amdgcn_rcpf(1.0f + a);
+            dn[i] = ((1.0f - a) * din[i] + wl[i]) * r;
+            on[i] = q[i][K] + dn[i];
+        }
+        if (ptin) {
+            const long long p0 = (long long)z * sxy + rowoff + x0;
+            if constexpr (VEC) {
+                *reinterpret_cast<float4 *>(inc + p0) = make_float4(dn[0], dn[1], dn[2], dn[3]);
+                *reinterpret_cast<float4 *>(fout + p0) = make_float4(on[0], on[1], on[2], on[3]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (x0 + i < nx) {
+                        inc[p0 + i] = dn[i];
+                        fout[p0 + i] = on[i];
+                    }
+            }
+            if constexpr (GRAD) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (VEC || x0 + i < nx) G[p0 + i] = gold[i] + gscale * (double)uin[i] * (double)wl[i];
+            }
+        }
+        if (z + 1 < z1) {
+            *reinterpret_cast<float4 *>(&tile[cur ^ 1][ty + K][HX + 4 * tx4]) =
+                make_float4(q[0][K + 1], q[1][K + 1], q[2][K + 1], q[3][K + 1]);
+            if (tid < NH) *reinterpret_cast<float4 *>(&tile[cur ^ 1][hrow][hcol]) = S.h;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+            for (int j = 0; j < 2 * K; ++j) q[i][j] = q[i][j + 1];
+        }
+        q[0][2 * K] = S.f.x; q[1][2 * K] = S.f.y; q[2][2 * K] = S.f.z; q[3][2 * K] = S.f.w;
+    };
+    for (int z = z0; z < z1; z += 2) {
+        step(z, A, B);
+        if (z + 1 < z1) step(z + 1, B, A);
+    }
+}
+
+// 2-D: a workgroup owns 256 consecutive x and marches down z (the second axis).
+template <int K, bool GRAD>
+__global__ __launch_bounds__(256) void stencil2d(Grid g, const float *__restrict__ fin, float *__restrict__ fout,
+                                                 float *__restrict__ inc, const float *__restrict__ w,
+                                                 const float *__restrict__ uk, double *__restrict__ G,
+                                                 double gscale, int tiles_x, int zchunks, int zlen)
+{
+    constexpr int TX = 256;
+    __shared__ float row[TX + 2 * K];
+    const int nwg = tiles_x * zchunks;
+    const int lid = xcd_remap(blockIdx.x, nwg);
+    const int tix = lid % tiles_x, zc = lid / tiles_x;
+    const int z0 = zc * zlen, z1 = min(z0 + zlen, g.nz);
+    const int nx = g.nx, nz = g.nz;
+    const int tid = threadIdx.x;
+    const int x = tix * TX + tid;
+    const bool in = x < nx;
+    const float *col = fin + (in ? x : 0);
+    float q[2 * K + 1];
+#pragma unroll
+    for (int j = 0; j < 2 * K; ++j) {
+        const int z = z0 - K + j;
+        q[j] = (in && z >= 0 && z < nz) ? col[(long long)z * nx] : 0.0f;
+    }
+    for (int z = z0; z < z1; ++z) {
+        const int zf = z + K;
+        q[2 * K] = (in && zf < nz) ? col[(long long)zf * nx] : 0.0f;
+        row[tid + K] = q[K];
+        const float *plane = fin + (long long)z * nx;
+        if (tid < K) {
+            const int gl = tix * TX - K + tid;
+            row[tid] = (gl >= 0 && gl < nx) ? plane[gl] : 0.0f;
+            const int gr = tix * TX + TX + tid;
+            row[TX + K + tid] = (gr < nx) ? plane[gr] : 0.0f;
+        }
+        __syncthreads();
+        if (in) {
+            const float c = q[K];
+            float sx = 0.0f, sz = 0.0f;
+#pragma unroll
+            for (int k = 1; k <= K; ++k) {
+                sx = fmaf(g.cx[k], (row[tid + K + k] - c) + (row[tid + K - k] - c), sx);
+                sz = fmaf(g.cz[k], (q[K + k] - c) + (q[K - k] - c), sz);
+            }
+            const float lap = sx + sz;
+            const long long p = (long long)z * nx + x;
+            const float a = damping(g, x, 0, z);
+            const float wl = w[p] * lap;
+            const float dn = damped_increment(a, inc[p], wl);
+            inc[p] = dn;
+            fout[p] = c + dn;
+            if constexpr (GRAD) G[p] += gscale * (double)uk[p] * (double)wl;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 2 * K; ++j) q[j] = q[j + 1];
+    }
+}
+
+template <bool GRAD>
+__global__ void inject_kernel(Grid g, Sparse sp, const float *__restrict__ vals, const float *__restrict__ w,
+                              float *__restrict__ inc, float *__restrict__ fout, const float *__restrict__ uk,
+                              double *__restrict__ G, double gscale)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sp.npts) return;
+    const int p = sp.s_pts[i];
+    float s = 0.0f;
+    for (int e = sp.s_start[i]; e < sp.s_start[i + 1]; ++e) s = fmaf(sp.s_wt[e], vals[sp.s_col[e]], s);
+    const long long sxy = (long long)g.nx * g.ny;
+    const int z = (int)(p / sxy);
+    const int rem = (int)(p - z * sxy);
+    const int y = rem / g.nx, x = rem - (rem / g.nx) * g.nx;
+    const float a = damping(g, x, y, z);
+    const float wi = w[p] * s;
+    const float inj = (a == 0.0f) ? wi : wi / (1.0f + a);
+    inc[p] += inj;
+    fout[p] += inj;
+    if constexpr (GRAD) G[p] += gscale * (double)uk[p] * (double)wi;
+}
+
+__global__ void gather_kernel(Sparse sp, const float *__restrict__ f, float *__restrict__ out)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= sp.n) return;
+    float s = 0.0f;
+    for (int c = 0; c < sp.nc; ++c) s = fmaf(sp.g_wt[r * sp.nc + c], f[sp.g_idx[r * sp.nc + c]], s);
+    out[r] = s;
+}
+
+__global__ void gather_sum_kernel(Sparse sp, const float *__restrict__ f, float *__restrict__ out)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    float tot = 0.0f;
+    for (int r = 0; r < sp.n; ++r) {
+        float s = 0.0f;
+        for (int c = 0; c < sp.nc; ++c) s = fmaf(sp.g_wt[r * sp.nc + c], f[sp.g_idx[r * sp.nc + c]], s);
+        tot += s;
+    }
+    out[0] = tot;
+}
+
+__global__ void setup_w_kernel(const float *__restrict__ vel, float *__restrict__ w, long long P, double dt,
+                               double vmax, unsigned *err)
+{
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P;
+         p += (long long)gridDim.x * blockDim.x) {
+        const float v = vel[p];
+        const double vd = (double)v;
+        if (!(vd > 0.0) || !(vd <= vmax)) atomicOr(err, 1u);
+        w[p] = (float)(dt * dt * vd * vd);
+    }
+}
+
+template <typename T>
+__global__ void fill_kernel(T *p, long long n, T v)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void check_finite_kernel(const float *__restrict__ f, long long n, unsigned *err)
+{
+    bool bad = false;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        bad |= !isfinite(f[i]);
+    if (bad) atomicOr(err, 8u);
+}
+
+constexpr int kRedThreads = 256;
+
+__global__ __launch_bounds__(kRedThreads) void residual_kernel(const float *__restrict__ dsim,
+                                                               const float *__restrict__ dobs,
+                                                               float *__restrict__ res, long long n,
+                                                               long long nrec, double *partials)
+{
+    __shared__ double sh[kRedThreads];
+    double acc = 0.0;
+    for (long long e = blockIdx.x * (long long)kRedThreads + threadIdx.x; e < n;
+         e += (long long)gridDim.x * kRedThreads) {
+        if (e < nrec) {
+            res[e] = 0.0f;
+            continue;
+        }
+        const double r = (double)dsim[e] - (double)dobs[e];
+        res[e] = (float)r;
+        acc += r * r;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kRedThreads) void final_sum_kernel(const double *partials, int n, double *out)
+{
+    __shared__ double sh[kRedThreads];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += kRedThreads) acc += partials[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = 0.5 * sh[0];
+}
+
+struct Dims3 { int n[3]; int N[3]; int nbl; int nd; };
+
+__global__ void pad_kernel(Dims3 d, const float *__restrict__ vin, float *__restrict__ vout, long long P)
+{
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P;
+         p += (long long)gridDim.x * blockDim.x) {
+        long long r = p;
+        long long src = 0, stride = 1;
+        for (int a = 0; a < d.nd; ++a) {
+            int i = (int)(r % d.N[a]);
+            r /= d.N[a];
+            int j = i - d.nbl;
+            j = j < 0 ? 0 : (j > d.n[a] - 1 ? d.n[a] - 1 : j);
+            src += (long long)j * stride;
+            stride *= d.n[a];
+        }
+        vout[p] = vin[src];
+    }
+}
+
+__global__ void velgrad_kernel(Dims3 d, const float *__restrict__ vpad, const double *__restrict__ gm,
+                               double *__restrict__ gv, long long Pint)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < Pint;
+         q += (long long)gridDim.x * blockDim.x) {
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        long long r = q;
+        for (int a = 0; a < d.nd; ++a) {
+            int j = (int)(r % d.n[a]);
+            r /= d.n[a];
+            lo[a] = (j == 0) ? 0 : j + d.nbl;
+            hi[a] = (j == d.n[a] - 1) ? d.N[a] - 1 : j + d.nbl;
+        }
+        double s = 0.0;
+        const int z1 = d.nd == 3 ? hi[2] : 0, zl = d.nd == 3 ? lo[2] : 0;
+        for (int k = zl; k <= z1; ++k)
+            for (int j = lo[1]; j <= hi[1]; ++j)
+                for (int i = lo[0]; i <= hi[0]; ++i) {
+                    const long long p = ((long long)k * d.N[1] + j) * d.N[0] + i;
+                    const double c = (double)vpad[p];
+                    s += gm[p] * (-2.0 / (c * c * c));
+                }
+        gv[q] = s;
+    }
+}
+
+int grid_for(long long n, int threads)
+{
+    long long b = (n + threads - 1) / threads;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+// z chunking: enough workgroups to keep every CU busy, chunks no shorter than 4K planes.
+void choose_chunks(long long tiles, int nz, int K, int target, int &zchunks, int &zlen)
+{
+    long long want = target / tiles;
+    long long maxc = nz / (4 * (K > 0 ? K : 1));
+    if (maxc < 1) maxc = 1;
+    if (want > maxc) want = maxc;
+    if (want < 1) want = 1;
+    zlen = (int)((nz + want - 1) / want);
+    zchunks = (nz + zlen - 1) / zlen;
+}
+
+// Workgroups that fit on the device at once for this kernel (occupancy x CUs).
+template <typename Kern>
+int resident_workgroups(Kern kern)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1024;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    return cus * per_cu;
+}
+
+template <int K, bool GRAD, bool VEC>
+hipError_t launch3d(const Grid &g, const float *fin, float *fout, float *inc, const float *w, const float *uk,
+                    double *G, double gscale, hipStream_t s)
+{
+    auto kern = stencil3d<K, GRAD, VEC>;
+    const int tiles_x = (g.nx + 31) / 32, tiles_y = (g.ny + 31) / 32;
+    // one resident round of workgroups: z chunks as long as possible (the 2K-plane
+    // warm-up of each chunk re-reads the field), but enough of them to fill the GPU
+    int zchunks, zlen;
+    choose_chunks((long long)tiles_x * tiles_y, g.nz, K, resident_workgroups(kern), zchunks, zlen);
+    const int nwg = tiles_x * tiles_y * zchunks;
+    hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), 0, s, g, fin, fout, inc, w, uk, G, gscale, tiles_x, tiles_y,
+                       zchunks, zlen);
+    return hipGetLastError();
+}
+
+template <int K, bool GRAD>
+hipError_t launch_k(const Grid &g, const float *fin, float *fout, float *inc, const float *w, const float *uk,
+                    double *G, double gscale, hipStream_t s)
+{
+    if (g.ndim == 3) {
+        if (g.nx % 4 == 0) return launch3d<K, GRAD, true>(g, fin, fout, inc, w, uk, G, gscale, s);
+        return launch3d<K, GRAD, false>(g, fin, fout, inc, w, uk, G, gscale, s);
+    }
+    const int tiles_x = (g.nx + 255) / 256;
+    int zchunks, zlen;
+    choose_chunks(tiles_x, g.nz, K, 512, zchunks, zlen);
+    const int nwg = tiles_x * zchunks;
+    hipLaunchKernelGGL((stencil2d<K, GRAD>), dim3(nwg), dim3(256), 0, s, g, fin, fout, inc, w, uk, G, gscale,
+                       tiles_x, zchunks, zlen);
+    return hipGetLastError();
+}
+
+template <bool GRAD>
+hipError_t launch_any(const Grid &g, const float *fin, float *fout, float *inc, const float *w, const float *uk,
+                      double *G, double gscale, hipStream_t s)
+{
+    switch (g.K) {
+    case 1: return launch_k<1, GRAD>(g, fin, fout, inc, w, uk, G, gscale, s);
+    case 2: return launch_k<2, GRAD>(g, fin, fout, inc, w, uk, G, gscale, s);
+    case 3: return launch_k<3, GRAD>(g, fin, fout, inc, w, uk, G, gscale, s);
+    case 4: return launch_k<4, GRAD>(g, fin, fout, inc, w, uk, G, gscale, s);
+    case 5: return launch_k<5, GRAD>(g, fin, fout, inc, w, uk, G, gscale, s);
+    case 6: return launch_k<6, GRAD>(g, fin, fout, inc, w, uk, G, gscale, s);
+    case 7: return launch_k<7, GRAD>(g, fin, fout, inc, w, uk, G, gscale, s);
+    case 8: return launch_k<8, GRAD>(g, fin, fout, inc, w, uk, G, gscale, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fwd_step(const Grid &g, const float *u_in, float *u_out, float *d, const float *w, hipStream_t s)
+{
+    return launch_any<false>(g, u_in, u_out, d, w, nullptr, nullptr, 0.0, s);
+}
+
+hipError_t launch_adj_step(const Grid &g, const float *lam_in, float *lam_out, float *mu, const float *w,
+                           const float *uk, double *G, double gscale, hipStream_t s)
+{
+    if (G) return launch_any<true>(g, lam_in, lam_out, mu, w, uk, G, gscale, s);
+    return launch_any<false>(g, lam_in, lam_out, mu, w, nullptr, nullptr, 0.0, s);
+}
+
+hipError_t launch_inject_src(const Grid &g, const Sparse &sp, const float *q, int n, const float *w, float *d,
+                             float *u_out, hipStream_t s)
+{
+    if (sp.npts == 0) return hipSuccess;
+    hipLaunchKernelGGL((inject_kernel<false>), dim3((sp.npts + 63) / 64), dim3(64), 0, s, g, sp, q + n, w, d, u_out,
+                       nullptr, nullptr, 0.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_inject_res(const Grid &g, const Sparse &sp, const float *r_row, const float *w, float *mu,
+                             float *lam_out, const float *uk, double *G, double gscale, hipStream_t s)
+{
+    if (sp.npts == 0) return hipSuccess;
+    if (G)
+        hipLaunchKernelGGL((inject_kernel<true>), dim3((sp.npts + 255) / 256), dim3(256), 0, s, g, sp, r_row, w, mu,
+                           lam_out, uk, G, gscale);
+    else
+        hipLaunchKernelGGL((inject_kernel<false>), dim3((sp.npts + 255) / 256), dim3(256), 0, s, g, sp, r_row, w,
+                           mu, lam_out, nullptr, nullptr, 0.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const Sparse &sp, const float *f, float *out, hipStream_t s)
+{
+    if (sp.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_kernel, dim3((sp.n + 255) / 256), dim3(256), 0, s, sp, f, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_sum(const Sparse &sp, const float *f, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(gather_sum_kernel, dim3(1), dim3(64), 0, s, sp, f, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup_w(const float *vel, float *w, long long P, double dt, double vmax, unsigned *err,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(setup_w_kernel, dim3(grid_for(P, 256)), dim3(256), 0, s, vel, w, P, dt, vmax, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float *p, long long n, float v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((fill_kernel<float>), dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *p, long long n, double v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((fill_kernel<double>), dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t *p, long long n, uint64_t v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((fill_kernel<uint64_t>), dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const float *f, long long n, unsigned *err, hipStream_t s)
+{
+    hipLaunchKernelGGL(check_finite_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, f, n, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_misfit(const float *dsim, const float *dobs, float *res, long long n, long long nrec,
+                                  double *partials, int nparts, double *misfit, hipStream_t s)
+{
+    hipLaunchKernelGGL(residual_kernel, dim3(nparts), dim3(kRedThreads), 0, s, dsim, dobs, res, n, nrec, partials);
+    hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(kRedThreads), 0, s, partials, nparts, misfit);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_velocity(int ndim, const int *n, int nbl, const float *vin, float *vout, hipStream_t s)
+{
+    Dims3 d{};
+    d.nd = ndim;
+    d.nbl = nbl;
+    long long P = 1;
+    for (int a = 0; a < 3; ++a) {
+        d.n[a] = a < ndim ? n[a] : 1;
+        d.N[a] = a < ndim ? n[a] + 2 * nbl : 1;
+        P *= d.N[a];
+    }
+    hipLaunchKernelGGL(pad_kernel, dim3(grid_for(P, 256)), dim3(256), 0, s, d, vin, vout, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_velocity_gradient(int ndim, const int *n, int nbl, const float *vpad, const double *gm,
+                                    double *gv, hipStream_t s)
+{
+    Dims3 d{};
+    d.nd = ndim;
+    d.nbl = nbl;
+    long long Pint = 1;
+    for (int a = 0; a < 3; ++a) {
+        d.n[a] = a < ndim ? n[a] : 1;
+        d.N[a] = a < ndim ? n[a] + 2 * nbl : 1;
+        Pint *= d.n[a];
+    }
+    hipLaunchKernelGGL(velgrad_kernel, dim3(grid_for(Pint, 256)), dim3(256), 0, s, d, vpad, gm, gv, Pint);
+    return hipGetLastError();
+}
+
+}  // namespace wv

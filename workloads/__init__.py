@@ -106,18 +106,26 @@ def surface_geometry(n, h, depth_cells: int = 2, rec_every: int = 1):
 
 # ------------------------------------------------------------------ configs
 
-def two_layer_2d(n=(101, 101), h=(10.0, 10.0), nbl=20, nt=500, order=4) -> Shot:
+def two_layer_2d(n=(101, 101), h=(10.0, 10.0), nbl=20, nt=500, order=4, interface_z=500.0,
+                 anomaly_centre=(500.0, 500.0), src_x=500.0, f0=10.0) -> Shot:
     """2-D, two layers 1.5 / 2.5 km/s split at z = 500 m (z >= 500 m below), Ricker 10 Hz
     at (500 m, 20 m), 101 receivers at z = 20 m; d_obs from the same model plus a
-    Gaussian +0.2 km/s anomaly (sigma 100 m) at (500 m, 500 m)."""
+    Gaussian +0.2 km/s anomaly (sigma 100 m) at (500 m, 500 m).  The keyword arguments
+    move the interface, anomaly and source for smaller test variants."""
     g = _grid(n, h)
     z = g[0]
-    vel = np.where(z < 500.0 - 1e-9, 1500.0, 2500.0)
-    anom = gaussian_anomaly(n, h, 200.0, 100.0, (500.0, 500.0))
-    src = np.array([[500.0, 20.0]])
+    vel = np.where(z < interface_z - 1e-9, 1500.0, 2500.0)
+    anom = gaussian_anomaly(n, h, 200.0, 100.0, anomaly_centre)
+    src = np.array([[src_x, 20.0]])
     rec = np.stack([np.arange(n[0]) * h[0], np.full(n[0], 20.0)], axis=1)
-    return Shot("two_layer_2d", 2, tuple(n), tuple(h), nbl, order, nt, 10.0,
+    return Shot("two_layer_2d", 2, tuple(n), tuple(h), nbl, order, nt, f0,
                 vel.astype(np.float32), (vel + anom).astype(np.float32), src, rec)
+
+
+def near_anomaly_2d(n=(61, 61), nt=400, order=4, nbl=20) -> Shot:
+    """Small two-layer variant whose anomaly the wave reaches early (well-conditioned residual)."""
+    return two_layer_2d(n=n, nbl=nbl, nt=nt, order=order, interface_z=200.0, anomaly_centre=(300.0, 250.0),
+                        src_x=300.0, f0=10.0)
 
 
 def layered_noise_3d(n=(128, 128, 128), h=(10.0, 10.0, 10.0), nbl=20, nt=1000, order=8, seed=2,
@@ -246,5 +254,5 @@ def small(shot_fn, **kw) -> Shot:
 
 
 __all__ = ["Shot", "pad_edge", "ricker", "surface_geometry", "two_layer_2d", "layered_noise_3d",
-           "smooth_random_2d", "fault_body_3d", "random_layers", "serving_stream", "CONFIGS", "replace",
+           "smooth_random_2d", "fault_body_3d", "near_anomaly_2d", "random_layers", "serving_stream", "CONFIGS", "replace",
            "Request", "gaussian_anomaly"]
