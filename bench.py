@@ -197,7 +197,7 @@ def main():
             "adjoint_step": {"avg_ms": adj_ms, "GBs": round(adj_gbs, 1), "frac": round(adj_gbs / HBM_PEAK_GBS, 4)}}
     st = st_comp[0]
     enc_gbs = 8.0 * Pn * st["stores"] / (st["ms_store"] * 1e-3) / 1e9 if st["ms_store"] > 0 else None
-    dec_gbs = 8.0 * Pn * st["restores"] / (st["ms_restore"] * 1e-3) / 1e9 if st["ms_restore"] > 0 else None
+    dec_gbs = 8.0 * Pn * st["decodes"] / (st["ms_restore"] * 1e-3) / 1e9 if st["ms_restore"] > 0 else None
 
     ms_step = 1e3 * statistics.mean(w_comp)
     value = Pn * 2 * shot.nt / (ms_step * 1e-3) / 1e9
@@ -215,7 +215,8 @@ def main():
         "grad_rel_err_vs_plain": err,
         "plain_gpts": round(Pn * 2 * shot.nt / statistics.mean(w_plain) / 1e9, 3),
         "latency_ms": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, math.ceil(0.99 * len(lat)) - 1)]},
-        "schedule": {"compressed": {k: st[k] for k in ("slots", "advances", "stores", "restores", "ratio")},
+        "schedule": {"compressed": {k: st[k] for k in ("slots", "advances", "stores", "restores", "decodes",
+                                                         "ratio")},
                      "plain": {k: st_plain[0][k] for k in ("slots", "advances", "stores", "restores")}},
         "phase_ms": {"compressed": {k: st[k] for k in ("ms_forward", "ms_adjoint", "ms_store", "ms_restore")},
                      "plain": {k: st_plain[0][k] for k in ("ms_forward", "ms_adjoint", "ms_store", "ms_restore")}},
@@ -226,8 +227,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample) ...")
-        out["cpu_baseline"] = cpu_baseline(shot, {k: st[k] for k in ("advances", "reverses", "stores",
-                                                                      "restores")}, args.tol)
+        out["cpu_baseline"] = cpu_baseline(shot, {"advances": st["advances"], "reverses": st["reverses"],
+                                                  "stores": st["stores"], "restores": st["decodes"]}, args.tol)
     print(json.dumps(out), flush=True)
 
 

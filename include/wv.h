@@ -87,7 +87,8 @@ typedef struct {
     int timing;          /* input: non-zero = time every schedule action with HIP events */
     long advances;       /* forward steps executed (first sweep + recomputation) */
     long stores;         /* checkpoints written */
-    long restores;       /* checkpoints read back */
+    long restores;       /* restore actions (a restore reads the checkpoint in place: no copy) */
+    long decodes;        /* restores that decoded a compressed checkpoint (the last one stays decoded) */
     long reverses;       /* adjoint steps */
     long slots;          /* M: checkpoint slots of the schedule (x_0 included) */
     double bytes_stored; /* sum of bytes written to checkpoint memory */
@@ -99,7 +100,7 @@ typedef struct {
     double ms_forward;   /* with timing: device ms in forward steps (stencil + source injection) */
     double ms_adjoint;   /* with timing: device ms in adjoint steps (stencil + gradient + residual injection) */
     double ms_store;     /* with timing: device ms writing checkpoints (copies or encodes) */
-    double ms_restore;   /* with timing: device ms reading checkpoints (copies or decodes) */
+    double ms_restore;   /* with timing: device ms restoring checkpoints (decodes; uncompressed restores are free) */
 } wv_stats;
 
 /* ------------------------------------------------------------------ queries */

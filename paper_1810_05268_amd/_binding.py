@@ -47,7 +47,7 @@ class WvGeom(C.Structure):
 
 class WvStats(C.Structure):
     _fields_ = [("timing", C.c_int), ("advances", C.c_long), ("stores", C.c_long), ("restores", C.c_long),
-                ("reverses", C.c_long), ("slots", C.c_long), ("bytes_stored", C.c_double),
+                ("decodes", C.c_long), ("reverses", C.c_long), ("slots", C.c_long), ("bytes_stored", C.c_double),
                 ("peak_bytes", C.c_double), ("ratio", C.c_double), ("ratio_planned", C.c_double),
                 ("misfit", C.c_double), ("ms_total", C.c_double), ("ms_forward", C.c_double),
                 ("ms_adjoint", C.c_double), ("ms_store", C.c_double), ("ms_restore", C.c_double)]

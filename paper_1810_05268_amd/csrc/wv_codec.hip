@@ -10,7 +10,8 @@
 //   * one lane encodes one block, so a 256-lane workgroup encodes a chunk of 256
 //     blocks; a block's bit length has a closed form per bit plane, so each lane
 //     first counts its bits, the workgroup scans them, and the chunk's word offset
-//     in the stream comes from a decoupled look-back over the preceding chunks;
+//     in the stream comes from a decoupled look-back over the preceding chunks
+//     (one wave reads 64 predecessor status words per round);
 //   * chunks start at 64-bit word boundaries and record their word offsets, so the
 //     decoder needs only a per-chunk scan of the 16-bit block lengths and every
 //     block decodes independently.
@@ -143,25 +144,48 @@ __device__ __forceinline__ void inv_transform(int32_t *q)
 
 __device__ __forceinline__ uint64_t low_mask(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
 
-// Bit writer over a zeroed word range: bits accumulate in `acc` for the word that
-// holds `pos`; completed words are OR-ed in (neighbouring lanes share edge words).
-struct BitWriter {
-    unsigned long long *data;
+// In-place transpose of a 32 x 32 bit matrix: bit k of a[s] moves to bit s of a[k]
+// (five stages of masked block swaps; an involution).
+constexpr uint32_t kSwapMask[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
+
+__device__ __forceinline__ void transpose32(uint32_t *a)
+{
+#pragma unroll
+    for (int st = 0; st < 5; ++st) {
+        const int j = 16 >> st;
+        const uint32_t m = kSwapMask[st];
+#pragma unroll
+        for (int s = 0; s < 32; ++s) {
+            if (!(s & j)) {
+                const uint32_t t = ((a[s] >> j) ^ a[s + j]) & m;
+                a[s] ^= t << j;
+                a[s + j] ^= t;
+            }
+        }
+    }
+}
+
+// Bit emitter: bits accumulate in `acc` for the word that holds `pos`; each
+// completed word, and the last partial one, goes to sink(word_index, bits), which
+// ORs it into a zeroed word range (neighbouring lanes share edge words).
+struct Emitter {
     long long pos;
     unsigned long long acc;
-    __device__ __forceinline__ void put(unsigned long long v, int nb)
+    template <typename Sink>
+    __device__ __forceinline__ void put(unsigned long long v, int nb, Sink &sink)
     {
         const int off = (int)(pos & 63);
         acc |= v << off;
         if (off + nb >= 64) {
-            atomicOr(&data[pos >> 6], acc);
+            sink(pos >> 6, acc);
             acc = off ? (v >> (64 - off)) : 0ull;
         }
         pos += nb;
     }
-    __device__ __forceinline__ void flush()
+    template <typename Sink>
+    __device__ __forceinline__ void flush(Sink &sink)
     {
-        if (pos & 63) atomicOr(&data[pos >> 6], acc);
+        if (pos & 63) sink(pos >> 6, acc);
     }
 };
 
@@ -205,7 +229,6 @@ struct EncArgs {
     const uint64_t *base;
     uint64_t *next;
     uint64_t *flags;
-    unsigned *ticket;
     uint32_t epoch;
     unsigned *err;
     unsigned long long *stats;
@@ -219,12 +242,13 @@ __device__ __forceinline__ uint64_t make_flag(uint64_t status, uint32_t epoch, u
     return status | ((uint64_t)(epoch & 0x3FFFFFFFu) << 32) | value;
 }
 
-template <int ND>
+template <int ND, bool VEC>
 __device__ __forceinline__ void load_block(const float *f, const int *dims, int bx, int by, int bz, float *v)
 {
     constexpr int KZ = ND == 3 ? 4 : 1;
-    const int ny = ND == 3 ? dims[1] : dims[1];
+    const int ny = dims[1];
     const int nzz = ND == 3 ? dims[2] : 1;
+    const bool full_x = 4 * bx + 3 < dims[0];
 #pragma unroll
     for (int k = 0; k < KZ; ++k) {
         const int z = min(4 * bz + k, nzz - 1);
@@ -232,27 +256,33 @@ __device__ __forceinline__ void load_block(const float *f, const int *dims, int 
         for (int j = 0; j < 4; ++j) {
             const int y = min(4 * by + j, ny - 1);
             const float *row = f + ((long long)z * ny + y) * dims[0];
+            if (VEC && full_x) {
+                const float4 t = *reinterpret_cast<const float4 *>(row + 4 * bx);
+                v[16 * k + 4 * j + 0] = t.x;
+                v[16 * k + 4 * j + 1] = t.y;
+                v[16 * k + 4 * j + 2] = t.z;
+                v[16 * k + 4 * j + 3] = t.w;
+            } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) v[16 * k + 4 * j + i] = row[min(4 * bx + i, dims[0] - 1)];
+                for (int i = 0; i < 4; ++i) v[16 * k + 4 * j + i] = row[min(4 * bx + i, dims[0] - 1)];
+            }
         }
     }
 }
 
-template <int ND>
+constexpr int kLdsWords = 1024;   // chunk bitstreams up to 8 KB are assembled in LDS
+
+template <int ND, bool VEC>
 __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
 {
     constexpr int S = ND == 3 ? 64 : 16;
-    __shared__ unsigned s_chunk;
     __shared__ unsigned s_scan[256];
     __shared__ unsigned long long s_excl;
+    __shared__ unsigned long long s_bits[kLdsWords];
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        const unsigned t = atomicAdd(A.ticket, 1u);
-        if (t == (unsigned)(A.nchunks - 1)) atomicExch(A.ticket, 0u);   // every ticket taken: reset for the next launch
-        s_chunk = t;
-    }
-    __syncthreads();
-    const long long c = s_chunk;
+    // Chunk c = workgroup c.  Workgroups are dispatched in index order on each XCD, so
+    // every chunk a look-back waits for is running or finished; the wait is bounded.
+    const long long c = blockIdx.x;
     const long long b = c * kBlocksPerChunk + tid;
     const bool valid = b < A.nblocks;
     const uint64_t base = *A.base;
@@ -265,7 +295,7 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
         bz = (int)(b / ((long long)A.nb[0] * A.nb[1]));
     }
     float v[S];
-    if (valid) load_block<ND>(A.field, A.dims, bx, by, bz, v);
+    if (valid) load_block<ND, VEC>(A.field, A.dims, bx, by, bz, v);
     else {
 #pragma unroll
         for (int i = 0; i < S; ++i) v[i] = 0.0f;
@@ -289,41 +319,42 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
     const bool coded = valid && finite && nonzero && prec > 0;
     const int kmin = 32 - prec;
 
-    unsigned long long m[32];
-#pragma unroll
-    for (int k = 0; k < 32; ++k) m[k] = 0ull;
-    if (coded) {
+    // bit planes: m_lo[k] / m_hi[k] hold bit k of coefficients 0..31 / 32..63
+    uint32_t m_lo[32], m_hi[32];
+    {
         int32_t q[S];
 #pragma unroll
-        for (int i = 0; i < S; ++i) q[i] = (int32_t)ldexpf(v[i], 30 - emax);   // exact scaling, truncation
+        for (int i = 0; i < S; ++i) q[i] = coded ? (int32_t)ldexpf(v[i], 30 - emax) : 0;   // exact scaling, truncation
         fwd_transform<ND>(q);
-        uint32_t u[S];
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int src = ND == 3 ? kPerm3.v[s] : kPerm2.v[s];
-            u[s] = ((uint32_t)q[src] + 0xAAAAAAAAu) ^ 0xAAAAAAAAu;
+        for (int s = 0; s < 32; ++s) {
+            const int src = ND == 3 ? kPerm3.v[s] : kPerm2.v[s & 15];
+            m_lo[s] = (s < S) ? (((uint32_t)q[src] + 0xAAAAAAAAu) ^ 0xAAAAAAAAu) : 0u;
+            if constexpr (ND == 3) m_hi[s] = (((uint32_t)q[kPerm3.v[32 + s]] + 0xAAAAAAAAu) ^ 0xAAAAAAAAu);
+            else m_hi[s] = 0u;
         }
-#pragma unroll
-        for (int k = 0; k < 32; ++k) {
-            if (k >= kmin) {
-                unsigned long long mk = 0ull;
-#pragma unroll
-                for (int s = 0; s < S; ++s) mk |= (unsigned long long)((u[s] >> k) & 1u) << s;
-                m[k] = mk;
-            }
-        }
+        transpose32(m_lo);
+        if constexpr (ND == 3) transpose32(m_hi);
     }
+    // Planes run from 31 down to the lowest kmin of the wave in a plain (rolled)
+    // loop: the plane index is wave-uniform, so m_lo[k] / m_hi[k] stay in registers
+    // (indexed moves), and each lane skips the planes below its own kmin.
+    int kmin_w = coded ? kmin : 32;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) kmin_w = min(kmin_w, __shfl_xor(kmin_w, o));
+    kmin_w = __builtin_amdgcn_readfirstlane(kmin_w);
+
     // closed-form bit count of the block
     unsigned nbits = valid ? 1u : 0u;
-    if (coded) {
-        nbits += 8;
+    if (coded) nbits += 8;
+    {
         int n = 0;
-#pragma unroll
-        for (int k = 31; k >= 0; --k) {
-            if (k >= kmin) {
+#pragma unroll 1
+        for (int k = 31; k >= kmin_w; --k) {
+            if (coded && k >= kmin) {
                 nbits += n;
                 if (n < S) {
-                    const unsigned long long r = m[k] >> n;
+                    const unsigned long long r = ((unsigned long long)m_hi[k] << 32 | m_lo[k]) >> n;
                     if (r == 0ull) nbits += 1;
                     else {
                         const int pt = 63 - __clzll((long long)r);
@@ -353,38 +384,47 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
     const unsigned total_bits = s_scan[255];
     const uint32_t chunk_words = (total_bits + 63u) / 64u;
 
-    // decoupled look-back over the preceding chunks (bounded wait)
-    if (tid == 0) {
+    // decoupled look-back, one wave, 64 predecessors per round (bounded wait)
+    if (tid < 64) {
+        const uint32_t ep = A.epoch & 0x3FFFFFFFu;
         unsigned long long excl = 0;
-        if (c == 0) {
-            __hip_atomic_store(&A.flags[0], make_flag(kFlagPrefix, A.epoch, chunk_words), __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(&A.flags[c], make_flag(kFlagAgg, A.epoch, chunk_words), __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            long long j = c - 1;
+        if (c > 0) {
+            if (tid == 0)
+                __hip_atomic_store(&A.flags[c], make_flag(kFlagAgg, A.epoch, chunk_words), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            long long top = c - 1;
             unsigned spins = 0;
             while (true) {
-                const uint64_t f = __hip_atomic_load(&A.flags[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                const long long j = top - tid;
+                const uint64_t f = j >= 0 ? __hip_atomic_load(&A.flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                          : make_flag(kFlagPrefix, A.epoch, 0u);   // before the first chunk: 0
                 const uint64_t st = f & (3ull << 62);
-                const uint32_t ep = (uint32_t)((f >> 32) & 0x3FFFFFFFu);
-                if (st != 0 && ep == (A.epoch & 0x3FFFFFFFu)) {
-                    excl += (uint32_t)f;
-                    if (st == kFlagPrefix) break;
-                    --j;
-                    if (j < 0) break;
-                } else {
+                const bool ok = st != 0 && (uint32_t)((f >> 32) & 0x3FFFFFFFu) == ep;
+                const unsigned long long pm = __ballot(ok && st == kFlagPrefix);
+                const unsigned long long vm = __ballot(ok);
+                const int first = pm ? __ffsll((long long)pm) - 1 : 64;
+                const unsigned long long need = first >= 63 ? ~0ull : ((2ull << first) - 1ull);
+                if ((vm & need) != need) {
                     if (++spins > (1u << 22)) {
-                        atomicOr(A.err, 16u);
+                        if (tid == 0) atomicOr(A.err, 16u);
                         break;
                     }
                     __builtin_amdgcn_s_sleep(1);
+                    continue;
                 }
+                long long val = (tid <= first) ? (long long)(uint32_t)f : 0;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) val += __shfl_xor(val, o);
+                excl += (unsigned long long)val;
+                if (first < 64) break;
+                top -= 64;
             }
-            __hip_atomic_store(&A.flags[c], make_flag(kFlagPrefix, A.epoch, (uint32_t)(excl + chunk_words)),
-                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_excl = excl;
+        if (tid == 0) {
+            __hip_atomic_store(&A.flags[c], make_flag(kFlagPrefix, A.epoch, (uint32_t)(excl + chunk_words)),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_excl = excl;
+        }
     }
     __syncthreads();
     const unsigned long long excl = s_excl;
@@ -393,36 +433,52 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
     if (tid == 0 && prefix_fits) chunk_off[c] = excl;
     if (tid == 0 && !fits) atomicOr(A.err, 4u);
     unsigned long long *data = (unsigned long long *)(hdr + A.prefix_bytes) + excl;
-    if (fits) {
-        for (uint32_t i = tid; i < chunk_words; i += 256) data[i] = 0ull;
-    }
-    __syncthreads();
-    if (fits && valid) {
-        BitWriter wr{data, (long long)excl_bits, 0ull};
-        wr.put(coded ? 1ull : 0ull, 1);
-        if (coded) {
-            wr.put((unsigned long long)(emax + 127), 8);
+
+    auto emit = [&](auto &sink) {
+        Emitter em{(long long)excl_bits, 0ull};
+        em.put(coded ? 1ull : 0ull, 1, sink);
+        if (coded) em.put((unsigned long long)(emax + 127), 8, sink);
+        {
             int n = 0;
-#pragma unroll
-            for (int k = 31; k >= 0; --k) {
-                if (k >= kmin) {
-                    const unsigned long long mk = m[k];
-                    if (n > 0) wr.put(mk & low_mask(n), n);
+#pragma unroll 1
+            for (int k = 31; k >= kmin_w; --k) {
+                if (coded && k >= kmin) {
+                    const unsigned long long mk = (unsigned long long)m_hi[k] << 32 | m_lo[k];
+                    if (n > 0) em.put(mk & low_mask(n), n, sink);
                     if (n < S) {
                         unsigned long long r = mk >> n;
                         while (r != 0ull) {
                             const int z = __ffsll((long long)r) - 1;
-                            wr.put(1ull, 1);
-                            wr.put(1ull << z, z + 1);
+                            em.put(1ull, 1, sink);
+                            em.put(1ull << z, z + 1, sink);
                             n += z + 1;
                             r = (z + 1 < 64) ? (r >> (z + 1)) : 0ull;
                         }
-                        if (n < S) wr.put(0ull, 1);
+                        if (n < S) em.put(0ull, 1, sink);
                     }
                 }
             }
         }
-        wr.flush();
+        em.flush(sink);
+    };
+
+    if (fits && chunk_words <= (uint32_t)kLdsWords) {
+        // assemble the chunk in LDS, then store it with coalesced writes
+        for (uint32_t i = tid; i < chunk_words; i += 256) s_bits[i] = 0ull;
+        __syncthreads();
+        if (valid) {
+            auto sink = [&](long long w, unsigned long long bits) { atomicOr(&s_bits[w], bits); };
+            emit(sink);
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < chunk_words; i += 256) data[i] = s_bits[i];
+    } else if (fits) {
+        for (uint32_t i = tid; i < chunk_words; i += 256) data[i] = 0ull;
+        __syncthreads();
+        if (valid) {
+            auto sink = [&](long long w, unsigned long long bits) { atomicOr(&data[w], bits); };
+            emit(sink);
+        }
     }
     if (c == A.nchunks - 1 && tid == 0) {
         const unsigned long long data_words = excl + chunk_words;
@@ -463,7 +519,7 @@ struct DecArgs {
     long long nblocks, nchunks, prefix_bytes;
 };
 
-template <int ND>
+template <int ND, bool VEC>
 __global__ __launch_bounds__(256) void decode_kernel(DecArgs A)
 {
     constexpr int S = ND == 3 ? 64 : 16;
@@ -556,12 +612,18 @@ __global__ __launch_bounds__(256) void decode_kernel(DecArgs A)
             }
             m[k] = mk;
         }
+        uint32_t lo[32], hi[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            lo[k] = (uint32_t)m[k];
+            hi[k] = (uint32_t)(m[k] >> 32);
+        }
+        transpose32(lo);
+        if constexpr (ND == 3) transpose32(hi);
         int32_t q[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            uint32_t u = 0;
-#pragma unroll
-            for (int k = 0; k < 32; ++k) u |= (uint32_t)((m[k] >> s) & 1ull) << k;
+            const uint32_t u = s < 32 ? lo[s] : hi[s - 32];
             const int dst = ND == 3 ? kPerm3.v[s] : kPerm2.v[s];
             q[dst] = (int32_t)((u ^ 0xAAAAAAAAu) - 0xAAAAAAAAu);
         }
@@ -574,17 +636,23 @@ __global__ __launch_bounds__(256) void decode_kernel(DecArgs A)
     const int bz = (int)(b / ((long long)A.nb[0] * A.nb[1]));
     constexpr int KZ = ND == 3 ? 4 : 1;
     const int nzz = ND == 3 ? A.dims[2] : 1;
+    const bool full_x = 4 * bx + 3 < A.dims[0];
 #pragma unroll
     for (int k = 0; k < KZ; ++k) {
         const int z = 4 * bz + k;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int y = 4 * by + j;
+            if (y >= A.dims[1] || z >= nzz) continue;
+            float *row = A.field + ((long long)z * A.dims[1] + y) * A.dims[0];
+            if (VEC && full_x) {
+                *reinterpret_cast<float4 *>(row + 4 * bx) =
+                    make_float4(out[16 * k + 4 * j + 0], out[16 * k + 4 * j + 1], out[16 * k + 4 * j + 2],
+                                out[16 * k + 4 * j + 3]);
+            } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int x = 4 * bx + i;
-                if (x < A.dims[0] && y < A.dims[1] && z < nzz)
-                    A.field[((long long)z * A.dims[1] + y) * A.dims[0] + x] = out[16 * k + 4 * j + i];
+                for (int i = 0; i < 4; ++i)
+                    if (4 * bx + i < A.dims[0]) row[4 * bx + i] = out[16 * k + 4 * j + i];
             }
         }
     }
@@ -616,7 +684,7 @@ size_t codec_max_bytes(const CodecDims &cd)
 }
 
 hipError_t launch_encode(const CodecDims &cd, const float *field, double tol, uint8_t *out, uint64_t cap,
-                         const uint64_t *base, uint64_t *next, uint64_t *flags, unsigned *ticket, uint32_t epoch,
+                         const uint64_t *base, uint64_t *next, uint64_t *flags, uint32_t epoch,
                          unsigned *err, unsigned long long *stats, hipStream_t s)
 {
     EncArgs A{};
@@ -638,14 +706,18 @@ hipError_t launch_encode(const CodecDims &cd, const float *field, double tol, ui
     A.base = base;
     A.next = next;
     A.flags = flags;
-    A.ticket = ticket;
     A.epoch = epoch;
     A.err = err;
     A.stats = stats;
-    if (cd.ndim == 3)
-        hipLaunchKernelGGL(encode_kernel<3>, dim3((unsigned)cd.nchunks), dim3(256), 0, s, A);
-    else
-        hipLaunchKernelGGL(encode_kernel<2>, dim3((unsigned)cd.nchunks), dim3(256), 0, s, A);
+    const bool vec = cd.dims[0] % 4 == 0;
+    const dim3 grid((unsigned)cd.nchunks);
+    if (cd.ndim == 3) {
+        if (vec) hipLaunchKernelGGL((encode_kernel<3, true>), grid, dim3(256), 0, s, A);
+        else hipLaunchKernelGGL((encode_kernel<3, false>), grid, dim3(256), 0, s, A);
+    } else {
+        if (vec) hipLaunchKernelGGL((encode_kernel<2, true>), grid, dim3(256), 0, s, A);
+        else hipLaunchKernelGGL((encode_kernel<2, false>), grid, dim3(256), 0, s, A);
+    }
     return hipGetLastError();
 }
 
@@ -664,10 +736,15 @@ hipError_t launch_decode(const CodecDims &cd, const uint8_t *in, const uint64_t 
     A.nblocks = cd.nblocks;
     A.nchunks = cd.nchunks;
     A.prefix_bytes = cd.prefix_bytes;
-    if (cd.ndim == 3)
-        hipLaunchKernelGGL(decode_kernel<3>, dim3((unsigned)cd.nchunks), dim3(256), 0, s, A);
-    else
-        hipLaunchKernelGGL(decode_kernel<2>, dim3((unsigned)cd.nchunks), dim3(256), 0, s, A);
+    const bool vec = cd.dims[0] % 4 == 0;
+    const dim3 grid((unsigned)cd.nchunks);
+    if (cd.ndim == 3) {
+        if (vec) hipLaunchKernelGGL((decode_kernel<3, true>), grid, dim3(256), 0, s, A);
+        else hipLaunchKernelGGL((decode_kernel<3, false>), grid, dim3(256), 0, s, A);
+    } else {
+        if (vec) hipLaunchKernelGGL((decode_kernel<2, true>), grid, dim3(256), 0, s, A);
+        else hipLaunchKernelGGL((decode_kernel<2, false>), grid, dim3(256), 0, s, A);
+    }
     return hipGetLastError();
 }
 

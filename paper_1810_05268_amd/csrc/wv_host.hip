@@ -181,7 +181,7 @@ int hip_fail(hipError_t e, const char *what, int line)
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    size_t bk, U0, U1, D, L0, L1, MU, W;
+    size_t bk, U0, U1, D, L0, L1, MU, W, Z, UB, DB;
     size_t src_tab, rec_tab, tab_bytes;
     size_t res, dsim, partials, flags, offs, arena;
     size_t total;
@@ -192,7 +192,7 @@ struct Layout {
 
 constexpr size_t kBk = 4096;
 // bookkeeping words inside bk
-constexpr size_t kErr = 0, kTicket = 64, kMisfit = 128, kStats = 192, kZero = 256, kProbeNext = 264, kScal = 320;
+constexpr size_t kErr = 0, kMisfit = 128, kStats = 192, kZero = 256, kProbeNext = 264, kScal = 320;
 constexpr int kParts = 1024;
 
 struct Setup {
@@ -372,6 +372,7 @@ Layout plan_layout(const wv_model *m, const wv_geom *geo, const Setup &su, int o
     L.U1 = take(fb);
     L.D = take(fb);
     L.W = take(fb);
+    L.Z = take(fb);
     L.src_tab = take(tab_bytes(su, false));
     L.rec_tab = take(tab_bytes(su, true));
     const size_t data_bytes = (size_t)(m->nt + 1) * geo->nrec * 4;
@@ -379,6 +380,8 @@ Layout plan_layout(const wv_model *m, const wv_geom *geo, const Setup &su, int o
         L.L0 = take(fb);
         L.L1 = take(fb);
         L.MU = take(fb);
+        L.UB = take(fb);
+        L.DB = take(fb);
         L.res = take(data_bytes);
         L.dsim = take(data_bytes);
         L.partials = take(kParts * 8);
@@ -401,8 +404,8 @@ struct Dev {
     uint8_t *base;
     Layout L;
     Sparse src, rec;
-    float *U[2], *D, *Lm[2], *MU, *W;
-    unsigned *err, *ticket;
+    float *U[2], *D, *Lm[2], *MU, *W, *Z, *UB, *DB;
+    unsigned *err;
     double *misfit;
     unsigned long long *stats;
     uint64_t *zero, *probe_next, *flags, *offs;
@@ -459,8 +462,8 @@ int bind(Dev &d, void *ws, size_t ws_bytes, const Layout &L, int op)
     d.U[1] = at<float>(d.base, L.U1);
     d.D = at<float>(d.base, L.D);
     d.W = at<float>(d.base, L.W);
+    d.Z = at<float>(d.base, L.Z);
     d.err = at<unsigned>(d.base, L.bk + kErr);
-    d.ticket = at<unsigned>(d.base, L.bk + kTicket);
     d.misfit = at<double>(d.base, L.bk + kMisfit);
     d.stats = at<unsigned long long>(d.base, L.bk + kStats);
     d.zero = at<uint64_t>(d.base, L.bk + kZero);
@@ -469,6 +472,8 @@ int bind(Dev &d, void *ws, size_t ws_bytes, const Layout &L, int op)
         d.Lm[0] = at<float>(d.base, L.L0);
         d.Lm[1] = at<float>(d.base, L.L1);
         d.MU = at<float>(d.base, L.MU);
+        d.UB = at<float>(d.base, L.UB);
+        d.DB = at<float>(d.base, L.DB);
         d.res = at<float>(d.base, L.res);
         d.dsim = at<float>(d.base, L.dsim);
         d.partials = at<double>(d.base, L.partials);
@@ -493,24 +498,44 @@ int start(Dev &d, const wv_model *m, const Setup &su, hipStream_t s)
     int rc = upload_tables(d, su, s);
     if (rc) return rc;
     HIPCHK(launch_setup_w(m->vel, d.W, su.P, m->dt, m->vmax, d.err, s));
+    HIPCHK(launch_fill_f32(d.Z, su.P, 0.0f, s));
     unsigned e = 0;
     rc = read_err(d, s, &e);
     if (rc) return rc;
     return e ? WV_EINVAL : WV_OK;
 }
 
+// The forward state x_k = (u^k, d^k).  It lives either in the working buffers
+// (U[cur], D) or, right after a restore, in place at its source: the zero field for
+// x_0, the checkpoint slot itself (uncompressed) or the decoded base pair
+// (compressed).  The next step reads it there and writes the working buffers, so a
+// restore moves no data.
 struct Fwd {
     Dev &d;
     const Setup &su;
     const wv_geom *geo;
-    int cur = 0;
     hipStream_t s;
+    const float *u = nullptr, *du = nullptr;   // current u^k, d^k
+    const float *u_prev = nullptr;              // u^{k-1} after a step (the step's input)
+    int cur = 0;
+    bool in_work = false;
+    void at(const float *uu, const float *dd)
+    {
+        u = uu;
+        du = dd;
+        in_work = false;
+    }
     int step(int n, float *data_row)
     {
-        HIPCHK(launch_fwd_step(su.g, d.U[cur], d.U[cur ^ 1], d.D, d.W, s));
-        HIPCHK(launch_inject_src(su.g, d.src, geo->wavelet, n, d.W, d.D, d.U[cur ^ 1], s));
-        cur ^= 1;
-        if (data_row) HIPCHK(launch_gather(d.rec, d.U[cur], data_row, s));
+        const int o = in_work ? (cur ^ 1) : cur;
+        HIPCHK(launch_fwd_step(su.g, u, d.U[o], du, d.D, d.W, s));
+        HIPCHK(launch_inject_src(su.g, d.src, geo->wavelet, n, d.W, d.D, d.U[o], s));
+        u_prev = u;
+        cur = o;
+        u = d.U[o];
+        du = d.D;
+        in_work = true;
+        if (data_row) HIPCHK(launch_gather(d.rec, u, data_row, s));
         return WV_OK;
     }
 };
@@ -587,17 +612,16 @@ int wv_forward(const wv_model *m, const wv_geom *geo, float *data, float *state_
     Dev d{};
     if ((rc = bind(d, ws, ws_bytes, L, WV_OP_FORWARD))) return rc;
     if ((rc = start(d, m, su, s))) return rc;
-    HIPCHK(launch_fill_f32(d.U[0], su.P, 0.0f, s));
-    HIPCHK(launch_fill_f32(d.D, su.P, 0.0f, s));
     HIPCHK(launch_fill_f32(data, geo->nrec, 0.0f, s));
-    Fwd f{d, su, geo, 0, s};
+    Fwd f{d, su, geo, s};
+    f.at(d.Z, d.Z);
     for (int n = 0; n < m->nt; ++n)
         if ((rc = f.step(n, data + (size_t)(n + 1) * geo->nrec))) return rc;
     if (state_out) {
-        HIPCHK(hipMemcpyAsync(state_out, d.U[f.cur], (size_t)su.P * 4, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(state_out + su.P, d.U[f.cur ^ 1], (size_t)su.P * 4, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(state_out, f.u, (size_t)su.P * 4, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(state_out + su.P, f.u_prev, (size_t)su.P * 4, hipMemcpyDeviceToDevice, s));
     }
-    HIPCHK(launch_check_finite(d.U[f.cur], su.P, d.err, s));
+    HIPCHK(launch_check_finite(f.u, su.P, d.err, s));
     unsigned e = 0;
     if ((rc = read_err(d, s, &e))) return rc;
     return (e & 8u) ? WV_EUNSTABLE : WV_OK;
@@ -624,13 +648,13 @@ struct GradRun {
     CodecDims cd{};
     size_t S = 0;                      // bytes of one uncompressed checkpoint
     uint32_t epoch = 0;
-    long advances = 0, stores = 0, restores = 0, reverses = 0;
+    long advances = 0, stores = 0, restores = 0, reverses = 0, decodes = 0;
     int max_depth = 0;
 
     int encode_field(const float *f, uint64_t *base, uint64_t *next)
     {
         ++epoch;
-        HIPCHK(launch_encode(cd, f, tol, d.arena, d.L.arena_bytes, base, next, d.flags, d.ticket, epoch, d.err,
+        HIPCHK(launch_encode(cd, f, tol, d.arena, d.L.arena_bytes, base, next, d.flags, epoch, d.err,
                              d.stats, s));
         return WV_OK;
     }
@@ -694,9 +718,9 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
 
     float *data = R.misfit_mode ? (R.dsim_out ? R.dsim_out : d.dsim) : nullptr;
     const float *res = R.misfit_mode ? d.res : R.residual;
-    Fwd f{d, R.su, R.geo, 0, s};
-    HIPCHK(launch_fill_f32(d.U[0], P, 0.0f, s));
-    HIPCHK(launch_fill_f32(d.D, P, 0.0f, s));
+    Fwd f{d, R.su, R.geo, s};
+    f.at(d.Z, d.Z);
+    int hot_slot = -1, hot_k = -1;   // checkpoint currently decoded in the base pair
     HIPCHK(launch_fill_f32(d.Lm[0], P, 0.0f, s));
     HIPCHK(launch_fill_f32(d.MU, P, 0.0f, s));
     if (R.G) HIPCHK(launch_fill_f64(R.G, P, 0.0, s));
@@ -733,27 +757,32 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
             break;
         case STORE:
             if (comp) {
-                if ((rc = R.encode_field(d.U[f.cur], d.offs + 2 * b, d.offs + 2 * b + 1))) break;
-                if ((rc = R.encode_field(d.D, d.offs + 2 * b + 1, d.offs + 2 * b + 2))) break;
+                if ((rc = R.encode_field(f.u, d.offs + 2 * b, d.offs + 2 * b + 1))) break;
+                if ((rc = R.encode_field(f.du, d.offs + 2 * b + 1, d.offs + 2 * b + 2))) break;
+                if (hot_slot == b) hot_slot = -1;
             } else {
                 uint8_t *slot = d.arena + (size_t)(b - 1) * R.S;
-                HIPCHK(hipMemcpyAsync(slot, d.U[f.cur], fb, hipMemcpyDeviceToDevice, s));
-                HIPCHK(hipMemcpyAsync(slot + fb, d.D, fb, hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(slot, f.u, fb, hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(slot + fb, f.du, fb, hipMemcpyDeviceToDevice, s));
             }
             R.stores++;
             R.max_depth = std::max(R.max_depth, b);
             break;
         case RESTORE:
             if (b == 0) {
-                HIPCHK(launch_fill_f32(d.U[f.cur], P, 0.0f, s));
-                HIPCHK(launch_fill_f32(d.D, P, 0.0f, s));
+                f.at(d.Z, d.Z);
             } else if (comp) {
-                HIPCHK(launch_decode(R.cd, d.arena, d.offs + 2 * b, d.L.arena_bytes, d.U[f.cur], s));
-                HIPCHK(launch_decode(R.cd, d.arena, d.offs + 2 * b + 1, d.L.arena_bytes, d.D, s));
+                if (hot_slot != b || hot_k != a) {
+                    HIPCHK(launch_decode(R.cd, d.arena, d.offs + 2 * b, d.L.arena_bytes, d.UB, s));
+                    HIPCHK(launch_decode(R.cd, d.arena, d.offs + 2 * b + 1, d.L.arena_bytes, d.DB, s));
+                    hot_slot = b;
+                    hot_k = a;
+                    R.decodes++;
+                }
+                f.at(d.UB, d.DB);
             } else {
-                const uint8_t *slot = d.arena + (size_t)(b - 1) * R.S;
-                HIPCHK(hipMemcpyAsync(d.U[f.cur], slot, fb, hipMemcpyDeviceToDevice, s));
-                HIPCHK(hipMemcpyAsync(d.D, slot + fb, fb, hipMemcpyDeviceToDevice, s));
+                const float *slot = (const float *)(d.arena + (size_t)(b - 1) * R.S);
+                f.at(slot, slot + P);
             }
             R.restores++;
             break;
@@ -761,12 +790,12 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
             break;
         case REVERSE: {
             if (!residual_ready) {
-                HIPCHK(launch_check_finite(d.U[f.cur], P, d.err, s));
+                HIPCHK(launch_check_finite(f.u, P, d.err, s));
                 HIPCHK(launch_residual_misfit(data, R.dobs, d.res, (long long)(N + 1) * R.geo->nrec, R.geo->nrec,
                                               d.partials, kParts, d.misfit, s));
                 residual_ready = true;
             }
-            const float *uk = R.G ? d.U[f.cur] : nullptr;
+            const float *uk = R.G ? f.u : nullptr;
             HIPCHK(launch_adj_step(R.su.g, d.Lm[lc], d.Lm[lc ^ 1], d.MU, d.W, uk, R.G, gscale, s));
             HIPCHK(launch_inject_res(R.su.g, d.rec, res + (size_t)a * R.geo->nrec, d.W, d.MU, d.Lm[lc ^ 1], uk, R.G,
                                      gscale, s));
@@ -806,6 +835,7 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
         stats->advances = R.advances;
         stats->stores = R.stores;
         stats->restores = R.restores;
+        stats->decodes = R.decodes;
         stats->reverses = R.reverses;
         stats->slots = M;
         stats->bytes_stored = comp ? (double)st[0] : (double)R.stores * (double)R.S;
@@ -829,9 +859,8 @@ int probe_ratio(GradRun &R, double *ratio)
     hipStream_t s = R.s;
     const long long P = R.su.P;
     float *data = R.misfit_mode ? (R.dsim_out ? R.dsim_out : d.dsim) : nullptr;
-    Fwd f{d, R.su, R.geo, 0, s};
-    HIPCHK(launch_fill_f32(d.U[0], P, 0.0f, s));
-    HIPCHK(launch_fill_f32(d.D, P, 0.0f, s));
+    Fwd f{d, R.su, R.geo, s};
+    f.at(d.Z, d.Z);
     HIPCHK(launch_fill_u64(d.offs, d.L.offs_n, 0, s));
     HIPCHK(launch_fill_u64(d.flags, d.L.nchunks_max, 0, s));
     HIPCHK(launch_fill_u64(at<uint64_t>(d.base, d.L.bk + kStats), 2, 0, s));
@@ -840,8 +869,8 @@ int probe_ratio(GradRun &R, double *ratio)
         if (rc) return rc;
     }
     int rc;
-    if ((rc = R.encode_field(d.U[f.cur], d.offs + 2, d.offs + 3))) return rc;
-    if ((rc = R.encode_field(d.D, d.offs + 3, d.offs + 4))) return rc;
+    if ((rc = R.encode_field(f.u, d.offs + 2, d.offs + 3))) return rc;
+    if ((rc = R.encode_field(f.du, d.offs + 3, d.offs + 4))) return rc;
     unsigned long long st[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(st, d.stats, sizeof(st), hipMemcpyDeviceToHost, s));
     unsigned e = 0;
@@ -955,7 +984,7 @@ int wv_velocity_gradient(int ndim, const int *n, int nbl, const float *vpad, con
 
 // ------------------------------------------------------------------ codec entry points
 namespace {
-constexpr size_t kCodecBk = 512;   // err, ticket, base word, next word, stats[2]
+constexpr size_t kCodecBk = 512;   // err, base word, next word, stats[2]
 }
 
 size_t wv_zfpk_workspace_bytes(int ndim, const int *dims)
@@ -985,14 +1014,13 @@ int wv_zfpk_encode(const float *field, int ndim, const int *dims, double tol, vo
     if (!ws || ws_bytes < wv_zfpk_workspace_bytes(ndim, dims) || (((uintptr_t)ws) & 255)) return WV_ENOMEM;
     uint8_t *b = (uint8_t *)ws;
     unsigned *err = (unsigned *)b;
-    unsigned *ticket = (unsigned *)(b + 64);
     uint64_t *base = (uint64_t *)(b + 128);
     uint64_t *next = (uint64_t *)(b + 136);
     unsigned long long *st = (unsigned long long *)(b + 192);
     uint64_t *flags = (uint64_t *)(b + kCodecBk);
     HIPCHK(launch_fill_u64((uint64_t *)b, kCodecBk / 8, 0, s));
     HIPCHK(launch_fill_u64(flags, cd.nchunks, 0, s));
-    HIPCHK(launch_encode(cd, field, tol, (uint8_t *)out, cap, base, next, flags, ticket, 1u, err, st, s));
+    HIPCHK(launch_encode(cd, field, tol, (uint8_t *)out, cap, base, next, flags, 1u, err, st, s));
     unsigned e = 0;
     unsigned long long tot[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, s));

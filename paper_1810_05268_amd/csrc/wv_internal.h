@@ -40,9 +40,10 @@ struct Sparse {
 };
 
 // ---------------------------------------------------------------- stencil launches (wv_stencil.hip)
-// Forward step in increment form: d <- ((1-a) d + w lap u)/(1+a), u_out = u_in + d.
-hipError_t launch_fwd_step(const Grid &g, const float *u_in, float *u_out, float *d, const float *w,
-                           hipStream_t s);
+// Forward step in increment form: d_out = ((1-a) d_in + w lap u_in)/(1+a), u_out = u_in + d_out
+// (d_in may equal d_out; u_in must differ from u_out).
+hipError_t launch_fwd_step(const Grid &g, const float *u_in, float *u_out, const float *d_in, float *d_out,
+                           const float *w, hipStream_t s);
 // Adjoint step: mu <- ((1-a) mu + w lap lam)/(1+a), lam_out = lam_in + mu,
 // and (if G) G += gscale * uk * (w lap lam).
 hipError_t launch_adj_step(const Grid &g, const float *lam_in, float *lam_out, float *mu, const float *w,
@@ -87,7 +88,7 @@ size_t codec_max_bytes(const CodecDims &cd);
 // err: bit 2 = capacity overflow, bit 1 = non-finite input, bit 4 = look-back timeout.
 // stats[0] += stream bytes, stats[1] = max(stats[1], *next).
 hipError_t launch_encode(const CodecDims &cd, const float *field, double tol, uint8_t *out, uint64_t cap,
-                         const uint64_t *base, uint64_t *next, uint64_t *flags, unsigned *ticket, uint32_t epoch,
+                         const uint64_t *base, uint64_t *next, uint64_t *flags, uint32_t epoch,
                          unsigned *err, unsigned long long *stats, hipStream_t s);
 // Decode the stream at in + *base (base == nullptr: offset 0) into field; cap bytes
 // are readable from `in` (a stream that does not fit decodes to zeros).

@@ -69,7 +69,7 @@ __device__ __forceinline__ float damped_increment(float a, float d, float wl)
 // VEC: nx % 4 == 0, every float4 of a row is either inside or outside the grid.
 template <int K, bool GRAD, bool VEC>
 __global__ __launch_bounds__(256) void stencil3d(const Grid g, const float *__restrict__ fin,
-                                                 float *__restrict__ fout, float *__restrict__ inc,
+                                                 float *__restrict__ fout, const float *inc_in, float *inc,
                                                  const float *__restrict__ w, const float *__restrict__ uk,
                                                  double *__restrict__ G, double gscale, int tiles_x, int tiles_y,
                                                  int zchunks, int zlen)
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void stencil3d(const Grid g, const float *__re
     auto fill = [&](Stage &S, int z) {
         const bool pin = ptin && z < z1;
         const long long off = (long long)z * sxy + rowoff;
-        S.d = load4(inc, off, x0, pin);
+        S.d = load4(inc_in, off, x0, pin);
         S.w = load4(w, off, x0, pin);
         if constexpr (GRAD) S.u = load4(uk, off, x0, pin);
         const bool more = z + 1 < z1;
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(256) void stencil3d(const Grid g, const float *__re
 // 2-D: a workgroup owns 256 consecutive x and marches down z (the second axis).
 template <int K, bool GRAD>
 __global__ __launch_bounds__(256) void stencil2d(Grid g, const float *__restrict__ fin, float *__restrict__ fout,
-                                                 float *__restrict__ inc, const float *__restrict__ w,
+                                                 const float *inc_in, float *inc, const float *__restrict__ w,
                                                  const float *__restrict__ uk, double *__restrict__ G,
                                                  double gscale, int tiles_x, int zchunks, int zlen)
 {
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(256) void stencil2d(Grid g, const float *__restrict
             const long long p = (long long)z * nx + x;
             const float a = damping(g, x, 0, z);
             const float wl = w[p] * lap;
-            const float dn = damped_increment(a, inc[p], wl);
+            const float dn = damped_increment(a, inc_in[p], wl);
             inc[p] = dn;
             fout[p] = c + dn;
             if constexpr (GRAD) G[p] += gscale * (double)uk[p] * (double)wl;
@@ -522,8 +522,8 @@ int resident_workgroups(Kern kern)
 }
 
 template <int K, bool GRAD, bool VEC>
-hipError_t launch3d(const Grid &g, const float *fin, float *fout, float *inc, const float *w, const float *uk,
-                    double *G, double gscale, hipStream_t s)
+hipError_t launch3d(const Grid &g, const float *fin, float *fout, const float *inc_in, float *inc, const float *w,
+                    const float *uk, double *G, double gscale, hipStream_t s)
 {
     auto kern = stencil3d<K, GRAD, VEC>;
     const int tiles_x = (g.nx + 31) / 32, tiles_y = (g.ny + 31) / 32;
@@ -532,57 +532,58 @@ hipError_t launch3d(const Grid &g, const float *fin, float *fout, float *inc, co
     int zchunks, zlen;
     choose_chunks((long long)tiles_x * tiles_y, g.nz, K, resident_workgroups(kern), zchunks, zlen);
     const int nwg = tiles_x * tiles_y * zchunks;
-    hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), 0, s, g, fin, fout, inc, w, uk, G, gscale, tiles_x, tiles_y,
-                       zchunks, zlen);
+    hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), 0, s, g, fin, fout, inc_in, inc, w, uk, G, gscale, tiles_x,
+                       tiles_y, zchunks, zlen);
     return hipGetLastError();
 }
 
 template <int K, bool GRAD>
-hipError_t launch_k(const Grid &g, const float *fin, float *fout, float *inc, const float *w, const float *uk,
-                    double *G, double gscale, hipStream_t s)
+hipError_t launch_k(const Grid &g, const float *fin, float *fout, const float *inc_in, float *inc, const float *w,
+                    const float *uk, double *G, double gscale, hipStream_t s)
 {
     if (g.ndim == 3) {
-        if (g.nx % 4 == 0) return launch3d<K, GRAD, true>(g, fin, fout, inc, w, uk, G, gscale, s);
-        return launch3d<K, GRAD, false>(g, fin, fout, inc, w, uk, G, gscale, s);
+        if (g.nx % 4 == 0) return launch3d<K, GRAD, true>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
+        return launch3d<K, GRAD, false>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
     }
     const int tiles_x = (g.nx + 255) / 256;
     int zchunks, zlen;
     choose_chunks(tiles_x, g.nz, K, 512, zchunks, zlen);
     const int nwg = tiles_x * zchunks;
-    hipLaunchKernelGGL((stencil2d<K, GRAD>), dim3(nwg), dim3(256), 0, s, g, fin, fout, inc, w, uk, G, gscale,
-                       tiles_x, zchunks, zlen);
+    hipLaunchKernelGGL((stencil2d<K, GRAD>), dim3(nwg), dim3(256), 0, s, g, fin, fout, inc_in, inc, w, uk, G,
+                       gscale, tiles_x, zchunks, zlen);
     return hipGetLastError();
 }
 
 template <bool GRAD>
-hipError_t launch_any(const Grid &g, const float *fin, float *fout, float *inc, const float *w, const float *uk,
-                      double *G, double gscale, hipStream_t s)
+hipError_t launch_any(const Grid &g, const float *fin, float *fout, const float *inc_in, float *inc, const float *w,
+                      const float *uk, double *G, double gscale, hipStream_t s)
 {
     switch (g.K) {
-    case 1: return launch_k<1, GRAD>(g, fin, fout, inc, w, uk, G, gscale, s);
-    case 2: return launch_k<2, GRAD>(g, fin, fout, inc, w, uk, G, gscale, s);
-    case 3: return launch_k<3, GRAD>(g, fin, fout, inc, w, uk, G, gscale, s);
-    case 4: return launch_k<4, GRAD>(g, fin, fout, inc, w, uk, G, gscale, s);
-    case 5: return launch_k<5, GRAD>(g, fin, fout, inc, w, uk, G, gscale, s);
-    case 6: return launch_k<6, GRAD>(g, fin, fout, inc, w, uk, G, gscale, s);
-    case 7: return launch_k<7, GRAD>(g, fin, fout, inc, w, uk, G, gscale, s);
-    case 8: return launch_k<8, GRAD>(g, fin, fout, inc, w, uk, G, gscale, s);
+    case 1: return launch_k<1, GRAD>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
+    case 2: return launch_k<2, GRAD>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
+    case 3: return launch_k<3, GRAD>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
+    case 4: return launch_k<4, GRAD>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
+    case 5: return launch_k<5, GRAD>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
+    case 6: return launch_k<6, GRAD>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
+    case 7: return launch_k<7, GRAD>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
+    case 8: return launch_k<8, GRAD>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-hipError_t launch_fwd_step(const Grid &g, const float *u_in, float *u_out, float *d, const float *w, hipStream_t s)
+hipError_t launch_fwd_step(const Grid &g, const float *u_in, float *u_out, const float *d_in, float *d_out,
+                           const float *w, hipStream_t s)
 {
-    return launch_any<false>(g, u_in, u_out, d, w, nullptr, nullptr, 0.0, s);
+    return launch_any<false>(g, u_in, u_out, d_in, d_out, w, nullptr, nullptr, 0.0, s);
 }
 
 hipError_t launch_adj_step(const Grid &g, const float *lam_in, float *lam_out, float *mu, const float *w,
                            const float *uk, double *G, double gscale, hipStream_t s)
 {
-    if (G) return launch_any<true>(g, lam_in, lam_out, mu, w, uk, G, gscale, s);
-    return launch_any<false>(g, lam_in, lam_out, mu, w, nullptr, nullptr, 0.0, s);
+    if (G) return launch_any<true>(g, lam_in, lam_out, mu, mu, w, uk, G, gscale, s);
+    return launch_any<false>(g, lam_in, lam_out, mu, mu, w, nullptr, nullptr, 0.0, s);
 }
 
 hipError_t launch_inject_src(const Grid &g, const Sparse &sp, const float *q, int n, const float *w, float *d,
