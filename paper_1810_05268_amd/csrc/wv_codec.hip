@@ -11,7 +11,7 @@
 //     blocks; a block's bit length has a closed form per bit plane, so each lane
 //     first counts its bits, the workgroup scans them, and the chunk's word offset
 //     in the stream comes from a decoupled look-back over the preceding chunks
-//     (one wave reads 64 predecessor status words per round);
+//     (one wave reads 256 predecessor status words per round);
 //   * chunks start at 64-bit word boundaries and record their word offsets, so the
 //     decoder needs only a per-chunk scan of the 16-bit block lengths and every
 //     block decodes independently.
@@ -242,13 +242,15 @@ __device__ __forceinline__ uint64_t make_flag(uint64_t status, uint32_t epoch, u
     return status | ((uint64_t)(epoch & 0x3FFFFFFFu) << 32) | value;
 }
 
+// Block values, axis 0 fastest; partial blocks repeat the last valid index.  With
+// VEC (dims[0] % 4 == 0) every block is complete along x and each row is one
+// float4 load with no branch, so all 16 row loads of a lane are in flight together.
 template <int ND, bool VEC>
 __device__ __forceinline__ void load_block(const float *f, const int *dims, int bx, int by, int bz, float *v)
 {
     constexpr int KZ = ND == 3 ? 4 : 1;
     const int ny = dims[1];
     const int nzz = ND == 3 ? dims[2] : 1;
-    const bool full_x = 4 * bx + 3 < dims[0];
 #pragma unroll
     for (int k = 0; k < KZ; ++k) {
         const int z = min(4 * bz + k, nzz - 1);
@@ -256,7 +258,7 @@ __device__ __forceinline__ void load_block(const float *f, const int *dims, int 
         for (int j = 0; j < 4; ++j) {
             const int y = min(4 * by + j, ny - 1);
             const float *row = f + ((long long)z * ny + y) * dims[0];
-            if (VEC && full_x) {
+            if constexpr (VEC) {
                 const float4 t = *reinterpret_cast<const float4 *>(row + 4 * bx);
                 v[16 * k + 4 * j + 0] = t.x;
                 v[16 * k + 4 * j + 1] = t.y;
@@ -384,7 +386,8 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
     const unsigned total_bits = s_scan[255];
     const uint32_t chunk_words = (total_bits + 63u) / 64u;
 
-    // decoupled look-back, one wave, 64 predecessors per round (bounded wait)
+    // decoupled look-back: one wave reads 256 predecessor status words per round
+    // (4 per lane, nearest first) and stops at the nearest inclusive prefix
     if (tid < 64) {
         const uint32_t ep = A.epoch & 0x3FFFFFFFu;
         unsigned long long excl = 0;
@@ -395,16 +398,30 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
             long long top = c - 1;
             unsigned spins = 0;
             while (true) {
-                const long long j = top - tid;
-                const uint64_t f = j >= 0 ? __hip_atomic_load(&A.flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                          : make_flag(kFlagPrefix, A.epoch, 0u);   // before the first chunk: 0
-                const uint64_t st = f & (3ull << 62);
-                const bool ok = st != 0 && (uint32_t)((f >> 32) & 0x3FFFFFFFu) == ep;
-                const unsigned long long pm = __ballot(ok && st == kFlagPrefix);
-                const unsigned long long vm = __ballot(ok);
-                const int first = pm ? __ffsll((long long)pm) - 1 : 64;
-                const unsigned long long need = first >= 63 ? ~0ull : ((2ull << first) - 1ull);
-                if ((vm & need) != need) {
+                uint64_t f[4];
+                int firstp = 4;            // nearest prefix among this lane's four
+                bool allok = true;         // every word up to (and incl.) that prefix is valid
+                unsigned long long sum = 0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const long long j = top - 4 * tid - i;
+                    f[i] = j >= 0 ? __hip_atomic_load(&A.flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                  : make_flag(kFlagPrefix, A.epoch, 0u);   // before the first chunk: 0
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint64_t st = f[i] & (3ull << 62);
+                    const bool ok = st != 0 && (uint32_t)((f[i] >> 32) & 0x3FFFFFFFu) == ep;
+                    if (firstp == 4) {
+                        allok = allok && ok;
+                        sum += ok ? (uint32_t)f[i] : 0u;
+                        if (ok && st == kFlagPrefix) firstp = i;
+                    }
+                }
+                const unsigned long long pm = __ballot(firstp < 4);
+                const int fl = pm ? __ffsll((long long)pm) - 1 : 64;     // nearest lane with a prefix
+                const unsigned long long bad = __ballot(!allok && tid <= fl);
+                if (bad) {
                     if (++spins > (1u << 22)) {
                         if (tid == 0) atomicOr(A.err, 16u);
                         break;
@@ -412,12 +429,12 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
                     __builtin_amdgcn_s_sleep(1);
                     continue;
                 }
-                long long val = (tid <= first) ? (long long)(uint32_t)f : 0;
+                long long val = tid <= fl ? (long long)sum : 0;
 #pragma unroll
                 for (int o = 32; o > 0; o >>= 1) val += __shfl_xor(val, o);
                 excl += (unsigned long long)val;
-                if (first < 64) break;
-                top -= 64;
+                if (fl < 64) break;
+                top -= 256;
             }
         }
         if (tid == 0) {
@@ -636,7 +653,6 @@ __global__ __launch_bounds__(256) void decode_kernel(DecArgs A)
     const int bz = (int)(b / ((long long)A.nb[0] * A.nb[1]));
     constexpr int KZ = ND == 3 ? 4 : 1;
     const int nzz = ND == 3 ? A.dims[2] : 1;
-    const bool full_x = 4 * bx + 3 < A.dims[0];
 #pragma unroll
     for (int k = 0; k < KZ; ++k) {
         const int z = 4 * bz + k;
@@ -645,7 +661,7 @@ __global__ __launch_bounds__(256) void decode_kernel(DecArgs A)
             const int y = 4 * by + j;
             if (y >= A.dims[1] || z >= nzz) continue;
             float *row = A.field + ((long long)z * A.dims[1] + y) * A.dims[0];
-            if (VEC && full_x) {
+            if (VEC) {
                 *reinterpret_cast<float4 *>(row + 4 * bx) =
                     make_float4(out[16 * k + 4 * j + 0], out[16 * k + 4 * j + 1], out[16 * k + 4 * j + 2],
                                 out[16 * k + 4 * j + 3]);

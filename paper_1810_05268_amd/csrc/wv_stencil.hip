@@ -61,14 +61,17 @@ __device__ __forceinline__ float damped_increment(float a, float d, float wl)
 //   * x, y neighbours: the centre plane staged in LDS with its halos (x halo padded to
 //     a multiple of four columns so that every LDS access is an aligned float4),
 //     double buffered, one barrier per plane;
-//   * software pipeline: while plane z is computed, every global load plane z+1
-//     needs (its point operands, the halo of the plane after it, the next queue
-//     front) is already in flight in a second register stage;
+//   * software pipeline: while plane z is computed, the global loads plane z+1
+//     needs (its point operands and the next queue front) are already in flight in a
+//     second register stage;
+//   * halos are read K+1 planes ahead, together with the queue front of the same
+//     plane, i.e. when the neighbouring tiles stream that plane from HBM, so they
+//     hit in L2; each lane parks its halo float4 in its own LDS ring slots;
 //   * interior LDS values come from the queue, so HBM is read once per value
 //     (plus the 2K-plane warm-up of each z chunk); halos come from L2.
 // VEC: nx % 4 == 0, every float4 of a row is either inside or outside the grid.
 template <int K, bool GRAD, bool VEC>
-__global__ __launch_bounds__(256) void stencil3d(const Grid g, const float *__restrict__ fin,
+__global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *__restrict__ fin,
                                                  float *__restrict__ fout, const float *inc_in, float *inc,
                                                  const float *__restrict__ w, const float *__restrict__ uk,
                                                  double *__restrict__ G, double gscale, int tiles_x, int tiles_y,
@@ -82,7 +85,9 @@ __global__ __launch_bounds__(256) void stencil3d(const Grid g, const float *__re
     constexpr int NHX = 2 * TY * (HX / 4);        // x-halo float4s per plane
     constexpr int NH = NHX + 2 * K * (TX / 4);    // all halo float4s per plane (<= 256)
     static_assert(NH <= 256, "one halo float4 per lane at most");
+    constexpr int R = K + 2;                     // halo ring: planes z+1 .. z+1+K in flight
     __shared__ __align__(16) float tile[2][LY][LX];
+    __shared__ __align__(16) float4 ring[R][256];   // lane-private slots: no barrier needed
 
     const int nwg = tiles_x * tiles_y * zchunks;
     const int lid = xcd_remap(blockIdx.x, nwg);
@@ -123,18 +128,29 @@ __global__ __launch_bounds__(256) void stencil3d(const Grid g, const float *__re
         hgy = tiy * TY - K + hrow;
     }
     const bool hact = tid < NH && hgy >= 0 && hgy < ny;
-    const long long hrowoff = (long long)(hact ? hgy : 0) * nx;
 
-    auto load4 = [&](const float *base, long long off, int gx, bool ok) -> float4 {
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (!ok) return v;
+    // Branch-free float4 load of (gx..gx+3, yy, z): the address is clamped into the
+    // grid and the value zeroed outside, so every lane issues its load and no wait
+    // is forced at a control-flow join (the pipeline depends on that).
+    auto load4 = [&](const float *base, int z, int yy, int gx, bool ok) -> float4 {
+        const bool in = ok && z >= 0 && z < nz && yy >= 0 && yy < ny;
+        const int zc = min(max(z, 0), nz - 1), yc = min(max(yy, 0), ny - 1);
+        const float *row = base + (long long)zc * sxy + (long long)yc * nx;
+        float4 v;
         if constexpr (VEC) {
-            if (gx >= 0 && gx < nx) v = *reinterpret_cast<const float4 *>(base + off + gx);
+            const bool inx = in && gx >= 0 && gx < nx;
+            const float4 t = *reinterpret_cast<const float4 *>(row + min(max(gx, 0), nx - 4));
+            v.x = inx ? t.x : 0.0f;
+            v.y = inx ? t.y : 0.0f;
+            v.z = inx ? t.z : 0.0f;
+            v.w = inx ? t.w : 0.0f;
         } else {
-            if (gx + 0 >= 0 && gx + 0 < nx) v.x = base[off + gx + 0];
-            if (gx + 1 >= 0 && gx + 1 < nx) v.y = base[off + gx + 1];
-            if (gx + 2 >= 0 && gx + 2 < nx) v.z = base[off + gx + 2];
-            if (gx + 3 >= 0 && gx + 3 < nx) v.w = base[off + gx + 3];
+            const float t0 = row[min(max(gx + 0, 0), nx - 1)], t1 = row[min(max(gx + 1, 0), nx - 1)];
+            const float t2 = row[min(max(gx + 2, 0), nx - 1)], t3 = row[min(max(gx + 3, 0), nx - 1)];
+            v.x = (in && gx + 0 >= 0 && gx + 0 < nx) ? t0 : 0.0f;
+            v.y = (in && gx + 1 >= 0 && gx + 1 < nx) ? t1 : 0.0f;
+            v.z = (in && gx + 2 >= 0 && gx + 2 < nx) ? t2 : 0.0f;
+            v.w = (in && gx + 3 >= 0 && gx + 3 < nx) ? t3 : 0.0f;
         }
         return v;
     };
@@ -144,44 +160,57 @@ __global__ __launch_bounds__(256) void stencil3d(const Grid g, const float *__re
     };
     // loads that computing plane z needs: its point operands, the halo of plane z+1
     // and the queue front of plane z+1+K
+    // point operands feed only values stored under the same in-range predicate, so
+    // they are loaded from the clamped address without zeroing
+    auto load4p = [&](const float *base, int z, int gx) -> float4 {
+        const int zc = min(z, nz - 1), yc = min(y, ny - 1);
+        const float *row = base + (long long)zc * sxy + (long long)yc * nx;
+        if constexpr (VEC) return *reinterpret_cast<const float4 *>(row + min(gx, nx - 4));
+        return make_float4(row[min(gx + 0, nx - 1)], row[min(gx + 1, nx - 1)], row[min(gx + 2, nx - 1)],
+                           row[min(gx + 3, nx - 1)]);
+    };
     auto fill = [&](Stage &S, int z) {
-        const bool pin = ptin && z < z1;
-        const long long off = (long long)z * sxy + rowoff;
-        S.d = load4(inc_in, off, x0, pin);
-        S.w = load4(w, off, x0, pin);
-        if constexpr (GRAD) S.u = load4(uk, off, x0, pin);
+        S.d = load4p(inc_in, z, x0);
+        S.w = load4p(w, z, x0);
+        if constexpr (GRAD) S.u = load4p(uk, z, x0);
         const bool more = z + 1 < z1;
-        S.h = load4(fin, (long long)(z + 1) * sxy + hrowoff, hgx, hact && more);
-        const int zf = z + 1 + K;
-        S.f = load4(fin, (long long)zf * sxy + rowoff, x0, more && rowin && zf < nz);
+        // the halo of plane z+1+K is read together with the queue front of the same
+        // plane (which is the neighbouring tiles' interior), so it hits in L2; it waits
+        // K+1 planes in the lane's ring slots before the tile needs it
+        S.h = load4(fin, z + 1 + K, hgy, hgx, hact && z + 1 + K < z1);
+        S.f = load4(fin, z + 1 + K, y, x0, more && rowin);
     };
 
     // register queue: q[i][j] = u(x0+i, y, z-K+j)
     float q[4][2 * K + 1];
 #pragma unroll
     for (int j = 0; j < 2 * K + 1; ++j) {
-        const int z = z0 - K + j;
-        const float4 v = load4(fin, (long long)z * sxy + rowoff, x0, rowin && z >= 0 && z < nz);
+        const float4 v = load4(fin, z0 - K + j, y, x0, rowin);
         q[0][j] = v.x; q[1][j] = v.y; q[2][j] = v.z; q[3][j] = v.w;
     }
     Stage A, B;
     fill(A, z0);
     {
-        const float4 hv = load4(fin, (long long)z0 * sxy + hrowoff, hgx, hact);
+        const float4 hv = load4(fin, z0, hgy, hgx, hact);
         *reinterpret_cast<float4 *>(&tile[0][ty + K][HX + 4 * tx4]) = make_float4(q[0][K], q[1][K], q[2][K], q[3][K]);
-        if (tid < NH) *reinterpret_cast<float4 *>(&tile[0][hrow][hcol]) = hv;
+        if (tid < NH) {
+            *reinterpret_cast<float4 *>(&tile[0][hrow][hcol]) = hv;
+#pragma unroll
+            for (int j = 1; j <= K; ++j) ring[(z0 + j) % R][tid] = load4(fin, z0 + j, hgy, hgx, hact && z0 + j < z1);
+        }
     }
     __syncthreads();
 
     const float c1 = g.cy[0], c2 = g.cz[0];   // h_x^2/h_y^2, h_x^2/h_z^2
     auto step = [&](int z, Stage &S, Stage &N) {
-        // the binary64 gradient is read in the iteration that updates it (registers)
+        // the binary64 gradient is read in the iteration that updates it (clamped
+        // address, no branch; only in-range lanes store the update)
         double gold[4] = {0.0, 0.0, 0.0, 0.0};
         if constexpr (GRAD) {
-            const long long pg = (long long)z * sxy + rowoff + x0;
+            const int yc = min(y, ny - 1);
+            const long long pg = (long long)z * sxy + (long long)yc * nx;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (ptin && (VEC || x0 + i < nx)) gold[i] = G[pg + i];
+            for (int i = 0; i < 4; ++i) gold[i] = G[pg + min(x0 + i, nx - 1)];
         }
         fill(N, z + 1);
         const int cur = (z - z0) & 1;
@@ -252,10 +281,12 @@ __global__ __launch_bounds__(256) void stencil3d(const Grid g, const float *__re
                     if (VEC || x0 + i < nx) G[p0 + i] = gold[i] + gscale * (double)uin[i] * (double)wl[i];
             }
         }
-        if (z + 1 < z1) {
-            *reinterpret_cast<float4 *>(&tile[cur ^ 1][ty + K][HX + 4 * tx4]) =
-                make_float4(q[0][K + 1], q[1][K + 1], q[2][K + 1], q[3][K + 1]);
-            if (tid < NH) *reinterpret_cast<float4 *>(&tile[cur ^ 1][hrow][hcol]) = S.h;
+        // stage plane z+1 (after the last plane this buffer is simply not read)
+        *reinterpret_cast<float4 *>(&tile[cur ^ 1][ty + K][HX + 4 * tx4]) =
+            make_float4(q[0][K + 1], q[1][K + 1], q[2][K + 1], q[3][K + 1]);
+        if (tid < NH) {
+            ring[(z + 1 + K) % R][tid] = S.h;
+            *reinterpret_cast<float4 *>(&tile[cur ^ 1][hrow][hcol]) = ring[(z + 1) % R][tid];
         }
         __syncthreads();
 #pragma unroll
@@ -265,10 +296,22 @@ __global__ __launch_bounds__(256) void stencil3d(const Grid g, const float *__re
         }
         q[0][2 * K] = S.f.x; q[1][2 * K] = S.f.y; q[2][2 * K] = S.f.z; q[3][2 * K] = S.f.w;
     };
-    for (int z = z0; z < z1; z += 2) {
-        step(z, A, B);
-        if (z + 1 < z1) step(z + 1, B, A);
+    // several planes per trip: the wait pass drains outstanding loads at the
+    // back-edge (four for the forward step; two where registers are tight)
+    int z = z0;
+    if constexpr (!GRAD) {
+        for (; z + 3 < z1; z += 4) {
+            step(z, A, B);
+            step(z + 1, B, A);
+            step(z + 2, A, B);
+            step(z + 3, B, A);
+        }
     }
+    for (; z + 1 < z1; z += 2) {
+        step(z, A, B);
+        step(z + 1, B, A);
+    }
+    if (z < z1) step(z, A, B);
 }
 
 // 2-D: a workgroup owns 256 consecutive x and marches down z (the second axis).
