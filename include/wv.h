@@ -62,6 +62,7 @@ extern "C" {
 #define WV_EUNSTABLE (-7)  /* non-finite wavefield detected */
 #define WV_ENOTIMPL (-8)
 #define WV_ECAP (-9)       /* codec output buffer too small */
+#define WV_ETIMEOUT (-10)  /* wv_engine_wait: the request has not finished yet */
 
 typedef struct {
     int ndim;            /* 2 or 3 */
@@ -206,6 +207,49 @@ int wv_zfpk_encode(const float *field, int ndim, const int *dims, double tol, vo
 
 /* Decode a stream made by wv_zfpk_encode into field (device, same dims). */
 int wv_zfpk_decode(const void *in, int ndim, const int *dims, float *field, void *stream);
+
+/* ------------------------------------------------------------------ serving engine */
+
+/* Continuous batching of shot-gradient requests (shots are independent; the paper
+ * computes one gradient per shot and sums them, Sec. "Example adjoint problem").
+ * The engine owns max_active worker threads, each with its own HIP stream (default
+ * priority) on the device current at creation.  A queued request is admitted, first
+ * come first served, as soon as a worker is free and a contiguous slice of the pool
+ * holds its workspace (wv_workspace_bytes with WV_OP_GRADIENT and its mem_budget,
+ * i.e. its working fields plus its checkpoint arena); its kernels then run beside
+ * those of the other admitted requests.  A request's result does not depend on what
+ * else is in flight. */
+typedef struct wv_engine wv_engine;
+
+typedef struct {
+    int status;          /* WV_OK or the wv_misfit_gradient error */
+    double misfit;
+    double t_submit_ms;  /* engine clock (ms since creation) */
+    double t_start_ms;   /* admission */
+    double t_end_ms;     /* completion */
+    wv_stats stats;
+} wv_result;
+
+/* pool: device memory, 256-byte aligned, caller-owned, must outlive the engine.
+ * max_active: 1..64 requests in flight. */
+int wv_engine_create(void *pool, size_t pool_bytes, int max_active, wv_engine **engine);
+
+/* Queue a misfit + gradient request (as wv_misfit_gradient).  model->vel, wavelet,
+ * d_obs, grad_m and d_sim (nullable) must stay valid until wv_engine_wait returns
+ * for it; src/rec host arrays are copied.  Returns the request id (>= 0), WV_EBUDGET
+ * if its workspace exceeds the whole pool, or WV_EINVAL. */
+int wv_engine_submit(wv_engine *engine, const wv_model *model, const wv_geom *geom, const float *d_obs,
+                     size_t mem_budget, double tol, double ratio_hint, double *grad_m, float *d_sim);
+
+/* Wait for request id (timeout_ms < 0: no limit) and release it.  WV_ETIMEOUT if it
+ * did not finish in time (it stays queued or running). */
+int wv_engine_wait(wv_engine *engine, int id, double timeout_ms, wv_result *result);
+
+/* Requests waiting for admission and requests running. */
+int wv_engine_pending(wv_engine *engine, int *queued, int *active);
+
+/* Finish every queued and running request, then release the engine. */
+int wv_engine_destroy(wv_engine *engine);
 
 /* ------------------------------------------------------------------ schedule (host) */
 

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libwv.so")
 
 WV_OK, WV_EINVAL, WV_ECFL, WV_EBUDGET, WV_EARENA, WV_ENOMEM, WV_EHIP, WV_EUNSTABLE, WV_ENOTIMPL, WV_ECAP = (
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
+WV_ETIMEOUT = -10
 OP_FORWARD, OP_GRADIENT = 0, 1
 ADVANCE, STORE, RESTORE, FREE, REVERSE = 1, 2, 3, 4, 5
 
@@ -56,11 +57,17 @@ class WvStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class WvResult(C.Structure):
+    _fields_ = [("status", C.c_int), ("misfit", C.c_double), ("t_submit_ms", C.c_double),
+                ("t_start_ms", C.c_double), ("t_end_ms", C.c_double), ("stats", WvStats)]
+
+
 # every symbol include/wv.h declares
 SYMBOLS = ["wv_cfl_dt", "wv_workspace_bytes", "wv_forward", "wv_gradient", "wv_misfit_gradient", "wv_adjoint_src",
            "wv_pad_velocity", "wv_velocity_gradient", "wv_zfpk_workspace_bytes", "wv_zfpk_max_bytes",
            "wv_zfpk_encode", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_strerror",
-           "wv_last_error", "wv_version"]
+           "wv_last_error", "wv_version", "wv_engine_create", "wv_engine_submit", "wv_engine_wait",
+           "wv_engine_pending", "wv_engine_destroy"]
 
 _lib = None
 
@@ -100,6 +107,11 @@ def lib():
         L.wv_strerror.restype = C.c_char_p
         L.wv_version.restype = C.c_char_p
         L.wv_last_error.restype = C.c_char_p
+        L.wv_engine_create.argtypes = [vp, sz, C.c_int, C.POINTER(C.c_void_p)]
+        L.wv_engine_submit.argtypes = [vp, mp, gp, vp, sz, C.c_double, C.c_double, vp, vp]
+        L.wv_engine_wait.argtypes = [vp, C.c_int, C.c_double, C.POINTER(WvResult)]
+        L.wv_engine_pending.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.wv_engine_destroy.argtypes = [vp]
         for name in SYMBOLS:
             getattr(L, name)
         _lib = L

@@ -561,6 +561,7 @@ const char *wv_strerror(int code)
     case WV_EUNSTABLE: return "non-finite wavefield";
     case WV_ENOTIMPL: return "not implemented";
     case WV_ECAP: return "output buffer too small";
+    case WV_ETIMEOUT: return "request not finished";
     default: return "unknown error";
     }
 }

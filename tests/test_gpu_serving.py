@@ -1,0 +1,72 @@
+"""Serving engine: continuous batching; every result equals the same request alone."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.helpers import has_gpu
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not has_gpu(), reason="needs a GPU")]
+
+
+def device_requests(nreq=8, seed=5):
+    import torch
+    import paper_1810_05268_amd as P
+    from paper_1810_05268_amd.shot import DeviceShot
+    classes = [(0.5, 2, (120, 100), 8, 300), (0.3, 3, (36, 32, 30), 8, 160), (0.2, 3, (40, 36, 44), 12, 200)]
+    reqs = W.serving_stream(nreq=nreq, rate=50.0, seed=seed, classes=classes)
+    out = []
+    for r in reqs:
+        s = r.shot
+        dt = s.cfl_frac * P.cfl_dt(s.ndim, s.h, s.order, s.vmax)
+        q = W.ricker(s.f0, dt, s.nt).astype(np.float32)
+        G = DeviceShot(s.ndim, s.n, s.h, s.nbl, s.order, s.nt, dt, s.vmax, s.padded("true"), q, s.src, s.rec)
+        d_obs = G.forward()
+        G.set_velocity(s.padded("vel"))
+        budget = 8 * G.P * max(4, s.nt // 10)
+        tol = 1e-4 if r.rid % 2 else 0.0
+        out.append((r.arrival, G, d_obs, budget, tol, 0.0))
+    torch.cuda.synchronize()
+    return out
+
+
+def test_alone_equals_mix():
+    import torch
+    from paper_1810_05268_amd.serving import Engine, replay
+    items = device_requests()
+    alone = []
+    for arrival, G, d_obs, budget, tol, hint in items:
+        phi, g, st = G.misfit_gradient(d_obs, budget, tol, hint)
+        alone.append((phi, g.clone()))
+    eng = Engine(pool_bytes=sum(G.pb.workspace_bytes(1, b) + 4096 for _, G, _, b, _, _ in items), max_active=4)
+    res, wall = replay(eng, items, time_scale=1.0)
+    eng.close()
+    for (phi, g), r in zip(alone, res):
+        assert r["status"] == 0
+        assert r["misfit"] == phi
+        assert torch.equal(r["grad"], g)
+        assert r["t_start_ms"] >= r["t_submit_ms"] and r["t_end_ms"] > r["t_start_ms"]
+
+
+def test_admission_under_a_tight_pool():
+    """A pool that holds one workspace at a time still serves every request, in order."""
+    from paper_1810_05268_amd.serving import Engine
+    items = device_requests(nreq=4, seed=7)
+    need = max(G.pb.workspace_bytes(1, b) for _, G, _, b, _, _ in items)
+    eng = Engine(pool_bytes=need + 4096, max_active=4)
+    ids = [eng.submit(G, d, b, t, h) for _, G, d, b, t, h in items]
+    res = [eng.wait(i) for i in ids]
+    eng.close()
+    assert all(r["status"] == 0 for r in res)
+    for a, b in zip(res, res[1:]):
+        assert b["t_start_ms"] >= a["t_start_ms"]     # first come, first served
+
+
+def test_request_larger_than_pool_is_rejected():
+    import paper_1810_05268_amd as P
+    from paper_1810_05268_amd.serving import Engine
+    items = device_requests(nreq=1, seed=9)
+    _, G, d, b, t, h = items[0]
+    eng = Engine(pool_bytes=1 << 20, max_active=1)
+    with pytest.raises(P.WvError):
+        eng.submit(G, d, b, t, h)
+    eng.close()

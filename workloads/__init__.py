@@ -148,14 +148,15 @@ def layered_noise_3d(n=(128, 128, 128), h=(10.0, 10.0, 10.0), nbl=20, nt=1000, o
 def smooth_random_2d(n=(400, 400), h=(5.0, 5.0), nbl=20, nt=2000, order=8, seed=3, f0=20.0) -> Shot:
     """2-D smooth random medium: N(0,1) noise (seeded) filtered by a Gaussian of sigma
     50 m, mapped affinely onto [1.5, 3.0] km/s; Ricker 20 Hz, one receiver per surface
-    grid point; d_obs model adds +0.2 km/s, sigma 10 cells, at the centre."""
+    grid point; d_obs model adds +0.2 km/s, sigma 10 cells, centred laterally at a
+    quarter of the depth (its reflection returns well within the 2000 steps)."""
     from scipy.ndimage import gaussian_filter
     rng = np.random.default_rng(seed)
     noise = rng.standard_normal((n[1], n[0]))
     s = gaussian_filter(noise, sigma=50.0 / h[0], mode="reflect")
     s = (s - s.min()) / (s.max() - s.min())
     vel = 1500.0 + 1500.0 * s
-    centre = [(n[d] - 1) * h[d] / 2.0 for d in range(2)]
+    centre = [(n[0] - 1) * h[0] / 2.0, (n[1] - 1) * h[1] / 4.0]
     anom = gaussian_anomaly(n, h, 200.0, 10 * h[0], centre)
     src, rec = surface_geometry(n, h)
     return Shot("smooth_random_2d", 2, tuple(n), tuple(h), nbl, order, nt, f0,
