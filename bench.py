@@ -14,6 +14,18 @@ in HBM before timing starts.
 
 Prints one JSON line.  ``value`` = effective Gpt/s of the compressed shot
 gradient (P * 2N stencil updates of the forward + adjoint problem / wall time).
+
+Beside it: the plain (recompute-only) Revolve time at the same memory budget and
+the gradient error between the two; a tolerance sweep; per-kernel device times
+of the stencil launches (HIP events on the call's stream) priced at the
+algorithmic bytes per point (forward 16 B, adjoint + gradient 36 B); the serving
+stream (200 Poisson requests at 2/s of mixed 2-D / 3-D shots through the
+continuous-batching engine: p50/p99 latency from arrival, throughput); and the
+FP64 oracle timed on a bounded sample on the host cores.
+
+``--kernels`` runs only a short kernel workload for hardware-counter passes
+(a 1 GiB copy for calibration, then 12 forward and 12 adjoint steps of the
+large grid).
 """
 from __future__ import annotations
 
@@ -30,8 +42,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FWD_BYTES_PER_POINT = 20.0     # read u^n, d^n, w; write u^{n+1}, d^{n+1}
-ADJ_BYTES_PER_POINT = 40.0     # read lam^k, mu, w, u^k, G(8); write lam^{k-1}, mu, G(8)
+# algorithmic bytes per point and step (what the method must move):
+FWD_BYTES_PER_POINT = 16.0     # read u^n, u^{n-1}, w; write u^{n+1}
+ADJ_BYTES_PER_POINT = 36.0     # read lam^k, lam^{k+1}, w, u^k; write lam^{k-1}; read + write the FP64 gradient
+COUNTERS = os.path.join(ROOT, "profiles", "stencil3d_fault_body_3d_counters.txt")
+STENCIL_SRC = os.path.join(ROOT, "paper_1810_05268_amd", "csrc", "wv_stencil.hip")
 
 
 def log(*a):
@@ -47,6 +62,134 @@ def make_shot(args):
     if args.workload == "layered_noise_3d":
         return W.layered_noise_3d()
     raise SystemExit(f"unknown workload {args.workload}")
+
+
+def plan_hint(st, points):
+    """Planning ratio for the next call of the same shot and tolerance: the uncompressed
+    bytes of the slots the previous call held at its peak over the arena bytes they
+    took, with a 15 % margin.  The peak is what the budget must hold; it is made of
+    states from the whole time range, most of them more compressible than the final
+    state the first call planned with.  If it still overflows, the library re-plans."""
+    S = 8.0 * points
+    if st["peak_bytes"] <= 0 or st["slots"] < 2:
+        return 0.95 * st["ratio_planned"]
+    return max(1.0, 0.85 * S * (st["slots"] - 1) / st["peak_bytes"])
+
+
+def traffic_per_launch():
+    """HBM bytes per launch of the forward and adjoint stencils from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each
+    scaled by what the counter reads for a plain copy of known size), or None when
+    the stencil source has changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    for line in open(COUNTERS):
+        if ":" in line and not line.lstrip().startswith(("#", "|", "`")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    with open(STENCIL_SRC, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if kv.get("stencil_source_sha256") != sha:
+        return None
+    ff, wf = float(kv["fetch_scale"]), float(kv["write_scale"])
+    out = {}
+    for k in ("forward", "adjoint"):
+        out[k] = 1024.0 * (ff * float(kv[f"{k}_fetch_kib"]) + wf * float(kv[f"{k}_write_kib"]))
+    return out
+
+
+def kernels_mode():
+    """Short workload for counter passes: 1 GiB copy (calibration), 12 forward steps,
+    12 adjoint steps of the large grid."""
+    import numpy as np
+    import torch
+
+    import paper_1810_05268_amd as P
+    import workloads as W
+    from paper_1810_05268_amd.shot import DeviceShot
+    n = 256 * 1024 * 1024
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 2.0, out=b)
+    torch.cuda.synchronize()
+    del a, b
+    nt = 12
+    shot = W.fault_body_3d(nt=nt)
+    dt = shot.cfl_frac * P.cfl_dt(shot.ndim, shot.h, shot.order, shot.vmax)
+    q = W.ricker(shot.f0, dt, nt).astype(np.float32)
+    G = DeviceShot(3, shot.n, shot.h, shot.nbl, shot.order, nt, dt, shot.vmax, shot.padded("vel"), q,
+                   shot.src, shot.rec)
+    G.forward()
+    res = torch.randn(nt + 1, len(shot.rec), device="cuda") * 1e-3
+    g, st = G.gradient(res, 8 * G.P * (nt + 2), timing=3)
+    torch.cuda.synchronize()
+    print(json.dumps({"kernels": "copy 1 GiB x3, forward x12 (+12 in the gradient call), adjoint x12",
+                      "fwd_ms": st["ms_fwd_kernel"] / st["advances"], "adj_ms": st["ms_adj_kernel"] / st["reverses"],
+                      "points": G.P}), flush=True)
+
+
+def serving_leg(nreq, rate, pool_bytes, max_active, tol, cap):
+    """The serving stream: seeded Poisson arrivals of mixed shots through the engine.
+    Per request: checkpoint budget = 1.2 x the compressed full trajectory at the class's
+    planned ratio, capped; the planned ratio (the final state's, measured once per class
+    in an untimed call, as an optimisation loop would carry it over) is passed as the hint."""
+    import numpy as np
+    import torch
+
+    import paper_1810_05268_amd as P
+    import workloads as W
+    from paper_1810_05268_amd.serving import Engine, replay
+    from paper_1810_05268_amd.shot import DeviceShot
+    reqs = W.serving_stream(nreq=nreq, rate=rate, seed=5)
+    items, hints, cls = [], {}, []
+    for i, r in enumerate(reqs):
+        s = r.shot
+        dt = s.cfl_frac * P.cfl_dt(s.ndim, s.h, s.order, s.vmax)
+        q = W.ricker(s.f0, dt, s.nt).astype(np.float32)
+        G = DeviceShot(s.ndim, s.n, s.h, s.nbl, s.order, s.nt, dt, s.vmax, s.padded("true"), q, s.src, s.rec)
+        d_obs = G.forward()
+        G.set_velocity(s.padded("vel"))
+        c = s.extra["class"]
+        full = 8 * G.P * (s.nt + 1)
+        if c not in hints:
+            _, _, st = G.misfit_gradient(d_obs, min(full, cap), tol)
+            hints[c] = 0.95 * st["ratio_planned"]
+            G._ws = None
+            torch.cuda.empty_cache()
+        budget = int(min(cap, 1.2 * full / hints[c]))
+        items.append((r.arrival, G, d_obs, budget, tol, hints[c]))
+        cls.append(c)
+        if (i + 1) % 50 == 0:
+            log(f"serving set-up: {i + 1}/{nreq} requests prepared")
+    torch.cuda.synchronize()
+    eng = Engine(pool_bytes=pool_bytes, max_active=max_active)
+    log(f"serving: replaying {nreq} requests at {rate}/s ...")
+    res, wall = replay(eng, items, time_scale=1.0)
+    eng.close()
+    bad = [r["status"] for r in res if r["status"] != 0]
+    for r, (arr, G, _, b, _, h) in zip(res, items):
+        if r["status"] != 0 or r["stats"]["retries"]:
+            log(f"serving: request at {arr:.2f} s (shape {G.shape}, budget {b:.3g}, hint {h:.1f}) status "
+                f"{r['status']} retries {r['stats']['retries']}")
+    lat = sorted(r["latency_ms"] for r in res)
+    pts = sum(G.P * 2 * G.nt for _, G, _, _, _, _ in items)
+
+    def pct(v, p):
+        return v[min(len(v) - 1, max(0, math.ceil(p * len(v)) - 1))]
+    per_class = {}
+    for c in sorted(set(cls)):
+        lc = sorted(r["latency_ms"] for r, k in zip(res, cls) if k == c)
+        per_class[str(c)] = {"n": len(lc), "p50_ms": pct(lc, 0.5), "p99_ms": pct(lc, 0.99)}
+    return {"requests": nreq, "rate_per_s": rate, "failed": len(bad), "wall_s": wall,
+            "retried": sum(1 for r in res if r["stats"]["retries"]),
+            "p50_ms": pct(lat, 0.5), "p99_ms": pct(lat, 0.99), "req_per_s": nreq / wall,
+            "gpts": pts / wall / 1e9, "per_class": per_class, "pool_bytes": pool_bytes, "max_active": max_active,
+            "tol": tol, "ratio_hints": hints,
+            "classes": "0: 2-D 512^2 order 8 1500 steps; 1: 3-D 160^3 order 8 1200 steps; "
+                       "2: 3-D 256^3 order 12 2000 steps (interior; 20-cell layer; h = 10 m)"}
 
 
 def cpu_baseline(shot, counts, tol):
@@ -111,10 +254,18 @@ def main():
     ap.add_argument("--budget", type=float, default=16e9, help="checkpoint memory, bytes")
     ap.add_argument("--quick", action="store_true", help="small grid for a fast functional run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=200, help="0 = skip the serving stream")
+    ap.add_argument("--serving-rate", type=float, default=2.0)
+    ap.add_argument("--serving-pool", type=float, default=200e9)
+    ap.add_argument("--serving-active", type=int, default=8)
+    ap.add_argument("--kernels", action="store_true", help="short kernel workload for counter passes only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of it"}))
         sys.exit(2)
+    if args.kernels:
+        kernels_mode()
+        return
 
     import numpy as np
     import torch
@@ -141,11 +292,11 @@ def main():
     g_comp = torch.empty(G.shape, dtype=torch.float64, device="cuda")
 
     def timed(tol, hint, out, n):
-        walls, stats = [], []
+        walls, stats, phi = [], [], None
         for _ in range(n):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            phi, _, st = G.misfit_gradient(d_obs, budget, tol, hint, timing=True, out=out)
+            phi, _, st = G.misfit_gradient(d_obs, budget, tol, hint, timing=3, out=out)
             torch.cuda.synchronize()
             walls.append(time.perf_counter() - t0)
             stats.append(st)
@@ -157,11 +308,12 @@ def main():
     w_plain, st_plain, phi_plain = timed(0.0, 0.0, g_plain, args.steps)
     log(f"plain: {statistics.mean(w_plain):.3f} s  M={st_plain[0]['slots']} advances={st_plain[0]['advances']}")
 
-    # compressed: the first (warm-up) call measures the ratio on the final state; later
-    # calls reuse it as the hint, as an optimisation loop would from one iteration to the next
+    # compressed: the first (warm-up) call plans with the ratio of the final state; later
+    # calls plan with what it measured, as an optimisation loop would carry it from one
+    # iteration to the next
     log("compressed ...")
     _, st0, _ = timed(args.tol, 0.0, g_comp, max(1, args.warmup))
-    hint = 0.95 * st0[-1]["ratio_planned"]
+    hint = plan_hint(st0[-1], Pn)
     w_comp, st_comp, phi_comp = timed(args.tol, hint, g_comp, args.steps)
     err = float(torch.linalg.vector_norm(g_comp - g_plain) / torch.linalg.vector_norm(g_plain))
     log(f"compressed tol {args.tol}: {statistics.mean(w_comp):.3f} s  M={st_comp[0]['slots']} "
@@ -170,7 +322,7 @@ def main():
     sweep = []
     for tol in [float(t) for t in args.sweep.split(",") if t.strip()]:
         _, sp0, _ = timed(tol, 0.0, g_comp, 1)
-        ws_, ss_, _ = timed(tol, 0.95 * sp0[-1]["ratio_planned"], g_comp, 1)
+        ws_, ss_, _ = timed(tol, plan_hint(sp0[-1], Pn), g_comp, 1)
         e = float(torch.linalg.vector_norm(g_comp - g_plain) / torch.linalg.vector_norm(g_plain))
         sweep.append({"tol": tol, "shot_s": ws_[0], "slots": ss_[0]["slots"], "ratio": ss_[0]["ratio"],
                       "advances": ss_[0]["advances"], "grad_rel_err_vs_plain": e,
@@ -180,24 +332,29 @@ def main():
     # per-phase device times over the timed compressed steps (HIP events on the call's stream)
     adv = sum(s["advances"] for s in st_comp)
     rev = sum(s["reverses"] for s in st_comp)
-    ms_f = sum(s["ms_forward"] for s in st_comp)
-    ms_a = sum(s["ms_adjoint"] for s in st_comp)
+    ms_f = sum(s["ms_fwd_kernel"] for s in st_comp)
+    ms_a = sum(s["ms_adj_kernel"] for s in st_comp)
     fwd_ms = ms_f / adv
     adj_ms = ms_a / rev
     fwd_gbs = FWD_BYTES_PER_POINT * Pn / (fwd_ms * 1e-3) / 1e9
     adj_gbs = ADJ_BYTES_PER_POINT * Pn / (adj_ms * 1e-3) / 1e9
     dom = "adjoint" if ms_a >= ms_f else "forward"
     ach = adj_gbs if dom == "adjoint" else fwd_gbs
+    tr = traffic_per_launch()
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": (tr[dom] if tr else None),
+            "traffic_note": ("HBM bytes per launch from FETCH_SIZE/WRITE_SIZE, copy-calibrated"
+                             if tr else "counters absent or taken on a different stencil source"),
             "kernel": "stencil3d adjoint+gradient step" if dom == "adjoint" else "stencil3d forward step",
             "bytes_per_launch": (ADJ_BYTES_PER_POINT if dom == "adjoint" else FWD_BYTES_PER_POINT) * Pn,
             "avg_launch_ms": adj_ms if dom == "adjoint" else fwd_ms,
-            "forward_step": {"avg_ms": fwd_ms, "GBs": round(fwd_gbs, 1), "frac": round(fwd_gbs / HBM_PEAK_GBS, 4)},
-            "adjoint_step": {"avg_ms": adj_ms, "GBs": round(adj_gbs, 1), "frac": round(adj_gbs / HBM_PEAK_GBS, 4)}}
+            "forward_step": {"avg_ms": fwd_ms, "GBs": round(fwd_gbs, 1), "frac": round(fwd_gbs / HBM_PEAK_GBS, 4),
+                             "traffic": tr["forward"] if tr else None},
+            "adjoint_step": {"avg_ms": adj_ms, "GBs": round(adj_gbs, 1), "frac": round(adj_gbs / HBM_PEAK_GBS, 4),
+                             "traffic": tr["adjoint"] if tr else None}}
     st = st_comp[0]
-    enc_gbs = 8.0 * Pn * st["stores"] / (st["ms_store"] * 1e-3) / 1e9 if st["ms_store"] > 0 else None
-    dec_gbs = 8.0 * Pn * st["decodes"] / (st["ms_restore"] * 1e-3) / 1e9 if st["ms_restore"] > 0 else None
+    ms_per_store = st["ms_store"] / st["stores"] if st["stores"] else None
+    ms_per_decode = st["ms_restore"] / st["decodes"] if st["decodes"] else None
 
     ms_step = 1e3 * statistics.mean(w_comp)
     value = Pn * 2 * shot.nt / (ms_step * 1e-3) / 1e9
@@ -216,15 +373,27 @@ def main():
         "plain_gpts": round(Pn * 2 * shot.nt / statistics.mean(w_plain) / 1e9, 3),
         "latency_ms": {"p50": lat[len(lat) // 2], "p99": lat[min(len(lat) - 1, math.ceil(0.99 * len(lat)) - 1)]},
         "schedule": {"compressed": {k: st[k] for k in ("slots", "advances", "stores", "restores", "decodes",
-                                                         "ratio")},
+                                                         "ratio", "ratio_planned", "peak_bytes", "retries")},
                      "plain": {k: st_plain[0][k] for k in ("slots", "advances", "stores", "restores")}},
         "phase_ms": {"compressed": {k: st[k] for k in ("ms_forward", "ms_adjoint", "ms_store", "ms_restore")},
                      "plain": {k: st_plain[0][k] for k in ("ms_forward", "ms_adjoint", "ms_store", "ms_restore")}},
-        "codec_GBs_uncompressed": {"encode": enc_gbs, "decode": dec_gbs},
+        "codec": {"ms_per_store": ms_per_store, "ms_per_field_decode": ms_per_decode,
+                  "fields_per_store": (st["bytes_stored"] * st["ratio"]) / (4.0 * Pn * st["stores"])
+                  if st["stores"] else None},
         "misfit": {"compressed": phi_comp, "plain": phi_plain},
         "sweep": sweep,
         "roofline": roof,
     }
+    if args.serving_requests > 0 and not args.quick:
+        del G, g_plain, g_comp, d_obs
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        out["serving"] = serving_leg(args.serving_requests, args.serving_rate, int(args.serving_pool),
+                                     args.serving_active, 1e-4, int(16e9))
+        out["latency_ms"] = {"p50": out["serving"]["p50_ms"], "p99": out["serving"]["p99_ms"],
+                             "of": "serving stream, from arrival to completion"}
+        log(f"serving: p50 {out['serving']['p50_ms']:.1f} ms p99 {out['serving']['p99_ms']:.1f} ms "
+            f"{out['serving']['req_per_s']:.2f} req/s failed {out['serving']['failed']}")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample) ...")
         out["cpu_baseline"] = cpu_baseline(shot, {"advances": st["advances"], "reverses": st["reverses"],

@@ -56,7 +56,8 @@ extern "C" {
 #define WV_EINVAL (-1)     /* bad argument, dims, geometry, non-finite or out-of-range velocity */
 #define WV_ECFL (-2)       /* dt above the stability limit wv_cfl_dt */
 #define WV_EBUDGET (-3)    /* mem_budget below one checkpoint */
-#define WV_EARENA (-4)     /* compressed checkpoints overflowed mem_budget (ratio estimate too optimistic) */
+#define WV_EARENA (-4)     /* compressed checkpoints overflowed mem_budget even after the retries (the gradient
+                              calls re-plan with half the ratio, up to three times, the last time uncompressed-sized) */
 #define WV_ENOMEM (-5)     /* workspace too small */
 #define WV_EHIP (-6)       /* a HIP runtime call failed */
 #define WV_EUNSTABLE (-7)  /* non-finite wavefield detected */
@@ -85,16 +86,20 @@ typedef struct {
 } wv_geom;
 
 typedef struct {
-    int timing;          /* input: non-zero = time every schedule action with HIP events */
+    int timing;          /* input: bit 0 = time every schedule action with HIP events;
+                            bit 1 = also time every stencil launch on its own */
     long advances;       /* forward steps executed (first sweep + recomputation) */
-    long stores;         /* checkpoints written */
+    long stores;         /* checkpoints written (u^{k-1} is written only for checkpoints the schedule
+                            later advances from; a reverse step needs only u^k) */
     long restores;       /* restore actions (a restore reads the checkpoint in place: no copy) */
-    long decodes;        /* restores that decoded a compressed checkpoint (the last one stays decoded) */
+    long decodes;        /* fields decoded from compressed checkpoints (u^k at a restore unless it is still
+                            decoded; u^{k-1} only when the schedule advances from the restore) */
     long reverses;       /* adjoint steps */
     long slots;          /* M: checkpoint slots of the schedule (x_0 included) */
     double bytes_stored; /* sum of bytes written to checkpoint memory */
     double peak_bytes;   /* peak checkpoint memory in use */
-    double ratio;        /* achieved compression ratio (uncompressed bytes / stored bytes), 1 if tol = 0 */
+    double ratio;        /* achieved compression ratio (binary32 bytes of the fields written / bytes stored),
+                            1 if tol = 0 */
     double ratio_planned;/* ratio the slot count M was planned with */
     double misfit;       /* phi (wv_misfit_gradient only) */
     double ms_total;     /* device time of the call, ms (HIP events) */
@@ -102,6 +107,9 @@ typedef struct {
     double ms_adjoint;   /* with timing: device ms in adjoint steps (stencil + gradient + residual injection) */
     double ms_store;     /* with timing: device ms writing checkpoints (copies or encodes) */
     double ms_restore;   /* with timing: device ms restoring checkpoints (decodes; uncompressed restores are free) */
+    double ms_fwd_kernel;/* with timing bit 1: device ms inside the forward stencil launches (one per advance) */
+    double ms_adj_kernel;/* with timing bit 1: device ms inside the adjoint+gradient stencil launches (one per reverse) */
+    long retries;        /* compressed runs repeated because checkpoints outgrew mem_budget (see WV_EARENA) */
 } wv_stats;
 
 /* ------------------------------------------------------------------ queries */
@@ -135,15 +143,18 @@ int wv_forward(const wv_model *model, const wv_geom *geom, float *data, float *s
  *   residual    device [nt+1][nrec] float (row 0 unused)
  *   mem_budget  bytes available for checkpoints (SI bytes); the slot count is
  *               M = min(nt, 1 + floor(mem_budget / (S / F))), S = 8 P bytes per
- *               uncompressed checkpoint (u^k and its increment u^k - u^{k-1}),
+ *               uncompressed checkpoint (u^k and u^{k-1}; compressed, the pair is
+ *               stored as u^k and the increment u^k - u^{k-1}),
  *               F = 1 if tol == 0, else ratio_hint if > 0, else the ratio measured
  *               on the final state of a probe forward run (the paper uses the
  *               last time step as the worst-case compressibility);
  *   tol         0: checkpoints are exact copies; > 0: absolute error bound of the codec
  *   grad_m      device [P] double, overwritten (layer cells included)
  *   stats       host, may be NULL
- * Returns WV_EARENA if the compressed checkpoints did not fit (retry with a smaller
- * ratio_hint); the gradient is then invalid.  Synchronises the stream at the end. */
+ * If the compressed checkpoints outgrow mem_budget, the call re-plans with half the
+ * ratio and runs again (at most three times; the last plan uses the uncompressed
+ * size, which always fits) and reports the repeats in stats->retries.  WV_EARENA is
+ * returned only if that still fails.  Synchronises the stream at the end. */
 int wv_gradient(const wv_model *model, const wv_geom *geom, const float *residual, size_t mem_budget,
                 double tol, double ratio_hint, double *grad_m, wv_stats *stats,
                 void *ws, size_t ws_bytes, void *stream);

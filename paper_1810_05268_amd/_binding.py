@@ -51,7 +51,8 @@ class WvStats(C.Structure):
                 ("decodes", C.c_long), ("reverses", C.c_long), ("slots", C.c_long), ("bytes_stored", C.c_double),
                 ("peak_bytes", C.c_double), ("ratio", C.c_double), ("ratio_planned", C.c_double),
                 ("misfit", C.c_double), ("ms_total", C.c_double), ("ms_forward", C.c_double),
-                ("ms_adjoint", C.c_double), ("ms_store", C.c_double), ("ms_restore", C.c_double)]
+                ("ms_adjoint", C.c_double), ("ms_store", C.c_double), ("ms_restore", C.c_double),
+                ("ms_fwd_kernel", C.c_double), ("ms_adj_kernel", C.c_double), ("retries", C.c_long)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -228,7 +229,7 @@ def forward(pb: Problem, data, ws, state_out=None, stream=None) -> None:
 def gradient(pb: Problem, residual, mem_budget: int, tol: float, grad, ws, ratio_hint: float = 0.0,
              stream=None, timing: bool = False) -> dict:
     st = WvStats()
-    st.timing = 1 if timing else 0
+    st.timing = int(timing)
     _check(lib().wv_gradient(C.byref(pb.model), C.byref(pb.geom), _ptr(residual), int(mem_budget), float(tol),
                              float(ratio_hint), _ptr(grad), C.byref(st), _ptr(ws), ws.numel() * ws.element_size(),
                              _stream(stream)), "wv_gradient")
@@ -238,7 +239,7 @@ def gradient(pb: Problem, residual, mem_budget: int, tol: float, grad, ws, ratio
 def misfit_gradient(pb: Problem, d_obs, mem_budget: int, tol: float, grad, ws, ratio_hint: float = 0.0,
                     d_sim=None, stream=None, timing: bool = False) -> tuple[float, dict]:
     st = WvStats()
-    st.timing = 1 if timing else 0
+    st.timing = int(timing)
     phi = C.c_double(0.0)
     _check(lib().wv_misfit_gradient(C.byref(pb.model), C.byref(pb.geom), _ptr(d_obs), int(mem_budget), float(tol),
                                     float(ratio_hint), C.byref(phi), _ptr(grad), _ptr(d_sim), C.byref(st), _ptr(ws),

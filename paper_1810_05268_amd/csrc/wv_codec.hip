@@ -218,6 +218,7 @@ struct BitReader {
 
 struct EncArgs {
     const float *field;
+    const float *sub;        // nullable: encode field - sub
     int dims[3];
     int nb[3];
     long long nblocks, nchunks, prefix_bytes;
@@ -230,6 +231,7 @@ struct EncArgs {
     uint64_t *next;
     uint64_t *flags;
     uint32_t epoch;
+    unsigned *ticket;        // chunk order = start order (0 at launch, reset by the last taker)
     unsigned *err;
     unsigned long long *stats;
 };
@@ -246,7 +248,7 @@ __device__ __forceinline__ uint64_t make_flag(uint64_t status, uint32_t epoch, u
 // VEC (dims[0] % 4 == 0) every block is complete along x and each row is one
 // float4 load with no branch, so all 16 row loads of a lane are in flight together.
 template <int ND, bool VEC>
-__device__ __forceinline__ void load_block(const float *f, const int *dims, int bx, int by, int bz, float *v)
+__device__ __forceinline__ void load_raw(const float *f, const int *dims, int bx, int by, int bz, float *v)
 {
     constexpr int KZ = ND == 3 ? 4 : 1;
     const int ny = dims[1];
@@ -272,6 +274,21 @@ __device__ __forceinline__ void load_block(const float *f, const int *dims, int 
     }
 }
 
+// The block of f, or of f - sub (one binary32 subtraction per value) when sub is set.
+template <int ND, bool VEC>
+__device__ __forceinline__ void load_block(const float *f, const float *sub, const int *dims, int bx, int by, int bz,
+                                           float *v)
+{
+    constexpr int S = ND == 3 ? 64 : 16;
+    load_raw<ND, VEC>(f, dims, bx, by, bz, v);
+    if (sub) {
+        float t[S];
+        load_raw<ND, VEC>(sub, dims, bx, by, bz, t);
+#pragma unroll
+        for (int i = 0; i < S; ++i) v[i] -= t[i];
+    }
+}
+
 constexpr int kLdsWords = 1024;   // chunk bitstreams up to 8 KB are assembled in LDS
 
 template <int ND, bool VEC>
@@ -282,9 +299,18 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
     __shared__ unsigned long long s_excl;
     __shared__ unsigned long long s_bits[kLdsWords];
     const int tid = threadIdx.x;
-    // Chunk c = workgroup c.  Workgroups are dispatched in index order on each XCD, so
-    // every chunk a look-back waits for is running or finished; the wait is bounded.
-    const long long c = blockIdx.x;
+    // Chunk index = the order in which workgroups start (an atomic ticket), so every
+    // chunk a look-back waits for belongs to a workgroup that is already running or
+    // finished, whatever else the device runs concurrently; the wait always ends.  The
+    // workgroup taking the last ticket resets the word for the next launch.
+    __shared__ unsigned s_chunk;
+    if (tid == 0) {
+        const unsigned t = atomicAdd(A.ticket, 1u);
+        if (t == (unsigned)(A.nchunks - 1)) atomicExch(A.ticket, 0u);
+        s_chunk = t;
+    }
+    __syncthreads();
+    const long long c = s_chunk;
     const long long b = c * kBlocksPerChunk + tid;
     const bool valid = b < A.nblocks;
     const uint64_t base = *A.base;
@@ -297,7 +323,7 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
         bz = (int)(b / ((long long)A.nb[0] * A.nb[1]));
     }
     float v[S];
-    if (valid) load_block<ND, VEC>(A.field, A.dims, bx, by, bz, v);
+    if (valid) load_block<ND, VEC>(A.field, A.sub, A.dims, bx, by, bz, v);
     else {
 #pragma unroll
         for (int i = 0; i < S; ++i) v[i] = 0.0f;
@@ -527,6 +553,7 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
 }
 
 struct DecArgs {
+    const float *sub;        // nullable: store sub - decoded
     const uint8_t *in;
     const uint64_t *base;
     uint64_t cap;        // bytes readable from `in`
@@ -557,8 +584,10 @@ __global__ __launch_bounds__(256) void decode_kernel(DecArgs A)
                 for (int j = 0; j < 4; ++j)
                     for (int i = 0; i < 4; ++i) {
                         const int x = 4 * bx + i, y = 4 * by + j, z = 4 * bz + k;
-                        if (x < A.dims[0] && y < A.dims[1] && z < nzz)
-                            A.field[((long long)z * A.dims[1] + y) * A.dims[0] + x] = 0.0f;
+                        if (x < A.dims[0] && y < A.dims[1] && z < nzz) {
+                            const long long p = ((long long)z * A.dims[1] + y) * A.dims[0] + x;
+                            A.field[p] = A.sub ? A.sub[p] : 0.0f;
+                        }
                     }
         }
         return;
@@ -660,15 +689,23 @@ __global__ __launch_bounds__(256) void decode_kernel(DecArgs A)
         for (int j = 0; j < 4; ++j) {
             const int y = 4 * by + j;
             if (y >= A.dims[1] || z >= nzz) continue;
-            float *row = A.field + ((long long)z * A.dims[1] + y) * A.dims[0];
+            const long long r0 = ((long long)z * A.dims[1] + y) * A.dims[0];
+            float *row = A.field + r0;
             if (VEC) {
-                *reinterpret_cast<float4 *>(row + 4 * bx) =
-                    make_float4(out[16 * k + 4 * j + 0], out[16 * k + 4 * j + 1], out[16 * k + 4 * j + 2],
-                                out[16 * k + 4 * j + 3]);
+                float4 o = make_float4(out[16 * k + 4 * j + 0], out[16 * k + 4 * j + 1], out[16 * k + 4 * j + 2],
+                                       out[16 * k + 4 * j + 3]);
+                if (A.sub) {
+                    const float4 b = *reinterpret_cast<const float4 *>(A.sub + r0 + 4 * bx);
+                    o = make_float4(b.x - o.x, b.y - o.y, b.z - o.z, b.w - o.w);
+                }
+                *reinterpret_cast<float4 *>(row + 4 * bx) = o;
             } else {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    if (4 * bx + i < A.dims[0]) row[4 * bx + i] = out[16 * k + 4 * j + i];
+                    if (4 * bx + i < A.dims[0]) {
+                        const float o = out[16 * k + 4 * j + i];
+                        row[4 * bx + i] = A.sub ? A.sub[r0 + 4 * bx + i] - o : o;
+                    }
             }
         }
     }
@@ -699,12 +736,13 @@ size_t codec_max_bytes(const CodecDims &cd)
     return (size_t)(cd.prefix_bytes + 8 * words);
 }
 
-hipError_t launch_encode(const CodecDims &cd, const float *field, double tol, uint8_t *out, uint64_t cap,
-                         const uint64_t *base, uint64_t *next, uint64_t *flags, uint32_t epoch,
-                         unsigned *err, unsigned long long *stats, hipStream_t s)
+hipError_t launch_encode(const CodecDims &cd, const float *field, const float *sub, double tol, uint8_t *out,
+                         uint64_t cap, const uint64_t *base, uint64_t *next, uint64_t *flags, uint32_t epoch,
+                         unsigned *ticket, unsigned *err, unsigned long long *stats, hipStream_t s)
 {
     EncArgs A{};
     A.field = field;
+    A.sub = sub;
     for (int a = 0; a < 3; ++a) {
         A.dims[a] = cd.dims[a];
         A.nb[a] = cd.nb[a];
@@ -723,6 +761,7 @@ hipError_t launch_encode(const CodecDims &cd, const float *field, double tol, ui
     A.next = next;
     A.flags = flags;
     A.epoch = epoch;
+    A.ticket = ticket;
     A.err = err;
     A.stats = stats;
     const bool vec = cd.dims[0] % 4 == 0;
@@ -738,9 +777,10 @@ hipError_t launch_encode(const CodecDims &cd, const float *field, double tol, ui
 }
 
 hipError_t launch_decode(const CodecDims &cd, const uint8_t *in, const uint64_t *base, uint64_t cap, float *field,
-                         hipStream_t s)
+                         const float *sub, hipStream_t s)
 {
     DecArgs A{};
+    A.sub = sub;
     A.in = in;
     A.base = base;
     A.cap = cap;

@@ -181,7 +181,7 @@ int hip_fail(hipError_t e, const char *what, int line)
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    size_t bk, U0, U1, D, L0, L1, MU, W, Z, UB, DB;
+    size_t bk, U0, U1, L0, L1, W, Z, UB, DB;
     size_t src_tab, rec_tab, tab_bytes;
     size_t res, dsim, partials, flags, offs, arena;
     size_t total;
@@ -192,7 +192,7 @@ struct Layout {
 
 constexpr size_t kBk = 4096;
 // bookkeeping words inside bk
-constexpr size_t kErr = 0, kMisfit = 128, kStats = 192, kZero = 256, kProbeNext = 264, kScal = 320;
+constexpr size_t kErr = 0, kMisfit = 128, kStats = 192, kZero = 256, kProbeNext = 264, kScal = 320, kTicket = 384;
 constexpr int kParts = 1024;
 
 struct Setup {
@@ -370,7 +370,6 @@ Layout plan_layout(const wv_model *m, const wv_geom *geo, const Setup &su, int o
     L.bk = take(kBk);
     L.U0 = take(fb);
     L.U1 = take(fb);
-    L.D = take(fb);
     L.W = take(fb);
     L.Z = take(fb);
     L.src_tab = take(tab_bytes(su, false));
@@ -379,7 +378,6 @@ Layout plan_layout(const wv_model *m, const wv_geom *geo, const Setup &su, int o
     if (op == WV_OP_GRADIENT) {
         L.L0 = take(fb);
         L.L1 = take(fb);
-        L.MU = take(fb);
         L.UB = take(fb);
         L.DB = take(fb);
         L.res = take(data_bytes);
@@ -404,7 +402,7 @@ struct Dev {
     uint8_t *base;
     Layout L;
     Sparse src, rec;
-    float *U[2], *D, *Lm[2], *MU, *W, *Z, *UB, *DB;
+    float *U[2], *Lm[2], *W, *Z, *UB, *DB;
     unsigned *err;
     double *misfit;
     unsigned long long *stats;
@@ -460,7 +458,6 @@ int bind(Dev &d, void *ws, size_t ws_bytes, const Layout &L, int op)
     d.L = L;
     d.U[0] = at<float>(d.base, L.U0);
     d.U[1] = at<float>(d.base, L.U1);
-    d.D = at<float>(d.base, L.D);
     d.W = at<float>(d.base, L.W);
     d.Z = at<float>(d.base, L.Z);
     d.err = at<unsigned>(d.base, L.bk + kErr);
@@ -471,7 +468,6 @@ int bind(Dev &d, void *ws, size_t ws_bytes, const Layout &L, int op)
     if (op == WV_OP_GRADIENT) {
         d.Lm[0] = at<float>(d.base, L.L0);
         d.Lm[1] = at<float>(d.base, L.L1);
-        d.MU = at<float>(d.base, L.MU);
         d.UB = at<float>(d.base, L.UB);
         d.DB = at<float>(d.base, L.DB);
         d.res = at<float>(d.base, L.res);
@@ -510,31 +506,95 @@ int start(Dev &d, const wv_model *m, const Setup &su, hipStream_t s)
 // x_0, the checkpoint slot itself (uncompressed) or the decoded base pair
 // (compressed).  The next step reads it there and writes the working buffers, so a
 // restore moves no data.
+// Device timing with one event pair per timed region (a schedule action, or one stencil
+// launch), read after the final sync.
+struct ActionTimer {
+    bool on = false;
+    hipStream_t s = nullptr;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;
+    size_t used = 0;
+    ~ActionTimer()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    int begin(int k)
+    {
+        if (!on) return WV_OK;
+        if (used + 2 > ev.size()) {
+            for (int i = 0; i < 2; ++i) {
+                hipEvent_t e;
+                HIPCHK(hipEventCreate(&e));
+                ev.push_back(e);
+            }
+        }
+        kind.push_back(k);
+        HIPCHK(hipEventRecord(ev[used], s));
+        return WV_OK;
+    }
+    int end()
+    {
+        if (!on) return WV_OK;
+        HIPCHK(hipEventRecord(ev[used + 1], s));
+        used += 2;
+        return WV_OK;
+    }
+    // a fresh event pair of kind k for a launch that records it itself ({} when off)
+    int pair(int k, LaunchEvents *le)
+    {
+        *le = LaunchEvents{};
+        if (!on) return WV_OK;
+        if (used + 2 > ev.size()) {
+            for (int i = 0; i < 2; ++i) {
+                hipEvent_t e;
+                HIPCHK(hipEventCreate(&e));
+                ev.push_back(e);
+            }
+        }
+        kind.push_back(k);
+        le->start = ev[used];
+        le->stop = ev[used + 1];
+        used += 2;
+        return WV_OK;
+    }
+    // after a sync: accumulate per-kind milliseconds (kinds 1..5 = action codes)
+    int totals(double *ms)
+    {
+        for (size_t i = 0; i < used / 2; ++i) {
+            float t = 0.0f;
+            HIPCHK(hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]));
+            ms[kind[i]] += t;
+        }
+        return WV_OK;
+    }
+};
+
+// Forward state x_n = (u^n, u^{n-1}).  The two levels may live anywhere (a
+// checkpoint slot, the zero field, the decoded pair): a step writes the work buffer
+// that does not hold u^n, which is in place over u^{n-1} once both levels are in the
+// work buffers, so restored states are only ever read.
 struct Fwd {
     Dev &d;
     const Setup &su;
     const wv_geom *geo;
     hipStream_t s;
-    const float *u = nullptr, *du = nullptr;   // current u^k, d^k
-    const float *u_prev = nullptr;              // u^{k-1} after a step (the step's input)
-    int cur = 0;
-    bool in_work = false;
-    void at(const float *uu, const float *dd)
+    const float *u = nullptr, *up = nullptr;   // u^n, u^{n-1}
+    ActionTimer *kt = nullptr;                  // optional per-launch timing of the stencil (kind 0)
+    void at(const float *cur, const float *prev)
     {
-        u = uu;
-        du = dd;
-        in_work = false;
+        u = cur;
+        up = prev;
     }
     int step(int n, float *data_row)
     {
-        const int o = in_work ? (cur ^ 1) : cur;
-        HIPCHK(launch_fwd_step(su.g, u, d.U[o], du, d.D, d.W, s));
-        HIPCHK(launch_inject_src(su.g, d.src, geo->wavelet, n, d.W, d.D, d.U[o], s));
-        u_prev = u;
-        cur = o;
-        u = d.U[o];
-        du = d.D;
-        in_work = true;
+        float *out = (u == d.U[0]) ? d.U[1] : d.U[0];
+        int rc;
+        LaunchEvents le;
+        if (kt && (rc = kt->pair(0, &le))) return rc;
+        HIPCHK(launch_fwd_step(su.g, u, up, out, d.W, s, le));
+        HIPCHK(launch_inject_src(su.g, d.src, geo->wavelet, n, d.W, out, s));
+        up = u;
+        u = out;
         if (data_row) HIPCHK(launch_gather(d.rec, u, data_row, s));
         return WV_OK;
     }
@@ -620,7 +680,7 @@ int wv_forward(const wv_model *m, const wv_geom *geo, float *data, float *state_
         if ((rc = f.step(n, data + (size_t)(n + 1) * geo->nrec))) return rc;
     if (state_out) {
         HIPCHK(hipMemcpyAsync(state_out, f.u, (size_t)su.P * 4, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(state_out + su.P, f.u_prev, (size_t)su.P * 4, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(state_out + su.P, f.up, (size_t)su.P * 4, hipMemcpyDeviceToDevice, s));
     }
     HIPCHK(launch_check_finite(f.u, su.P, d.err, s));
     unsigned e = 0;
@@ -649,58 +709,15 @@ struct GradRun {
     CodecDims cd{};
     size_t S = 0;                      // bytes of one uncompressed checkpoint
     uint32_t epoch = 0;
-    long advances = 0, stores = 0, restores = 0, reverses = 0, decodes = 0;
+    long advances = 0, stores = 0, restores = 0, reverses = 0, decodes = 0, fields = 0;
     int max_depth = 0;
 
-    int encode_field(const float *f, uint64_t *base, uint64_t *next)
+    // encodes f (or f - sub) at the device offset *base; *next receives the end
+    int encode_field(const float *f, const float *sub, uint64_t *base, uint64_t *next)
     {
         ++epoch;
-        HIPCHK(launch_encode(cd, f, tol, d.arena, d.L.arena_bytes, base, next, d.flags, epoch, d.err,
-                             d.stats, s));
-        return WV_OK;
-    }
-};
-
-// Per-action device timing: one event pair per schedule action, read after the final sync.
-struct ActionTimer {
-    bool on = false;
-    hipStream_t s = nullptr;
-    std::vector<hipEvent_t> ev;
-    std::vector<int> kind;
-    size_t used = 0;
-    ~ActionTimer()
-    {
-        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-    }
-    int begin(int k)
-    {
-        if (!on) return WV_OK;
-        if (used + 2 > ev.size()) {
-            for (int i = 0; i < 2; ++i) {
-                hipEvent_t e;
-                HIPCHK(hipEventCreate(&e));
-                ev.push_back(e);
-            }
-        }
-        kind.push_back(k);
-        HIPCHK(hipEventRecord(ev[used], s));
-        return WV_OK;
-    }
-    int end()
-    {
-        if (!on) return WV_OK;
-        HIPCHK(hipEventRecord(ev[used + 1], s));
-        used += 2;
-        return WV_OK;
-    }
-    // after a sync: accumulate per-kind milliseconds (kinds 1..5 = action codes)
-    int totals(double *ms)
-    {
-        for (size_t i = 0; i < used / 2; ++i) {
-            float t = 0.0f;
-            HIPCHK(hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]));
-            ms[kind[i]] += t;
-        }
+        HIPCHK(launch_encode(cd, f, sub, tol, d.arena, d.L.arena_bytes, base, next, d.flags, epoch,
+                             at<unsigned>(d.base, d.L.bk + kTicket), d.err, d.stats, s));
         return WV_OK;
     }
 };
@@ -723,7 +740,7 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
     f.at(d.Z, d.Z);
     int hot_slot = -1, hot_k = -1;   // checkpoint currently decoded in the base pair
     HIPCHK(launch_fill_f32(d.Lm[0], P, 0.0f, s));
-    HIPCHK(launch_fill_f32(d.MU, P, 0.0f, s));
+    HIPCHK(launch_fill_f32(d.Lm[1], P, 0.0f, s));
     if (R.G) HIPCHK(launch_fill_f64(R.G, P, 0.0, s));
     HIPCHK(launch_fill_u64(d.offs, d.L.offs_n, 0, s));
     HIPCHK(launch_fill_u64(d.flags, d.L.nchunks_max, 0, s));
@@ -741,14 +758,53 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
     int rc = WV_OK;
     const bool comp = R.tol > 0;
     const size_t fb = (size_t)P * 4;
-    ActionTimer timer;
-    timer.on = stats && stats->timing;
+    const size_t nact = acts.size() / 3;
+    // A reverse step k reads only u^k.  The second level u^{k-1} of a checkpoint is
+    // needed only if the schedule advances from a restore of it; scan the list once and
+    // store (and later decode) that level only for those checkpoints.
+    std::vector<char> need2(nact, 0);
+    {
+        std::vector<long> holder((size_t)M + 2, -1);   // slot -> index of the STORE that filled it
+        for (size_t i = 0; i < nact; ++i) {
+            const int op = acts[3 * i], b = acts[3 * i + 2];
+            if (op == STORE && b >= 0 && b <= M) holder[b] = (long)i;
+            if (op == RESTORE && b > 0 && b <= M && holder[b] >= 0) {
+                size_t j = i + 1;
+                while (j < nact && acts[3 * j] == FREE) ++j;
+                if (j >= nact || acts[3 * j] != REVERSE) need2[holder[b]] = 1;
+            }
+        }
+    }
+    std::vector<char> slot2((size_t)M + 2, 0);   // slot holds both levels
+    bool up_pending = false;                    // restored state: u^{k-1} not decoded yet
+    bool hot_db = false;                        // DB holds u^{k-1} of the hot checkpoint
+    int pend_slot = -1;
+    ActionTimer timer, ktimer;
+    timer.on = stats && (stats->timing & 1);
     timer.s = s;
+    ktimer.on = stats && (stats->timing & 2);
+    ktimer.s = s;
+    if (ktimer.on) f.kt = &ktimer;
     for (size_t i = 0; i < acts.size() / 3 && rc == WV_OK; ++i) {
         const int op = acts[3 * i], a = acts[3 * i + 1], b = acts[3 * i + 2];
         if (op != FREE && (rc = timer.begin(op))) break;
         switch (op) {
         case ADVANCE:
+            if (!f.up) {   // advancing from a restore: the second level is needed now
+                if (!up_pending) {
+                    rc = WV_EINVAL;   // cannot happen: the scan above marks these checkpoints
+                    break;
+                }
+                if (!hot_db) {
+                    // u^{k-1} = u^k - (u^k - u^{k-1})
+                    HIPCHK(launch_decode(R.cd, d.arena, d.offs + 2 * pend_slot + 1, d.L.arena_bytes, d.DB, d.UB,
+                                         s));
+                    hot_db = true;
+                    R.decodes++;
+                }
+                f.up = d.DB;
+                up_pending = false;
+            }
             for (int n = a; n < b; ++n) {
                 float *row = (data && n + 1 > gathered) ? data + (size_t)(n + 1) * R.geo->nrec : nullptr;
                 if ((rc = f.step(n, row))) break;
@@ -757,33 +813,49 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
             R.advances += b - a;
             break;
         case STORE:
+            slot2[b] = need2[i];
+            if (need2[i] && !f.up) {
+                rc = WV_EINVAL;
+                break;
+            }
             if (comp) {
-                if ((rc = R.encode_field(f.u, d.offs + 2 * b, d.offs + 2 * b + 1))) break;
-                if ((rc = R.encode_field(f.du, d.offs + 2 * b + 1, d.offs + 2 * b + 2))) break;
+                // u^k at offs[2b]; with both levels the increment u^k - u^{k-1} follows at
+                // offs[2b+1]; the next slot starts at offs[2b+2]
+                if (need2[i]) {
+                    if ((rc = R.encode_field(f.u, nullptr, d.offs + 2 * b, d.offs + 2 * b + 1))) break;
+                    if ((rc = R.encode_field(f.u, f.up, d.offs + 2 * b + 1, d.offs + 2 * b + 2))) break;
+                } else {
+                    if ((rc = R.encode_field(f.u, nullptr, d.offs + 2 * b, d.offs + 2 * b + 2))) break;
+                }
                 if (hot_slot == b) hot_slot = -1;
             } else {
                 uint8_t *slot = d.arena + (size_t)(b - 1) * R.S;
                 HIPCHK(hipMemcpyAsync(slot, f.u, fb, hipMemcpyDeviceToDevice, s));
-                HIPCHK(hipMemcpyAsync(slot + fb, f.du, fb, hipMemcpyDeviceToDevice, s));
+                if (need2[i]) HIPCHK(hipMemcpyAsync(slot + fb, f.up, fb, hipMemcpyDeviceToDevice, s));
             }
             R.stores++;
+            R.fields += need2[i] ? 2 : 1;
             R.max_depth = std::max(R.max_depth, b);
             break;
         case RESTORE:
+            up_pending = false;
             if (b == 0) {
                 f.at(d.Z, d.Z);
             } else if (comp) {
                 if (hot_slot != b || hot_k != a) {
-                    HIPCHK(launch_decode(R.cd, d.arena, d.offs + 2 * b, d.L.arena_bytes, d.UB, s));
-                    HIPCHK(launch_decode(R.cd, d.arena, d.offs + 2 * b + 1, d.L.arena_bytes, d.DB, s));
+                    HIPCHK(launch_decode(R.cd, d.arena, d.offs + 2 * b, d.L.arena_bytes, d.UB, nullptr, s));
                     hot_slot = b;
                     hot_k = a;
+                    hot_db = false;
                     R.decodes++;
                 }
-                f.at(d.UB, d.DB);
+                // u^{k-1} is decoded by the advance that needs it
+                f.at(d.UB, nullptr);
+                up_pending = slot2[b] != 0;
+                pend_slot = b;
             } else {
                 const float *slot = (const float *)(d.arena + (size_t)(b - 1) * R.S);
-                f.at(slot, slot + P);
+                f.at(slot, slot2[b] ? slot + P : nullptr);
             }
             R.restores++;
             break;
@@ -797,8 +869,11 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
                 residual_ready = true;
             }
             const float *uk = R.G ? f.u : nullptr;
-            HIPCHK(launch_adj_step(R.su.g, d.Lm[lc], d.Lm[lc ^ 1], d.MU, d.W, uk, R.G, gscale, s));
-            HIPCHK(launch_inject_res(R.su.g, d.rec, res + (size_t)a * R.geo->nrec, d.W, d.MU, d.Lm[lc ^ 1], uk, R.G,
+            LaunchEvents le;
+            if ((rc = ktimer.pair(1, &le))) break;
+            // lam^{k-1} overwrites lam^{k+1}
+            HIPCHK(launch_adj_step(R.su.g, d.Lm[lc], d.Lm[lc ^ 1], d.Lm[lc ^ 1], d.W, uk, R.G, gscale, s, le));
+            HIPCHK(launch_inject_res(R.su.g, d.rec, res + (size_t)a * R.geo->nrec, d.W, d.Lm[lc ^ 1], uk, R.G,
                                      gscale, s));
             lc ^= 1;
             if (R.src_adj) HIPCHK(launch_gather_sum(d.src, d.Lm[lc], R.src_adj + (a - 1), s));
@@ -823,8 +898,9 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (misfit_out) *misfit_out = mis;
-    double kind_ms[6] = {0, 0, 0, 0, 0, 0};
+    double kind_ms[6] = {0, 0, 0, 0, 0, 0}, kern_ms[6] = {0, 0, 0, 0, 0, 0};
     if (timer.on && (rc = timer.totals(kind_ms))) return rc;
+    if (ktimer.on && (rc = ktimer.totals(kern_ms))) return rc;
     if (stats) {
         const int timing = stats->timing;
         std::memset(stats, 0, sizeof(*stats));
@@ -833,15 +909,18 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
         stats->ms_adjoint = kind_ms[REVERSE];
         stats->ms_store = kind_ms[STORE];
         stats->ms_restore = kind_ms[RESTORE];
+        stats->ms_fwd_kernel = kern_ms[0];
+        stats->ms_adj_kernel = kern_ms[1];
         stats->advances = R.advances;
         stats->stores = R.stores;
         stats->restores = R.restores;
         stats->decodes = R.decodes;
         stats->reverses = R.reverses;
         stats->slots = M;
-        stats->bytes_stored = comp ? (double)st[0] : (double)R.stores * (double)R.S;
+        const double raw = (double)R.fields * (double)(R.S / 2);   // binary32 fields written
+        stats->bytes_stored = comp ? (double)st[0] : raw;
         stats->peak_bytes = comp ? (double)st[1] : (double)R.max_depth * (double)R.S;
-        stats->ratio = stats->bytes_stored > 0 ? (double)R.stores * (double)R.S / stats->bytes_stored : 1.0;
+        stats->ratio = stats->bytes_stored > 0 ? raw / stats->bytes_stored : 1.0;
         stats->ratio_planned = ratio_planned;
         stats->misfit = mis;
         stats->ms_total = ms;
@@ -870,8 +949,8 @@ int probe_ratio(GradRun &R, double *ratio)
         if (rc) return rc;
     }
     int rc;
-    if ((rc = R.encode_field(f.u, d.offs + 2, d.offs + 3))) return rc;
-    if ((rc = R.encode_field(f.du, d.offs + 3, d.offs + 4))) return rc;
+    if ((rc = R.encode_field(f.u, nullptr, d.offs + 2, d.offs + 3))) return rc;
+    if ((rc = R.encode_field(f.u, f.up, d.offs + 3, d.offs + 4))) return rc;
     unsigned long long st[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(st, d.stats, sizeof(st), hipMemcpyDeviceToHost, s));
     unsigned e = 0;
@@ -886,6 +965,8 @@ int probe_ratio(GradRun &R, double *ratio)
     HIPCHK(launch_fill_u64(at<uint64_t>(d.base, d.L.bk), kBk / 8, 0, s));
     return WV_OK;
 }
+
+constexpr int kArenaRetries = 3;
 
 int gradient_common(const wv_model *m, const wv_geom *geo, const float *residual, const float *dobs,
                     size_t mem_budget, double tol, double ratio_hint, double *misfit, double *grad_m, float *d_sim,
@@ -914,12 +995,25 @@ int gradient_common(const wv_model *m, const wv_geom *geo, const float *residual
         else if ((rc = probe_ratio(R, &F))) return rc;
     }
     const int N = m->nt;
-    size_t slot_bytes = tol > 0 ? (size_t)((double)R.S / F) + 2 * (size_t)(R.cd.prefix_bytes + 256) : R.S;
-    if (slot_bytes < 1) slot_bytes = 1;
-    const size_t nslots = mem_budget / slot_bytes;
-    if (nslots < 1 && N > 1) return WV_EBUDGET;
-    const int M = (int)std::min<size_t>((size_t)N, nslots + 1);
-    return run_gradient(R, std::max(M, 1), F, stats, misfit);
+    // A compressed run whose checkpoints outgrow the budget (the planned ratio was too
+    // optimistic) is repeated with half the planned ratio, i.e. fewer slots; the last
+    // attempt plans with the uncompressed size, which always fits.
+    for (int attempt = 0;; ++attempt) {
+        size_t slot_bytes = tol > 0 ? (size_t)((double)R.S / F) + 2 * (size_t)(R.cd.prefix_bytes + 256) : R.S;
+        if (slot_bytes < 1) slot_bytes = 1;
+        const size_t nslots = mem_budget / slot_bytes;
+        if (nslots < 1 && N > 1) return WV_EBUDGET;
+        const int M = (int)std::min<size_t>((size_t)N, nslots + 1);
+        rc = run_gradient(R, std::max(M, 1), F, stats, misfit);
+        if (rc != WV_EARENA || tol <= 0 || F <= 1.0 || attempt >= kArenaRetries) {
+            if (stats) stats->retries = attempt;
+            return rc;
+        }
+        F = attempt + 1 == kArenaRetries ? 1.0 : std::max(1.0, F / 2);
+        HIPCHK(launch_fill_u64(at<uint64_t>(d.base, d.L.bk), kBk / 8, 0, s));
+        R.advances = R.stores = R.restores = R.reverses = R.decodes = R.fields = 0;
+        R.max_depth = 0;
+    }
 }
 
 }  // namespace
@@ -985,7 +1079,7 @@ int wv_velocity_gradient(int ndim, const int *n, int nbl, const float *vpad, con
 
 // ------------------------------------------------------------------ codec entry points
 namespace {
-constexpr size_t kCodecBk = 512;   // err, base word, next word, stats[2]
+constexpr size_t kCodecBk = 512;   // err, base word, next word, stats[2], chunk ticket
 }
 
 size_t wv_zfpk_workspace_bytes(int ndim, const int *dims)
@@ -1021,7 +1115,8 @@ int wv_zfpk_encode(const float *field, int ndim, const int *dims, double tol, vo
     uint64_t *flags = (uint64_t *)(b + kCodecBk);
     HIPCHK(launch_fill_u64((uint64_t *)b, kCodecBk / 8, 0, s));
     HIPCHK(launch_fill_u64(flags, cd.nchunks, 0, s));
-    HIPCHK(launch_encode(cd, field, tol, (uint8_t *)out, cap, base, next, flags, 1u, err, st, s));
+    HIPCHK(launch_encode(cd, field, nullptr, tol, (uint8_t *)out, cap, base, next, flags, 1u,
+                         (unsigned *)(b + 256), err, st, s));
     unsigned e = 0;
     unsigned long long tot[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, s));
@@ -1041,7 +1136,7 @@ int wv_zfpk_decode(const void *in, int ndim, const int *dims, float *field, void
         if (dims[a] < 1) return WV_EINVAL;
     const CodecDims cd = codec_dims(ndim, dims);
     (void)hipGetLastError();
-    HIPCHK(launch_decode(cd, (const uint8_t *)in, nullptr, ~0ull, field, (hipStream_t)stream));
+    HIPCHK(launch_decode(cd, (const uint8_t *)in, nullptr, ~0ull, field, nullptr, (hipStream_t)stream));
     return WV_OK;
 }
 

@@ -40,20 +40,26 @@ struct Sparse {
 };
 
 // ---------------------------------------------------------------- stencil launches (wv_stencil.hip)
-// Forward step in increment form: d_out = ((1-a) d_in + w lap u_in)/(1+a), u_out = u_in + d_out
-// (d_in may equal d_out; u_in must differ from u_out).
-hipError_t launch_fwd_step(const Grid &g, const float *u_in, float *u_out, const float *d_in, float *d_out,
-                           const float *w, hipStream_t s);
-// Adjoint step: mu <- ((1-a) mu + w lap lam)/(1+a), lam_out = lam_in + mu,
-// and (if G) G += gscale * uk * (w lap lam).
-hipError_t launch_adj_step(const Grid &g, const float *lam_in, float *lam_out, float *mu, const float *w,
-                           const float *uk, double *G, double gscale, hipStream_t s);
-// Source injection of sample q[n] (forward) at the unique source points.
+// Optional pair of events recorded by the kernel dispatch itself (start and end of the
+// stencil kernel, nothing else), for per-launch timing.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+// Forward step: u_out = u_in + ((1-a)(u_in - u_prev) + w lap u_in)/(1+a).
+// u_out may equal u_prev (in place); it must differ from u_in.
+hipError_t launch_fwd_step(const Grid &g, const float *u_in, const float *u_prev, float *u_out, const float *w,
+                           hipStream_t s, LaunchEvents ev = {});
+// Adjoint step (lam_in = lam^k, lam_next = lam^{k+1}, lam_out = lam^{k-1}, may equal
+// lam_next): the same update, and (if G) G += gscale * uk * (w lap lam_in).
+hipError_t launch_adj_step(const Grid &g, const float *lam_in, const float *lam_next, float *lam_out,
+                           const float *w, const float *uk, double *G, double gscale, hipStream_t s,
+                           LaunchEvents ev = {});
+// Source injection of sample q[n] (forward) at the unique source points of u_out.
 hipError_t launch_inject_src(const Grid &g, const Sparse &sp, const float *q, int n, const float *w,
-                             float *d, float *u_out, hipStream_t s);
+                             float *u_out, hipStream_t s);
 // Residual injection of row r_row (adjoint) at the unique receiver points; gradient term.
-hipError_t launch_inject_res(const Grid &g, const Sparse &sp, const float *r_row, const float *w, float *mu,
-                             float *lam_out, const float *uk, double *G, double gscale, hipStream_t s);
+hipError_t launch_inject_res(const Grid &g, const Sparse &sp, const float *r_row, const float *w, float *lam_out,
+                             const float *uk, double *G, double gscale, hipStream_t s);
 // Receiver gather out[r] = (R f)_r.
 hipError_t launch_gather(const Sparse &sp, const float *f, float *out, hipStream_t s);
 // Sum over sources of the gathered field: out[0] = sum_s (S f)_s.
@@ -83,16 +89,19 @@ struct CodecDims {
 };
 CodecDims codec_dims(int ndim, const int *dims);
 size_t codec_max_bytes(const CodecDims &cd);
-// Encode field into out + *base (device offset), capacity cap bytes from `out`.
+// Encode field (or field - sub, in binary32, when sub is not null) into out + *base
+// (device offset), capacity cap bytes from `out`.
 // Writes *next = *base + stream bytes rounded up to 256.  flags: nchunks status words.
+// ticket: a word that is 0 at launch (the kernel leaves it 0 again).
 // err: bit 2 = capacity overflow, bit 1 = non-finite input, bit 4 = look-back timeout.
 // stats[0] += stream bytes, stats[1] = max(stats[1], *next).
-hipError_t launch_encode(const CodecDims &cd, const float *field, double tol, uint8_t *out, uint64_t cap,
-                         const uint64_t *base, uint64_t *next, uint64_t *flags, uint32_t epoch,
-                         unsigned *err, unsigned long long *stats, hipStream_t s);
-// Decode the stream at in + *base (base == nullptr: offset 0) into field; cap bytes
-// are readable from `in` (a stream that does not fit decodes to zeros).
+hipError_t launch_encode(const CodecDims &cd, const float *field, const float *sub, double tol, uint8_t *out,
+                         uint64_t cap, const uint64_t *base, uint64_t *next, uint64_t *flags, uint32_t epoch,
+                         unsigned *ticket, unsigned *err, unsigned long long *stats, hipStream_t s);
+// Decode the stream at in + *base (base == nullptr: offset 0) into field, or, when sub
+// is not null, store sub - decoded; cap bytes are readable from `in` (a stream that
+// does not fit decodes to zeros).
 hipError_t launch_decode(const CodecDims &cd, const uint8_t *in, const uint64_t *base, uint64_t cap, float *field,
-                         hipStream_t s);
+                         const float *sub, hipStream_t s);
 
 }  // namespace wv

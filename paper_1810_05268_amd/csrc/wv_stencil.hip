@@ -1,15 +1,21 @@
 // Stencil kernels of the forward and adjoint acoustic solver (gfx950, wave64).
 //
 // The discrete problem is eq. (7) of the paper with the OT2 (second order in time)
-// leapfrog, written in increment form so that binary32 keeps the per-step change
-// at full relative precision:
-//   d^{n+1} = [(1-a) d^n + w (lap u^n + s^n)] / (1+a),   u^{n+1} = u^n + d^{n+1},
-// d^n = u^n - u^{n-1}, w = dt^2 c^2.  This is algebraically the three-level update
-// u^{n+1} = [2u^n - (1-a)u^{n-1} + w(lap u^n + s^n)]/(1+a).  The adjoint of the
-// three-level recursion has the same form run backward in time (lam, mu = lam^k -
-// lam^{k+1}) with the residual injected at the receivers; the gradient of the
-// misfit with respect to m accumulates -(1/dt^2) u^k w (lap lam^k + R^T r^k), which
-// equals -(1/dt^2) u^k [(1+a)lam^{k-1} - 2lam^k + (1-a)lam^{k+1}].
+// leapfrog on two time levels, updated in place (u^{n+1} overwrites u^{n-1}):
+//   u^{n+1} = [2u^n - (1-a)u^{n-1} + w(lap u^n + s^n)]/(1+a),   w = dt^2 c^2,
+// so a step moves exactly three reads and one write per point.  It is evaluated as
+//   u^{n+1} = u^n + [(1-a)(u^n - u^{n-1}) + w lap u^n]/(1+a)
+// (the source term is added by the injection kernel): the small per-step change is
+// formed first and added once, which keeps binary32 rounding near 5e-6 relative over
+// thousands of steps.  The adjoint of the recursion has the same form run backward
+// in time (lam^{k-1} overwrites lam^{k+1}) with the residual injected at the
+// receivers; the gradient of the misfit with respect to m accumulates
+// -(1/dt^2) u^k w (lap lam^k + R^T r^k), which equals
+// -(1/dt^2) u^k [(1+a)lam^{k-1} - 2lam^k + (1-a)lam^{k+1}].
+//
+// Operands read or written once per step (u^{n-1}, w, u^k, the gradient, the new
+// level) use nontemporal loads and stores, so they stream past the caches and leave
+// L2 to the centre field, whose halos are re-read by neighbouring tiles.
 //
 // The Laplacian is summed as sum_k c_k ((u_{+k} - u) + (u_{-k} - u)): for smooth
 // fields the differences are small and nearly exact, which keeps the binary32
@@ -18,6 +24,8 @@
 //
 // Workgroup ids are remapped so that every XCD (each has its own L2) receives a
 // contiguous run of neighbouring tiles, whose halos then hit the same L2.
+#include <hip/hip_ext.h>
+
 #include "wv_internal.h"
 
 namespace wv {
@@ -48,11 +56,18 @@ __device__ __forceinline__ float damping(const Grid &g, int x, int y, int z)
     return g.dampx * (float)(dx * dx) + g.dampy * (float)(dy * dy) + g.dampz * (float)(dz * dz);
 }
 
-// d_new = ((1-a) d + wl) / (1+a)
-__device__ __forceinline__ float damped_increment(float a, float d, float wl)
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float4 ntload4(const float *p)
 {
-    if (a == 0.0f) return d + wl;
-    return ((1.0f - a) * d + wl) / (1.0f + a);
+    const f4v t = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(p));
+    return make_float4(t.x, t.y, t.z, t.w);
+}
+
+__device__ __forceinline__ void ntstore4(float *p, float a, float b, float c, float d)
+{
+    f4v t = {a, b, c, d};
+    __builtin_nontemporal_store(t, reinterpret_cast<f4v *>(p));
 }
 
 // 3-D step.  A workgroup owns a 32 x 32 tile of the x-y plane and marches down z
@@ -70,12 +85,13 @@ __device__ __forceinline__ float damped_increment(float a, float d, float wl)
 //   * interior LDS values come from the queue, so HBM is read once per value
 //     (plus the 2K-plane warm-up of each z chunk); halos come from L2.
 // VEC: nx % 4 == 0, every float4 of a row is either inside or outside the grid.
+// `prev` (u^{n-1}) and `fout` (u^{n+1}) may be the same array: each point of it is
+// read and then written by the same lane only.
 template <int K, bool GRAD, bool VEC>
 __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *__restrict__ fin,
-                                                 float *__restrict__ fout, const float *inc_in, float *inc,
-                                                 const float *__restrict__ w, const float *__restrict__ uk,
-                                                 double *__restrict__ G, double gscale, int tiles_x, int tiles_y,
-                                                 int zchunks, int zlen)
+                                                 const float *prev, float *fout, const float *__restrict__ w,
+                                                 const float *__restrict__ uk, double *__restrict__ G,
+                                                 double gscale, int tiles_x, int tiles_y, int zchunks, int zlen)
 {
     constexpr int TX = 32, TY = 32;
     constexpr int HX = (K + 3) / 4 * 4;          // x halo columns (>= K, multiple of 4)
@@ -156,7 +172,7 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
     };
 
     struct Stage {
-        float4 d, w, u, h, f;
+        float4 p, w, u, h, f;
     };
     // loads that computing plane z needs: its point operands, the halo of plane z+1
     // and the queue front of plane z+1+K
@@ -165,12 +181,12 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
     auto load4p = [&](const float *base, int z, int gx) -> float4 {
         const int zc = min(z, nz - 1), yc = min(y, ny - 1);
         const float *row = base + (long long)zc * sxy + (long long)yc * nx;
-        if constexpr (VEC) return *reinterpret_cast<const float4 *>(row + min(gx, nx - 4));
+        if constexpr (VEC) return ntload4(row + min(gx, nx - 4));
         return make_float4(row[min(gx + 0, nx - 1)], row[min(gx + 1, nx - 1)], row[min(gx + 2, nx - 1)],
                            row[min(gx + 3, nx - 1)]);
     };
     auto fill = [&](Stage &S, int z) {
-        S.d = load4p(inc_in, z, x0);
+        S.p = load4p(prev, z, x0);
         S.w = load4p(w, z, x0);
         if constexpr (GRAD) S.u = load4p(uk, z, x0);
         const bool more = z + 1 < z1;
@@ -210,7 +226,7 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
             const int yc = min(y, ny - 1);
             const long long pg = (long long)z * sxy + (long long)yc * nx;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) gold[i] = G[pg + min(x0 + i, nx - 1)];
+            for (int i = 0; i < 4; ++i) gold[i] = __builtin_nontemporal_load(&G[pg + min(x0 + i, nx - 1)]);
         }
         fill(N, z + 1);
         const int cur = (z - z0) & 1;
@@ -244,11 +260,12 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
             sy[2] = fmaf(g.cx[k], (a.z - q[2][K]) + (b.z - q[2][K]), sy[2]);
             sy[3] = fmaf(g.cx[k], (a.w - q[3][K]) + (b.w - q[3][K]), sy[3]);
         }
-        // damping a = dampx dx^2 + dampy dy^2 + dampz dz^2, update in increment form
+        // damping a = dampx dx^2 + dampy dy^2 + dampz dz^2; the change of this step is
+        // formed from the two levels and added once
         const int dy_ = layer_depth(y, g.ix0[1], g.ix1[1]);
         const int dz_ = layer_depth(z, g.ix0[2], g.ix1[2]);
         const float ayz = g.dampy * (float)(dy_ * dy_) + g.dampz * (float)(dz_ * dz_);
-        const float din[4] = {S.d.x, S.d.y, S.d.z, S.d.w};
+        const float pin[4] = {S.p.x, S.p.y, S.p.z, S.p.w};
         const float win[4] = {S.w.x, S.w.y, S.w.z, S.w.w};
         const float uin[4] = {S.u.x, S.u.y, S.u.z, S.u.w};
         float dn[4], on[4], wl[4];
@@ -259,26 +276,23 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
             const float l = fmaf(c1, sy[i], lap[i]);
             wl[i] = win[i] * l;
             const float r = __builtin_amdgcn_rcpf(1.0f + a);
-            dn[i] = ((1.0f - a) * din[i] + wl[i]) * r;
+            dn[i] = ((1.0f - a) * (q[i][K] - pin[i]) + wl[i]) * r;
             on[i] = q[i][K] + dn[i];
         }
         if (ptin) {
             const long long p0 = (long long)z * sxy + rowoff + x0;
             if constexpr (VEC) {
-                *reinterpret_cast<float4 *>(inc + p0) = make_float4(dn[0], dn[1], dn[2], dn[3]);
-                *reinterpret_cast<float4 *>(fout + p0) = make_float4(on[0], on[1], on[2], on[3]);
+                ntstore4(fout + p0, on[0], on[1], on[2], on[3]);
             } else {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    if (x0 + i < nx) {
-                        inc[p0 + i] = dn[i];
-                        fout[p0 + i] = on[i];
-                    }
+                    if (x0 + i < nx) fout[p0 + i] = on[i];
             }
             if constexpr (GRAD) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    if (VEC || x0 + i < nx) G[p0 + i] = gold[i] + gscale * (double)uin[i] * (double)wl[i];
+                    if (VEC || x0 + i < nx)
+                        __builtin_nontemporal_store(gold[i] + gscale * (double)uin[i] * (double)wl[i], &G[p0 + i]);
             }
         }
         // stage plane z+1 (after the last plane this buffer is simply not read)
@@ -315,9 +329,10 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
 }
 
 // 2-D: a workgroup owns 256 consecutive x and marches down z (the second axis).
+// `prev` and `fout` may be the same array (read, then written, by the same lane).
 template <int K, bool GRAD>
-__global__ __launch_bounds__(256) void stencil2d(Grid g, const float *__restrict__ fin, float *__restrict__ fout,
-                                                 const float *inc_in, float *inc, const float *__restrict__ w,
+__global__ __launch_bounds__(256) void stencil2d(Grid g, const float *__restrict__ fin, const float *prev,
+                                                 float *fout, const float *__restrict__ w,
                                                  const float *__restrict__ uk, double *__restrict__ G,
                                                  double gscale, int tiles_x, int zchunks, int zlen)
 {
@@ -361,11 +376,15 @@ __global__ __launch_bounds__(256) void stencil2d(Grid g, const float *__restrict
             const float lap = sx + sz;
             const long long p = (long long)z * nx + x;
             const float a = damping(g, x, 0, z);
-            const float wl = w[p] * lap;
-            const float dn = damped_increment(a, inc_in[p], wl);
-            inc[p] = dn;
-            fout[p] = c + dn;
-            if constexpr (GRAD) G[p] += gscale * (double)uk[p] * (double)wl;
+            const float wl = __builtin_nontemporal_load(&w[p]) * lap;
+            const float d = c - __builtin_nontemporal_load(&prev[p]);
+            const float dn = (a == 0.0f) ? d + wl : ((1.0f - a) * d + wl) / (1.0f + a);
+            __builtin_nontemporal_store(c + dn, &fout[p]);
+            if constexpr (GRAD) {
+                const double gn = __builtin_nontemporal_load(&G[p]) +
+                                  gscale * (double)__builtin_nontemporal_load(&uk[p]) * (double)wl;
+                __builtin_nontemporal_store(gn, &G[p]);
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -373,10 +392,11 @@ __global__ __launch_bounds__(256) void stencil2d(Grid g, const float *__restrict
     }
 }
 
+// Adds w s / (1+a) at the source (or receiver) points of the level just written.
 template <bool GRAD>
 __global__ void inject_kernel(Grid g, Sparse sp, const float *__restrict__ vals, const float *__restrict__ w,
-                              float *__restrict__ inc, float *__restrict__ fout, const float *__restrict__ uk,
-                              double *__restrict__ G, double gscale)
+                              float *__restrict__ fout, const float *__restrict__ uk, double *__restrict__ G,
+                              double gscale)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= sp.npts) return;
@@ -390,7 +410,6 @@ __global__ void inject_kernel(Grid g, Sparse sp, const float *__restrict__ vals,
     const float a = damping(g, x, y, z);
     const float wi = w[p] * s;
     const float inj = (a == 0.0f) ? wi : wi / (1.0f + a);
-    inc[p] += inj;
     fout[p] += inj;
     if constexpr (GRAD) G[p] += gscale * (double)uk[p] * (double)wi;
 }
@@ -564,9 +583,19 @@ int resident_workgroups(Kern kern)
     return cus * per_cu;
 }
 
+// Kernel launch; with events, the dispatch itself records them around the kernel.
+template <typename Kern, typename... Args>
+void launch_timed(Kern kern, dim3 grid, hipStream_t s, LaunchEvents ev, Args... args)
+{
+    if (ev.start)
+        hipExtLaunchKernelGGL(kern, grid, dim3(256), 0, s, ev.start, ev.stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, args...);
+}
+
 template <int K, bool GRAD, bool VEC>
-hipError_t launch3d(const Grid &g, const float *fin, float *fout, const float *inc_in, float *inc, const float *w,
-                    const float *uk, double *G, double gscale, hipStream_t s)
+hipError_t launch3d(const Grid &g, const float *fin, const float *prev, float *fout, const float *w,
+                    const float *uk, double *G, double gscale, hipStream_t s, LaunchEvents ev)
 {
     auto kern = stencil3d<K, GRAD, VEC>;
     const int tiles_x = (g.nx + 31) / 32, tiles_y = (g.ny + 31) / 32;
@@ -575,79 +604,79 @@ hipError_t launch3d(const Grid &g, const float *fin, float *fout, const float *i
     int zchunks, zlen;
     choose_chunks((long long)tiles_x * tiles_y, g.nz, K, resident_workgroups(kern), zchunks, zlen);
     const int nwg = tiles_x * tiles_y * zchunks;
-    hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), 0, s, g, fin, fout, inc_in, inc, w, uk, G, gscale, tiles_x,
-                       tiles_y, zchunks, zlen);
+    launch_timed(kern, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, G, gscale, tiles_x, tiles_y, zchunks, zlen);
     return hipGetLastError();
 }
 
 template <int K, bool GRAD>
-hipError_t launch_k(const Grid &g, const float *fin, float *fout, const float *inc_in, float *inc, const float *w,
-                    const float *uk, double *G, double gscale, hipStream_t s)
+hipError_t launch_k(const Grid &g, const float *fin, const float *prev, float *fout, const float *w,
+                    const float *uk, double *G, double gscale, hipStream_t s, LaunchEvents ev)
 {
     if (g.ndim == 3) {
-        if (g.nx % 4 == 0) return launch3d<K, GRAD, true>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
-        return launch3d<K, GRAD, false>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
+        if (g.nx % 4 == 0) return launch3d<K, GRAD, true>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
+        return launch3d<K, GRAD, false>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
     }
     const int tiles_x = (g.nx + 255) / 256;
     int zchunks, zlen;
     choose_chunks(tiles_x, g.nz, K, 512, zchunks, zlen);
     const int nwg = tiles_x * zchunks;
-    hipLaunchKernelGGL((stencil2d<K, GRAD>), dim3(nwg), dim3(256), 0, s, g, fin, fout, inc_in, inc, w, uk, G,
-                       gscale, tiles_x, zchunks, zlen);
+    launch_timed(stencil2d<K, GRAD>, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, G, gscale, tiles_x, zchunks,
+                 zlen);
     return hipGetLastError();
 }
 
 template <bool GRAD>
-hipError_t launch_any(const Grid &g, const float *fin, float *fout, const float *inc_in, float *inc, const float *w,
-                      const float *uk, double *G, double gscale, hipStream_t s)
+hipError_t launch_any(const Grid &g, const float *fin, const float *prev, float *fout, const float *w,
+                      const float *uk, double *G, double gscale, hipStream_t s, LaunchEvents ev)
 {
     switch (g.K) {
-    case 1: return launch_k<1, GRAD>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
-    case 2: return launch_k<2, GRAD>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
-    case 3: return launch_k<3, GRAD>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
-    case 4: return launch_k<4, GRAD>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
-    case 5: return launch_k<5, GRAD>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
-    case 6: return launch_k<6, GRAD>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
-    case 7: return launch_k<7, GRAD>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
-    case 8: return launch_k<8, GRAD>(g, fin, fout, inc_in, inc, w, uk, G, gscale, s);
+    case 1: return launch_k<1, GRAD>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
+    case 2: return launch_k<2, GRAD>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
+    case 3: return launch_k<3, GRAD>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
+    case 4: return launch_k<4, GRAD>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
+    case 5: return launch_k<5, GRAD>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
+    case 6: return launch_k<6, GRAD>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
+    case 7: return launch_k<7, GRAD>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
+    case 8: return launch_k<8, GRAD>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-hipError_t launch_fwd_step(const Grid &g, const float *u_in, float *u_out, const float *d_in, float *d_out,
-                           const float *w, hipStream_t s)
+hipError_t launch_fwd_step(const Grid &g, const float *u_in, const float *u_prev, float *u_out, const float *w,
+                           hipStream_t s, LaunchEvents ev)
 {
-    return launch_any<false>(g, u_in, u_out, d_in, d_out, w, nullptr, nullptr, 0.0, s);
+    return launch_any<false>(g, u_in, u_prev, u_out, w, nullptr, nullptr, 0.0, s, ev);
 }
 
-hipError_t launch_adj_step(const Grid &g, const float *lam_in, float *lam_out, float *mu, const float *w,
-                           const float *uk, double *G, double gscale, hipStream_t s)
+hipError_t launch_adj_step(const Grid &g, const float *lam_in, const float *lam_next, float *lam_out,
+                           const float *w, const float *uk, double *G, double gscale, hipStream_t s,
+                           LaunchEvents ev)
 {
-    if (G) return launch_any<true>(g, lam_in, lam_out, mu, mu, w, uk, G, gscale, s);
-    return launch_any<false>(g, lam_in, lam_out, mu, mu, w, nullptr, nullptr, 0.0, s);
+    if (G) return launch_any<true>(g, lam_in, lam_next, lam_out, w, uk, G, gscale, s, ev);
+    return launch_any<false>(g, lam_in, lam_next, lam_out, w, nullptr, nullptr, 0.0, s, ev);
 }
 
-hipError_t launch_inject_src(const Grid &g, const Sparse &sp, const float *q, int n, const float *w, float *d,
+hipError_t launch_inject_src(const Grid &g, const Sparse &sp, const float *q, int n, const float *w,
                              float *u_out, hipStream_t s)
 {
     if (sp.npts == 0) return hipSuccess;
-    hipLaunchKernelGGL((inject_kernel<false>), dim3((sp.npts + 63) / 64), dim3(64), 0, s, g, sp, q + n, w, d, u_out,
+    hipLaunchKernelGGL((inject_kernel<false>), dim3((sp.npts + 63) / 64), dim3(64), 0, s, g, sp, q + n, w, u_out,
                        nullptr, nullptr, 0.0);
     return hipGetLastError();
 }
 
-hipError_t launch_inject_res(const Grid &g, const Sparse &sp, const float *r_row, const float *w, float *mu,
-                             float *lam_out, const float *uk, double *G, double gscale, hipStream_t s)
+hipError_t launch_inject_res(const Grid &g, const Sparse &sp, const float *r_row, const float *w, float *lam_out,
+                             const float *uk, double *G, double gscale, hipStream_t s)
 {
     if (sp.npts == 0) return hipSuccess;
     if (G)
-        hipLaunchKernelGGL((inject_kernel<true>), dim3((sp.npts + 255) / 256), dim3(256), 0, s, g, sp, r_row, w, mu,
+        hipLaunchKernelGGL((inject_kernel<true>), dim3((sp.npts + 255) / 256), dim3(256), 0, s, g, sp, r_row, w,
                            lam_out, uk, G, gscale);
     else
         hipLaunchKernelGGL((inject_kernel<false>), dim3((sp.npts + 255) / 256), dim3(256), 0, s, g, sp, r_row, w,
-                           mu, lam_out, nullptr, nullptr, 0.0);
+                           lam_out, nullptr, nullptr, 0.0);
     return hipGetLastError();
 }
 

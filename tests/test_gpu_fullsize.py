@@ -1,0 +1,94 @@
+"""Parity at the benchmark's full sizes, in the launch configuration the benchmark
+times (same grids, same kernels, same z-chunking), against the FP64 oracle run on
+the same full grids for a bounded number of steps."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import schedule as SC
+from tests.helpers import gpu_side, has_gpu, oracle_side, rel_l2
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not has_gpu(), reason="needs a GPU")]
+
+WAVEFIELD_TOL = 1e-5
+GRAD_TOL = 1e-4
+
+
+def test_fault_body_full_grid_forward():
+    """400^3 padded points, order 16: 200 steps, data and final state against the oracle."""
+    shot = W.fault_body_3d(nt=200)
+    S, _ = oracle_side(shot)
+    G, _ = gpu_side(shot)
+    ref = S.forward(want_last=True)
+    data, state = G.forward(want_state=True)
+    e_d = rel_l2(data.cpu().numpy(), ref["data"])
+    e_u = rel_l2(state[0].cpu().numpy(), ref["last"][0])
+    e_p = rel_l2(state[1].cpu().numpy(), ref["last"][1])
+    print(f"full grid: data {e_d:.2e} u^N {e_u:.2e} u^(N-1) {e_p:.2e}")
+    assert e_d <= WAVEFIELD_TOL and e_u <= WAVEFIELD_TOL and e_p <= WAVEFIELD_TOL
+
+
+def test_fault_body_full_grid_revolve_gradient():
+    """400^3 padded points, order 16: a 30-step checkpointed gradient with 5 slots
+    (recomputation on) against the oracle running the same schedule."""
+    import torch
+    nt, M = 30, 5
+    shot = W.fault_body_3d(nt=nt)
+    S, _ = oracle_side(shot)
+    rng = np.random.default_rng(11)
+    res = rng.standard_normal((nt + 1, len(shot.rec))) * 1e-3
+    res[0] = 0.0
+    acts = SC.schedule(nt, M)
+    g_or, st_or = S.gradient_actions(res, acts, M)
+    G, _ = gpu_side(shot)
+    g, st = G.gradient(torch.as_tensor(res.astype(np.float32), device="cuda"), 8 * G.P * (M - 1))
+    e = rel_l2(g.cpu().numpy(), g_or)
+    print(f"full grid gradient rel-L2 {e:.2e}", st)
+    assert st["slots"] == M and st["advances"] == st_or["advances"]
+    assert e <= GRAD_TOL
+
+
+def test_fault_body_full_field_codec_byte_identical():
+    """One 400^3 binary32 field (a synthetic wave packet: Gaussian-enveloped plane
+    waves plus weak seeded noise), tolerance 1e-4: the GPU stream equals the oracle's
+    byte for byte, and the decoded field is within the tolerance."""
+    import oracle
+    from tests.test_gpu_codec import gpu_roundtrip
+    nz = ny = nx = 400
+    z, y, x = np.meshgrid(np.arange(nz, dtype=np.float32), np.arange(ny, dtype=np.float32),
+                          np.arange(nx, dtype=np.float32), indexing="ij")
+    r2 = (x - 200) ** 2 + (y - 180) ** 2 + (z - 60) ** 2
+    f = 0.05 * np.exp(-r2 / (2 * 70.0 ** 2)) * np.sin(0.21 * x + 0.13 * y - 0.17 * z)
+    del x, y, z, r2
+    f += 1e-5 * np.random.default_rng(4).standard_normal(f.shape).astype(np.float32)
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    ref = oracle.encode(f, 1e-4)
+    got, dec = gpu_roundtrip(f, 1e-4)
+    print(f"400^3 field: {len(ref)} bytes, ratio {f.nbytes / len(ref):.1f}")
+    assert len(got) == len(ref)
+    assert got == ref
+    assert float(np.max(np.abs(dec - f))) <= 1e-4
+
+
+def test_layered_noise_full_size_forward_and_revolve():
+    """168^3 padded points, order 8, 1000 steps: data against the oracle; the
+    20-slot Revolve gradient (t = 2750) against the oracle's on the same schedule."""
+    import torch
+    shot = W.layered_noise_3d()
+    S, _ = oracle_side(shot)
+    St, _ = oracle_side(shot, "true")
+    ref = S.forward()
+    d_obs = St.forward()["data"]
+    G, _ = gpu_side(shot)
+    data = G.forward()
+    e_d = rel_l2(data.cpu().numpy(), ref["data"])
+    res = ref["data"] - d_obs
+    M = 21                  # 20 stored checkpoints plus the initial (zero) state
+    acts = SC.schedule(shot.nt, M)
+    g_or, st_or = S.gradient_actions(res, acts, M)
+    g, st = G.gradient(torch.as_tensor(res.astype(np.float32), device="cuda"), 8 * G.P * (M - 1))
+    e_g = rel_l2(g.cpu().numpy(), g_or)
+    print(f"168^3: data {e_d:.2e} gradient {e_g:.2e} advances {st['advances']}")
+    assert e_d <= WAVEFIELD_TOL
+    assert st["advances"] == st_or["advances"] == SC.p_closed(shot.nt + 1, M)
+    assert e_g <= GRAD_TOL

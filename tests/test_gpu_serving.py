@@ -70,3 +70,34 @@ def test_request_larger_than_pool_is_rejected():
     with pytest.raises(P.WvError):
         eng.submit(G, d, b, t, h)
     eng.close()
+
+
+def test_many_concurrent_compressed_requests():
+    """Twelve compressed requests submitted at once to eight workers: the encoders of
+    different shots run concurrently on their own streams; every request completes and
+    equals the same request run alone."""
+    import torch
+    import paper_1810_05268_amd as P
+    from paper_1810_05268_amd.serving import Engine, replay
+    from paper_1810_05268_amd.shot import DeviceShot
+    classes = [(0.5, 3, (72, 64, 60), 8, 150), (0.5, 3, (96, 80, 70), 8, 120)]
+    reqs = W.serving_stream(nreq=12, rate=1e6, seed=9, classes=classes)
+    items = []
+    for r in reqs:
+        s = r.shot
+        dt = s.cfl_frac * P.cfl_dt(s.ndim, s.h, s.order, s.vmax)
+        q = W.ricker(s.f0, dt, s.nt).astype(np.float32)
+        G = DeviceShot(s.ndim, s.n, s.h, s.nbl, s.order, s.nt, dt, s.vmax, s.padded("true"), q, s.src, s.rec)
+        d_obs = G.forward()
+        G.set_velocity(s.padded("vel"))
+        items.append((r.arrival, G, d_obs, 8 * G.P * 12, 1e-4, 4.0))
+    torch.cuda.synchronize()
+    alone = [G.misfit_gradient(d_obs, b, tol, h)[1].clone() for _, G, d_obs, b, tol, h in items]
+    for _, G, _, _, _, _ in items:
+        G._ws = None
+    eng = Engine(pool_bytes=sum(G.pb.workspace_bytes(1, b) + 4096 for _, G, _, b, _, _ in items), max_active=8)
+    res, wall = replay(eng, items, time_scale=0.0)
+    eng.close()
+    for g, r in zip(alone, res):
+        assert r["status"] == 0
+        assert torch.equal(r["grad"], g)
