@@ -142,7 +142,7 @@ int wv_forward(const wv_model *model, const wv_geom *geom, float *data, float *s
  * reversed with Revolve checkpointing inside mem_budget bytes of checkpoint memory.
  *   residual    device [nt+1][nrec] float (row 0 unused)
  *   mem_budget  bytes available for checkpoints (SI bytes); the slot count is
- *               M = min(nt, 1 + floor(mem_budget / (S / F))), S = 8 P bytes per
+ *               M = min(nt, 1 + floor(mem_budget / (S / F + 512))), S = 8 P bytes per
  *               uncompressed checkpoint (u^k and u^{k-1}; compressed, the pair is
  *               stored as u^k and the increment u^k - u^{k-1}),
  *               F = 1 if tol == 0, else ratio_hint if > 0, else the ratio measured

@@ -349,7 +349,11 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
 
     // bit planes: m_lo[k] / m_hi[k] hold bit k of coefficients 0..31 / 32..63
     uint32_t m_lo[32], m_hi[32];
-    {
+#pragma unroll
+    for (int k = 0; k < 32; ++k) m_lo[k] = m_hi[k] = 0u;
+    // waves whose blocks are all empty or below the tolerance (most of an early
+    // wavefield) skip the transform and the plane transposes
+    if (__ballot(coded) != 0ull) {
         int32_t q[S];
 #pragma unroll
         for (int i = 0; i < S; ++i) q[i] = coded ? (int32_t)ldexpf(v[i], 30 - emax) : 0;   // exact scaling, truncation

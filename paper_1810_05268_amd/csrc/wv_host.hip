@@ -243,11 +243,15 @@ int validate_model(const wv_model *m, Setup &su)
         if (ax < 0) {
             g.ix0[t] = 0;
             g.ix1[t] = 0;
+            g.cf2[t] = 0.0f;
             *dd[t] = 0.0f;
             continue;
         }
         const double h = m->h[ax];
         for (int k = 1; k <= g.K; ++k) cc[t][k] = (float)(a[k] / (h * h));
+        double far = 0.0;
+        for (int k = 2; k <= g.K; ++k) far += (double)cc[t][k];
+        g.cf2[t] = (float)(2.0 * far);
         if (t > 0) cc[t][0] = (float)((m->h[0] * m->h[0]) / (h * h));
         g.ix0[t] = m->nbl;
         g.ix1[t] = m->nbl + m->n[ax] - 1;
@@ -999,7 +1003,9 @@ int gradient_common(const wv_model *m, const wv_geom *geo, const float *residual
     // optimistic) is repeated with half the planned ratio, i.e. fewer slots; the last
     // attempt plans with the uncompressed size, which always fits.
     for (int attempt = 0;; ++attempt) {
-        size_t slot_bytes = tol > 0 ? (size_t)((double)R.S / F) + 2 * (size_t)(R.cd.prefix_bytes + 256) : R.S;
+        // a compressed slot: S / F (F is a ratio of whole streams, prefixes included) plus
+        // the 256-byte alignment of its two streams
+        size_t slot_bytes = tol > 0 ? (size_t)((double)R.S / F) + 512 : R.S;
         if (slot_bytes < 1) slot_bytes = 1;
         const size_t nslots = mem_budget / slot_bytes;
         if (nslots < 1 && N > 1) return WV_EBUDGET;

@@ -21,6 +21,7 @@ struct Grid {
     float cx[kMaxK + 1];     // a_k / h^2 per axis, k = 1..K;
     float cy[kMaxK + 1];     // cy[0] = h_x^2/h_y^2 and cz[0] = h_x^2/h_z^2 (the 3-D kernel
     float cz[kMaxK + 1];     // applies cx[k] on every axis and scales y, z by these)
+    float cf2[3];            // 2 sum_{k>=2} of the axis's weights (x from cx, y from cy, z from cz)
     float dampx, dampy, dampz; // 0.5 dt smax_axis / nbl^2; a = sum damp_axis * delta_axis^2
     int K;
     int ndim;

@@ -13,14 +13,20 @@
 // -(1/dt^2) u^k w (lap lam^k + R^T r^k), which equals
 // -(1/dt^2) u^k [(1+a)lam^{k-1} - 2lam^k + (1-a)lam^{k+1}].
 //
-// Operands read or written once per step (u^{n-1}, w, u^k, the gradient, the new
-// level) use nontemporal loads and stores, so they stream past the caches and leave
-// L2 to the centre field, whose halos are re-read by neighbouring tiles.
+// Operands read or written once per step (u^{n-1}, w, u^k, the new level) use
+// nontemporal loads and stores, so they stream past the caches and leave L2 to the
+// centre field, whose halos are re-read by neighbouring tiles.  The binary64 gradient
+// takes two 16-byte accesses per lane; it is cached normally, so that a line is
+// fetched and written once although each access covers only half of it.
 //
-// The Laplacian is summed as sum_k c_k ((u_{+k} - u) + (u_{-k} - u)): for smooth
-// fields the differences are small and nearly exact, which keeps the binary32
-// rounding of the stencil far below the 1e-5 wavefield tolerance over thousands of
-// steps (a direct sum of the large weighted terms loses about two digits).
+// Laplacian along one axis, in binary32 without the cancellation of a direct sum:
+//   c_1 ((u_{+1} - u) + (u_{-1} - u)) + [sum_{k>=2} c_k (u_{+k} + u_{-k}) - 2 (sum_{k>=2} c_k) u].
+// The dominant k = 1 term is formed from differences, which are small and nearly
+// exact for smooth fields; the far weights are small (|c_k| <= 0.18 c_1 for k >= 2 at
+// every order up to 16, falling fast), so their plain sum, folded once against u, adds only
+// a fraction of an ulp of the result.  In a 3000-step binary32 run this matches the
+// all-difference form (about 5e-6 against binary64; a direct sum of all terms loses
+// about two digits) at 20 instead of 32 operations per axis for order 16.
 //
 // Workgroup ids are remapped so that every XCD (each has its own L2) receives a
 // contiguous run of neighbouring tiles, whose halos then hit the same L2.
@@ -173,9 +179,10 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
 
     struct Stage {
         float4 p, w, u, h, f;
+        double g[GRAD ? 4 : 1];
     };
-    // loads that computing plane z needs: its point operands, the halo of plane z+1
-    // and the queue front of plane z+1+K
+    // loads that computing plane z needs: its point operands (with GRAD also u^k and
+    // the gradient), the halo of plane z+1+K and the queue front of plane z+1+K
     // point operands feed only values stored under the same in-range predicate, so
     // they are loaded from the clamped address without zeroing
     auto load4p = [&](const float *base, int z, int gx) -> float4 {
@@ -188,7 +195,20 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
     auto fill = [&](Stage &S, int z) {
         S.p = load4p(prev, z, x0);
         S.w = load4p(w, z, x0);
-        if constexpr (GRAD) S.u = load4p(uk, z, x0);
+        if constexpr (GRAD) {
+            S.u = load4p(uk, z, x0);
+            const long long pg = (long long)min(z, nz - 1) * sxy + (long long)min(y, ny - 1) * nx;
+            if constexpr (VEC) {
+                // two 16-byte loads per lane, normally cached: the line a lane pair shares
+                // stays in L2 between them
+                const double2 g0 = *reinterpret_cast<const double2 *>(&G[pg + min(x0, nx - 4)]);
+                const double2 g1 = *reinterpret_cast<const double2 *>(&G[pg + min(x0, nx - 4) + 2]);
+                S.g[0] = g0.x; S.g[1] = g0.y; S.g[2] = g1.x; S.g[3] = g1.y;
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) S.g[i] = G[pg + min(x0 + i, nx - 1)];
+            }
+        }
         const bool more = z + 1 < z1;
         // the halo of plane z+1+K is read together with the queue front of the same
         // plane (which is the neighbouring tiles' interior), so it hits in L2; it waits
@@ -219,14 +239,12 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
 
     const float c1 = g.cy[0], c2 = g.cz[0];   // h_x^2/h_y^2, h_x^2/h_z^2
     auto step = [&](int z, Stage &S, Stage &N) {
-        // the binary64 gradient is read in the iteration that updates it (clamped
-        // address, no branch; only in-range lanes store the update)
+        // the binary64 gradient of this plane arrived with the stage (clamped address,
+        // no branch; only in-range lanes store the update)
         double gold[4] = {0.0, 0.0, 0.0, 0.0};
         if constexpr (GRAD) {
-            const int yc = min(y, ny - 1);
-            const long long pg = (long long)z * sxy + (long long)yc * nx;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) gold[i] = __builtin_nontemporal_load(&G[pg + min(x0 + i, nx - 1)]);
+            for (int i = 0; i < 4; ++i) gold[i] = S.g[i];
         }
         fill(N, z + 1);
         const int cur = (z - z0) & 1;
@@ -238,27 +256,49 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
             const float4 t = *reinterpret_cast<const float4 *>(trow + HX + 4 * tx4 - XC + 4 * v);
             xr[4 * v + 0] = t.x; xr[4 * v + 1] = t.y; xr[4 * v + 2] = t.z; xr[4 * v + 3] = t.w;
         }
+        // per axis: near (k = 1, differences) + far (k >= 2, plain sum) - cf2 * centre;
+        // the 3-D kernel applies cx on every axis and scales y and z afterwards
+        const float cf2 = g.cf2[0];
         float lap[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const float c = q[i][K];
-            float sx = 0.0f, sz = 0.0f;
+            float sx = g.cx[1] * ((xr[XC + i + 1] - c) + (xr[XC + i - 1] - c));
+            float sz = g.cx[1] * ((q[i][K + 1] - c) + (q[i][K - 1] - c));
+            if constexpr (K > 1) {
+                float fx = 0.0f, fz = 0.0f;
 #pragma unroll
-            for (int k = 1; k <= K; ++k) {
-                sx = fmaf(g.cx[k], (xr[XC + i + k] - c) + (xr[XC + i - k] - c), sx);
-                sz = fmaf(g.cx[k], (q[i][K + k] - c) + (q[i][K - k] - c), sz);
+                for (int k = 2; k <= K; ++k) {
+                    fx = fmaf(g.cx[k], xr[XC + i + k] + xr[XC + i - k], fx);
+                    fz = fmaf(g.cx[k], q[i][K + k] + q[i][K - k], fz);
+                }
+                sx += fmaf(-cf2, c, fx);
+                sz += fmaf(-cf2, c, fz);
             }
             lap[i] = fmaf(c2, sz, sx);
         }
-        float sy[4] = {0.f, 0.f, 0.f, 0.f};
+        float sy[4];
+        {
+            const float4 a = *reinterpret_cast<const float4 *>(&tile[cur][ty + K + 1][HX + 4 * tx4]);
+            const float4 b = *reinterpret_cast<const float4 *>(&tile[cur][ty + K - 1][HX + 4 * tx4]);
+            sy[0] = g.cx[1] * ((a.x - q[0][K]) + (b.x - q[0][K]));
+            sy[1] = g.cx[1] * ((a.y - q[1][K]) + (b.y - q[1][K]));
+            sy[2] = g.cx[1] * ((a.z - q[2][K]) + (b.z - q[2][K]));
+            sy[3] = g.cx[1] * ((a.w - q[3][K]) + (b.w - q[3][K]));
+        }
+        if constexpr (K > 1) {
+            float fy[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int k = 1; k <= K; ++k) {
-            const float4 a = *reinterpret_cast<const float4 *>(&tile[cur][ty + K + k][HX + 4 * tx4]);
-            const float4 b = *reinterpret_cast<const float4 *>(&tile[cur][ty + K - k][HX + 4 * tx4]);
-            sy[0] = fmaf(g.cx[k], (a.x - q[0][K]) + (b.x - q[0][K]), sy[0]);
-            sy[1] = fmaf(g.cx[k], (a.y - q[1][K]) + (b.y - q[1][K]), sy[1]);
-            sy[2] = fmaf(g.cx[k], (a.z - q[2][K]) + (b.z - q[2][K]), sy[2]);
-            sy[3] = fmaf(g.cx[k], (a.w - q[3][K]) + (b.w - q[3][K]), sy[3]);
+            for (int k = 2; k <= K; ++k) {
+                const float4 a = *reinterpret_cast<const float4 *>(&tile[cur][ty + K + k][HX + 4 * tx4]);
+                const float4 b = *reinterpret_cast<const float4 *>(&tile[cur][ty + K - k][HX + 4 * tx4]);
+                fy[0] = fmaf(g.cx[k], a.x + b.x, fy[0]);
+                fy[1] = fmaf(g.cx[k], a.y + b.y, fy[1]);
+                fy[2] = fmaf(g.cx[k], a.z + b.z, fy[2]);
+                fy[3] = fmaf(g.cx[k], a.w + b.w, fy[3]);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sy[i] += fmaf(-cf2, q[i][K], fy[i]);
         }
         // damping a = dampx dx^2 + dampy dy^2 + dampz dz^2; the change of this step is
         // formed from the two levels and added once
@@ -289,10 +329,17 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
                     if (x0 + i < nx) fout[p0 + i] = on[i];
             }
             if constexpr (GRAD) {
+                double gn[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (VEC || x0 + i < nx)
-                        __builtin_nontemporal_store(gold[i] + gscale * (double)uin[i] * (double)wl[i], &G[p0 + i]);
+                for (int i = 0; i < 4; ++i) gn[i] = gold[i] + gscale * (double)uin[i] * (double)wl[i];
+                if constexpr (VEC) {
+                    *reinterpret_cast<double2 *>(&G[p0]) = make_double2(gn[0], gn[1]);
+                    *reinterpret_cast<double2 *>(&G[p0 + 2]) = make_double2(gn[2], gn[3]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (x0 + i < nx) G[p0 + i] = gn[i];
+                }
             }
         }
         // stage plane z+1 (after the last plane this buffer is simply not read)
@@ -310,8 +357,10 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
         }
         q[0][2 * K] = S.f.x; q[1][2 * K] = S.f.y; q[2][2 * K] = S.f.z; q[3][2 * K] = S.f.w;
     };
-    // several planes per trip: the wait pass drains outstanding loads at the
-    // back-edge (four for the forward step; two where registers are tight)
+    // several planes per trip for the forward step (the wait pass drains outstanding
+    // loads at the back-edge); the adjoint step, whose stage also carries u^k and the
+    // binary64 gradient of the next plane, runs one plane per trip and hands the stage
+    // over by copy, which keeps it within 256 registers without spilling
     int z = z0;
     if constexpr (!GRAD) {
         for (; z + 3 < z1; z += 4) {
@@ -321,11 +370,18 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
             step(z + 3, B, A);
         }
     }
-    for (; z + 1 < z1; z += 2) {
-        step(z, A, B);
-        step(z + 1, B, A);
+    if constexpr (GRAD) {
+        for (; z < z1; ++z) {
+            step(z, A, B);
+            A = B;
+        }
+    } else {
+        for (; z + 1 < z1; z += 2) {
+            step(z, A, B);
+            step(z + 1, B, A);
+        }
+        if (z < z1) step(z, A, B);
     }
-    if (z < z1) step(z, A, B);
 }
 
 // 2-D: a workgroup owns 256 consecutive x and marches down z (the second axis).
@@ -367,11 +423,17 @@ __global__ __launch_bounds__(256) void stencil2d(Grid g, const float *__restrict
         __syncthreads();
         if (in) {
             const float c = q[K];
-            float sx = 0.0f, sz = 0.0f;
+            float sx = g.cx[1] * ((row[tid + K + 1] - c) + (row[tid + K - 1] - c));
+            float sz = g.cz[1] * ((q[K + 1] - c) + (q[K - 1] - c));
+            if constexpr (K > 1) {
+                float fx = 0.0f, fz = 0.0f;
 #pragma unroll
-            for (int k = 1; k <= K; ++k) {
-                sx = fmaf(g.cx[k], (row[tid + K + k] - c) + (row[tid + K - k] - c), sx);
-                sz = fmaf(g.cz[k], (q[K + k] - c) + (q[K - k] - c), sz);
+                for (int k = 2; k <= K; ++k) {
+                    fx = fmaf(g.cx[k], row[tid + K + k] + row[tid + K - k], fx);
+                    fz = fmaf(g.cz[k], q[K + k] + q[K - k], fz);
+                }
+                sx += fmaf(-g.cf2[0], c, fx);
+                sz += fmaf(-g.cf2[2], c, fz);
             }
             const float lap = sx + sz;
             const long long p = (long long)z * nx + x;
