@@ -76,6 +76,33 @@ def plan_hint(st, points):
     return max(1.0, 0.85 * S * (st["slots"] - 1) / st["peak_bytes"])
 
 
+def performance_model(nt, points, budget, st_plain, st_comp, hint, sweep_stats):
+    """The run-time model (wv_predict) fed with the per-unit costs of the timed plain
+    and compressed calls: predicted against measured device time of each run, as the
+    paper validates its model.  Sweep runs are predicted with the headline costs and
+    their own planning ratio."""
+    import paper_1810_05268_amd as P
+
+    def phases(st):
+        return st["ms_forward"] + st["ms_adjoint"] + st["ms_store"] + st["ms_restore"]
+    cp, cc = P.costs_from_stats(st_plain), P.costs_from_stats(st_comp)
+    rows = []
+    pr = P.predict(nt, points, budget, False, cp["c_f"], cp["c_r"], t_copy=cp["t_store"])
+    rows.append({"run": "plain", "predicted_ms": pr["ms_total"], "measured_ms": phases(st_plain),
+                 "slots": pr["slots"], "advances": pr["advances"]})
+    pr = P.predict(nt, points, budget, True, cc["c_f"], cc["c_r"], t_c=cc["t_store"], t_d=cc["t_d"], ratio=hint)
+    rows.append({"run": "compressed", "predicted_ms": pr["ms_total"], "measured_ms": phases(st_comp),
+                 "slots": pr["slots"], "advances": pr["advances"]})
+    for tol, h, st in sweep_stats:
+        pr = P.predict(nt, points, budget, True, cc["c_f"], cc["c_r"], t_c=cc["t_store"], t_d=cc["t_d"], ratio=h)
+        rows.append({"run": f"compressed tol {tol:g}", "predicted_ms": pr["ms_total"], "measured_ms": phases(st),
+                     "slots": pr["slots"], "advances": pr["advances"]})
+    for r in rows:
+        r["rel_err"] = (r["predicted_ms"] - r["measured_ms"]) / r["measured_ms"]
+    full = P.predict(nt, points, budget, False, cp["c_f"], cp["c_r"], t_copy=cp["t_store"])["ms_full_storage"]
+    return {"costs_plain": cp, "costs_compressed": cc, "full_storage_ms": full, "runs": rows}
+
+
 def traffic_per_launch():
     """HBM bytes per launch of the forward and adjoint stencils from the committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each
@@ -319,14 +346,16 @@ def main():
     log(f"compressed tol {args.tol}: {statistics.mean(w_comp):.3f} s  M={st_comp[0]['slots']} "
         f"ratio={st_comp[0]['ratio']:.1f} advances={st_comp[0]['advances']} grad err vs plain {err:.3e}")
 
-    sweep = []
+    sweep, sweep_stats = [], []
     for tol in [float(t) for t in args.sweep.split(",") if t.strip()]:
         _, sp0, _ = timed(tol, 0.0, g_comp, 1)
-        ws_, ss_, _ = timed(tol, plan_hint(sp0[-1], Pn), g_comp, 1)
+        h = plan_hint(sp0[-1], Pn)
+        ws_, ss_, _ = timed(tol, h, g_comp, 1)
         e = float(torch.linalg.vector_norm(g_comp - g_plain) / torch.linalg.vector_norm(g_plain))
         sweep.append({"tol": tol, "shot_s": ws_[0], "slots": ss_[0]["slots"], "ratio": ss_[0]["ratio"],
                       "advances": ss_[0]["advances"], "grad_rel_err_vs_plain": e,
                       "speedup_vs_plain": statistics.mean(w_plain) / ws_[0]})
+        sweep_stats.append((tol, h, ss_[0]))
         log(f"sweep tol {tol}: {ws_[0]:.3f} s ratio {ss_[0]['ratio']:.1f} err {e:.3e}")
 
     # per-phase device times over the timed compressed steps (HIP events on the call's stream)
@@ -356,6 +385,8 @@ def main():
     ms_per_store = st["ms_store"] / st["stores"] if st["stores"] else None
     ms_per_decode = st["ms_restore"] / st["decodes"] if st["decodes"] else None
 
+    model = performance_model(shot.nt, Pn, budget, st_plain[0], st_comp[0], hint, sweep_stats)
+
     ms_step = 1e3 * statistics.mean(w_comp)
     value = Pn * 2 * shot.nt / (ms_step * 1e-3) / 1e9
     lat = sorted(1e3 * w for w in w_comp)
@@ -382,6 +413,7 @@ def main():
                   if st["stores"] else None},
         "misfit": {"compressed": phi_comp, "plain": phi_plain},
         "sweep": sweep,
+        "model": model,
         "roofline": roof,
     }
     if args.serving_requests > 0 and not args.quick:

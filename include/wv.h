@@ -92,6 +92,7 @@ typedef struct {
     long stores;         /* checkpoints written (u^{k-1} is written only for checkpoints the schedule
                             later advances from; a reverse step needs only u^k) */
     long restores;       /* restore actions (a restore reads the checkpoint in place: no copy) */
+    long fields;         /* binary32 fields written to checkpoint memory (1 or 2 per store) */
     long decodes;        /* fields decoded from compressed checkpoints (u^k at a restore unless it is still
                             decoded; u^{k-1} only when the schedule advances from the restore) */
     long reverses;       /* adjoint steps */
@@ -276,6 +277,40 @@ int wv_schedule(int nt, int M, int32_t *actions, size_t cap, size_t *n_actions);
 /* Forward steps of that schedule: t(nt+1, M) = r (nt+1) - C(M+1+r-1, r-1),
  * r = min{r : C(M+r, r) >= nt+1}. */
 long wv_schedule_forward_steps(int nt, int M);
+
+/* ------------------------------------------------------------ performance model
+ * The run-time model of Sec. "Checkpointing performance model" (eqs. (1)-(5)) and
+ * Sec. "Performance model including compression" (eq. (6)), for this library's
+ * executor.  The executor restores in place (no read copy; a compressed restore
+ * decodes), and writes u^{k-1} only for checkpoints the schedule advances from.  Each
+ * cost is one unit's device time, e.g. from the stats of an earlier call with timing:
+ * c_f = ms_forward / advances, c_r = ms_adjoint / reverses, t_c or t_copy =
+ * ms_store / fields, t_d = ms_restore / decodes, ratio = stats ratio.  The counts come
+ * from the exact schedule and a host-only pass of the executor's bookkeeping, so they
+ * equal what a gradient call with the same slot count does.
+ *   T = c_f * advances + c_r * nt + (t_c | t_copy) * fields + t_d * decodes
+ * and the full-storage time of eq. (1), (c_f + c_r) * nt. */
+typedef struct {
+    double c_f;      /* ms per forward step (stencil, source, receivers) */
+    double c_r;      /* ms per adjoint step (stencil, gradient, residual) */
+    double t_copy;   /* ms to copy one binary32 field into checkpoint memory */
+    double t_c;      /* ms to encode one field */
+    double t_d;      /* ms to decode one field */
+    double ratio;    /* compression ratio of checkpoint streams (required if compressed) */
+} wv_costs;
+
+typedef struct {
+    int slots;                 /* M as a gradient call plans it for this budget and ratio */
+    long advances, stores, fields, decodes;
+    double ms_forward, ms_adjoint, ms_store, ms_restore, ms_total;
+    double ms_full_storage;    /* eq. (1): no checkpointing at all */
+} wv_prediction;
+
+/* Predicted gradient time for nt steps on a grid of `points` padded points with
+ * mem_budget bytes of checkpoint memory, uncompressed (compressed = 0) or compressed.
+ * Host only.  WV_EBUDGET if not one slot fits. */
+int wv_predict(int nt, long long points, size_t mem_budget, int compressed, const wv_costs *costs,
+               wv_prediction *out);
 
 const char *wv_strerror(int code);
 

@@ -48,11 +48,26 @@ class WvGeom(C.Structure):
 
 class WvStats(C.Structure):
     _fields_ = [("timing", C.c_int), ("advances", C.c_long), ("stores", C.c_long), ("restores", C.c_long),
-                ("decodes", C.c_long), ("reverses", C.c_long), ("slots", C.c_long), ("bytes_stored", C.c_double),
+                ("fields", C.c_long), ("decodes", C.c_long), ("reverses", C.c_long), ("slots", C.c_long), ("bytes_stored", C.c_double),
                 ("peak_bytes", C.c_double), ("ratio", C.c_double), ("ratio_planned", C.c_double),
                 ("misfit", C.c_double), ("ms_total", C.c_double), ("ms_forward", C.c_double),
                 ("ms_adjoint", C.c_double), ("ms_store", C.c_double), ("ms_restore", C.c_double),
                 ("ms_fwd_kernel", C.c_double), ("ms_adj_kernel", C.c_double), ("retries", C.c_long)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class WvCosts(C.Structure):
+    _fields_ = [("c_f", C.c_double), ("c_r", C.c_double), ("t_copy", C.c_double), ("t_c", C.c_double),
+                ("t_d", C.c_double), ("ratio", C.c_double)]
+
+
+class WvPrediction(C.Structure):
+    _fields_ = [("slots", C.c_int), ("advances", C.c_long), ("stores", C.c_long), ("fields", C.c_long),
+                ("decodes", C.c_long), ("ms_forward", C.c_double), ("ms_adjoint", C.c_double),
+                ("ms_store", C.c_double), ("ms_restore", C.c_double), ("ms_total", C.c_double),
+                ("ms_full_storage", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -66,7 +81,7 @@ class WvResult(C.Structure):
 # every symbol include/wv.h declares
 SYMBOLS = ["wv_cfl_dt", "wv_workspace_bytes", "wv_forward", "wv_gradient", "wv_misfit_gradient", "wv_adjoint_src",
            "wv_pad_velocity", "wv_velocity_gradient", "wv_zfpk_workspace_bytes", "wv_zfpk_max_bytes",
-           "wv_zfpk_encode", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_strerror",
+           "wv_zfpk_encode", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_predict", "wv_strerror",
            "wv_last_error", "wv_version", "wv_engine_create", "wv_engine_submit", "wv_engine_wait",
            "wv_engine_pending", "wv_engine_destroy"]
 
@@ -104,6 +119,7 @@ def lib():
         L.wv_schedule.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int32), sz, C.POINTER(C.c_size_t)]
         L.wv_schedule_forward_steps.argtypes = [C.c_int, C.c_int]
         L.wv_schedule_forward_steps.restype = C.c_long
+        L.wv_predict.argtypes = [C.c_int, C.c_longlong, sz, C.c_int, C.POINTER(WvCosts), C.POINTER(WvPrediction)]
         L.wv_strerror.argtypes = [C.c_int]
         L.wv_strerror.restype = C.c_char_p
         L.wv_version.restype = C.c_char_p
@@ -169,6 +185,23 @@ def schedule(nt: int, M: int) -> np.ndarray:
 
 def schedule_forward_steps(nt: int, M: int) -> int:
     return int(lib().wv_schedule_forward_steps(nt, M))
+
+
+def predict(nt: int, points: int, mem_budget: int, compressed: bool, c_f: float, c_r: float, t_copy: float = 0.0,
+            t_c: float = 0.0, t_d: float = 0.0, ratio: float = 1.0) -> dict:
+    """Predicted gradient time (ms) and counts for the given per-unit costs (host only)."""
+    costs = WvCosts(float(c_f), float(c_r), float(t_copy), float(t_c), float(t_d), float(ratio))
+    out = WvPrediction()
+    _check(lib().wv_predict(int(nt), int(points), int(mem_budget), 1 if compressed else 0, C.byref(costs),
+                            C.byref(out)), "wv_predict")
+    return out.as_dict()
+
+
+def costs_from_stats(st: dict) -> dict:
+    """Per-unit costs measured by a gradient call with timing (see wv_costs)."""
+    return {"c_f": st["ms_forward"] / max(1, st["advances"]), "c_r": st["ms_adjoint"] / max(1, st["reverses"]),
+            "t_store": st["ms_store"] / max(1, st["fields"]),
+            "t_d": st["ms_restore"] / st["decodes"] if st["decodes"] else 0.0, "ratio": st["ratio"]}
 
 
 def zfpk_max_bytes(ndim: int, dims) -> int:

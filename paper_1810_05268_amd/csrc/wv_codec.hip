@@ -289,7 +289,8 @@ __device__ __forceinline__ void load_block(const float *f, const float *sub, con
     }
 }
 
-constexpr int kLdsWords = 1024;   // chunk bitstreams up to 8 KB are assembled in LDS
+constexpr int kLdsWords = 1024;      // chunk bitstreams up to 8 KB are assembled in LDS
+constexpr int kDecLdsWords = 2048;   // and chunks up to 16 KB are staged in LDS for decoding
 
 template <int ND, bool VEC>
 __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
@@ -572,6 +573,7 @@ __global__ __launch_bounds__(256) void decode_kernel(DecArgs A)
 {
     constexpr int S = ND == 3 ? 64 : 16;
     __shared__ unsigned s_scan[256];
+    __shared__ unsigned long long s_words[kDecLdsWords];
     const int tid = threadIdx.x;
     const long long c = blockIdx.x;
     const long long b = c * kBlocksPerChunk + tid;
@@ -617,10 +619,23 @@ __global__ __launch_bounds__(256) void decode_kernel(DecArgs A)
         s_scan[tid] += add;
         __syncthreads();
     }
+    // The chunk's words are contiguous: stage them in LDS with one coalesced pass, so
+    // that each lane's sequential bit reads are LDS reads instead of a chain of
+    // dependent global loads.  Chunks too long for the buffer read global memory.
+    const long long cbase = (long long)chunk_off[c];
+    const long long cw = ((long long)s_scan[255] + 63) / 64 + 1;   // + the reader's look-ahead word
+    const bool staged = cw <= kDecLdsWords;
+    if (staged) {
+        for (long long i = tid; i < cw; i += 256) {
+            const long long j = cbase + i;
+            s_words[i] = (j >= 0 && j < nwords) ? data[j] : 0ull;
+        }
+    }
+    __syncthreads();
     if (!valid) return;
-    const long long pos = (long long)chunk_off[c] * 64 + (s_scan[tid] - nbits);
-    BitReader rd{data, nwords, 0, 0ull, 0ull, 0};
-    rd.init(pos);
+    const long long rel = (long long)(s_scan[tid] - nbits);
+    BitReader rd = staged ? BitReader{s_words, cw, 0, 0ull, 0ull, 0} : BitReader{data, nwords, 0, 0ull, 0ull, 0};
+    rd.init(staged ? rel : cbase * 64 + rel);
     float out[S];
     const bool coded = rd.peek() & 1ull;
     rd.skip(1);

@@ -205,6 +205,94 @@ struct Setup {
     std::vector<float> src_gwt, rec_gwt, src_swt, rec_swt;
 };
 
+// A reverse step k reads only u^k.  The second level u^{k-1} of a checkpoint is
+// needed only if the schedule advances from a restore of it: flag those STORE actions
+// (by action index) so that only they write, and their restores only then decode, it.
+std::vector<char> second_level_needed(const std::vector<int32_t> &acts, int M)
+{
+    const size_t nact = acts.size() / 3;
+    std::vector<char> need2(nact, 0);
+    std::vector<long> holder((size_t)M + 2, -1);   // slot -> index of the STORE that filled it
+    for (size_t i = 0; i < nact; ++i) {
+        const int op = acts[3 * i], b = acts[3 * i + 2];
+        if (op == STORE && b >= 0 && b <= M) holder[b] = (long)i;
+        if (op == RESTORE && b > 0 && b <= M && holder[b] >= 0) {
+            size_t j = i + 1;
+            while (j < nact && acts[3 * j] == FREE) ++j;
+            if (j >= nact || acts[3 * j] != REVERSE) need2[holder[b]] = 1;
+        }
+    }
+    return need2;
+}
+
+// What the executor does for a schedule, without a device: the counts that price it.
+struct DryRun {
+    long advances = 0, stores = 0, fields = 0, restores = 0, decodes = 0, reverses = 0;
+};
+
+DryRun dry_run(const std::vector<int32_t> &acts, int M, bool compressed)
+{
+    DryRun r;
+    const std::vector<char> need2 = second_level_needed(acts, M);
+    std::vector<char> slot2((size_t)M + 2, 0);
+    int hot_slot = -1, hot_k = -1, pend_slot = -1;
+    bool hot_db = false, pending = false;
+    for (size_t i = 0; i < acts.size() / 3; ++i) {
+        const int op = acts[3 * i], a = acts[3 * i + 1], b = acts[3 * i + 2];
+        switch (op) {
+        case ADVANCE:
+            if (pending) {
+                if (compressed && !hot_db) {
+                    ++r.decodes;
+                    hot_db = true;
+                }
+                pending = false;
+            }
+            r.advances += b - a;
+            break;
+        case STORE:
+            slot2[b] = need2[i];
+            r.fields += need2[i] ? 2 : 1;
+            ++r.stores;
+            if (hot_slot == b) hot_slot = -1;
+            break;
+        case RESTORE:
+            pending = false;
+            if (b > 0) {
+                if (compressed && (hot_slot != b || hot_k != a)) {
+                    ++r.decodes;
+                    hot_slot = b;
+                    hot_k = a;
+                    hot_db = false;
+                }
+                pending = slot2[b] != 0;
+                pend_slot = b;
+            }
+            ++r.restores;
+            break;
+        case REVERSE:
+            ++r.reverses;
+            break;
+        default:
+            break;
+        }
+    }
+    (void)pend_slot;
+    return r;
+}
+
+// Checkpoint slots M (x_0 included) for a budget: uncompressed slots hold S bytes; a
+// compressed slot S / F plus the 256-byte alignment of its two streams (F is a ratio of
+// whole streams, prefixes included).  0 if not even one slot fits (and nt > 1).
+int plan_slots(int nt, size_t mem_budget, size_t S, bool compressed, double F)
+{
+    size_t slot_bytes = compressed ? (size_t)((double)S / F) + 512 : S;
+    if (slot_bytes < 1) slot_bytes = 1;
+    const size_t nslots = mem_budget / slot_bytes;
+    if (nslots < 1 && nt > 1) return 0;
+    return std::max(1, (int)std::min<size_t>((size_t)nt, nslots + 1));
+}
+
 int validate_model(const wv_model *m, Setup &su)
 {
     if (!m || (m->ndim != 2 && m->ndim != 3)) return WV_EINVAL;
@@ -646,6 +734,32 @@ long wv_schedule_forward_steps(int nt, int M)
     return (long)forward_steps(nt, M);
 }
 
+int wv_predict(int nt, long long points, size_t mem_budget, int compressed, const wv_costs *costs,
+               wv_prediction *out)
+{
+    if (nt < 1 || points < 1 || !costs || !out) return WV_EINVAL;
+    if (compressed && !(costs->ratio > 0)) return WV_EINVAL;
+    const size_t S = (size_t)points * 8;
+    const int M = plan_slots(nt, mem_budget, S, compressed != 0, compressed ? costs->ratio : 1.0);
+    if (M < 1) return WV_EBUDGET;
+    std::vector<int32_t> acts;
+    make_schedule(nt, M, acts);
+    const DryRun r = dry_run(acts, M, compressed != 0);
+    std::memset(out, 0, sizeof(*out));
+    out->slots = M;
+    out->advances = r.advances;
+    out->stores = r.stores;
+    out->fields = r.fields;
+    out->decodes = r.decodes;
+    out->ms_forward = costs->c_f * (double)r.advances;
+    out->ms_adjoint = costs->c_r * (double)r.reverses;
+    out->ms_store = (compressed ? costs->t_c : costs->t_copy) * (double)r.fields;
+    out->ms_restore = compressed ? costs->t_d * (double)r.decodes : 0.0;
+    out->ms_total = out->ms_forward + out->ms_adjoint + out->ms_store + out->ms_restore;
+    out->ms_full_storage = (costs->c_f + costs->c_r) * (double)nt;
+    return WV_OK;
+}
+
 int wv_schedule(int nt, int M, int32_t *actions, size_t cap, size_t *n_actions)
 {
     if (nt < 0 || M < 1 || !n_actions) return WV_EINVAL;
@@ -763,22 +877,7 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
     const bool comp = R.tol > 0;
     const size_t fb = (size_t)P * 4;
     const size_t nact = acts.size() / 3;
-    // A reverse step k reads only u^k.  The second level u^{k-1} of a checkpoint is
-    // needed only if the schedule advances from a restore of it; scan the list once and
-    // store (and later decode) that level only for those checkpoints.
-    std::vector<char> need2(nact, 0);
-    {
-        std::vector<long> holder((size_t)M + 2, -1);   // slot -> index of the STORE that filled it
-        for (size_t i = 0; i < nact; ++i) {
-            const int op = acts[3 * i], b = acts[3 * i + 2];
-            if (op == STORE && b >= 0 && b <= M) holder[b] = (long)i;
-            if (op == RESTORE && b > 0 && b <= M && holder[b] >= 0) {
-                size_t j = i + 1;
-                while (j < nact && acts[3 * j] == FREE) ++j;
-                if (j >= nact || acts[3 * j] != REVERSE) need2[holder[b]] = 1;
-            }
-        }
-    }
+    const std::vector<char> need2 = second_level_needed(acts, M);
     std::vector<char> slot2((size_t)M + 2, 0);   // slot holds both levels
     bool up_pending = false;                    // restored state: u^{k-1} not decoded yet
     bool hot_db = false;                        // DB holds u^{k-1} of the hot checkpoint
@@ -917,6 +1016,7 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
         stats->ms_adj_kernel = kern_ms[1];
         stats->advances = R.advances;
         stats->stores = R.stores;
+        stats->fields = R.fields;
         stats->restores = R.restores;
         stats->decodes = R.decodes;
         stats->reverses = R.reverses;
@@ -1003,14 +1103,9 @@ int gradient_common(const wv_model *m, const wv_geom *geo, const float *residual
     // optimistic) is repeated with half the planned ratio, i.e. fewer slots; the last
     // attempt plans with the uncompressed size, which always fits.
     for (int attempt = 0;; ++attempt) {
-        // a compressed slot: S / F (F is a ratio of whole streams, prefixes included) plus
-        // the 256-byte alignment of its two streams
-        size_t slot_bytes = tol > 0 ? (size_t)((double)R.S / F) + 512 : R.S;
-        if (slot_bytes < 1) slot_bytes = 1;
-        const size_t nslots = mem_budget / slot_bytes;
-        if (nslots < 1 && N > 1) return WV_EBUDGET;
-        const int M = (int)std::min<size_t>((size_t)N, nslots + 1);
-        rc = run_gradient(R, std::max(M, 1), F, stats, misfit);
+        const int M = plan_slots(N, mem_budget, R.S, tol > 0, F);
+        if (M < 1) return WV_EBUDGET;
+        rc = run_gradient(R, M, F, stats, misfit);
         if (rc != WV_EARENA || tol <= 0 || F <= 1.0 || attempt >= kArenaRetries) {
             if (stats) stats->retries = attempt;
             return rc;

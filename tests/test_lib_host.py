@@ -100,3 +100,65 @@ def test_cfl_violation_reported_before_device_work():
     pb = host_problem(dt_factor=1.05)
     rc = lib().wv_forward(C.byref(pb.model), C.byref(pb.geom), None, None, None, 0, None)
     assert rc == B.WV_ECFL
+
+
+# ------------------------------------------------------------------ performance model
+
+def _second_level_stores(acts):
+    """Stores whose checkpoint is later restored and then advanced from (written from
+    the action list here, independently of the library)."""
+    acts = [tuple(a) for a in acts]
+    need, holder = set(), {}
+    for i, (op, a, b) in enumerate(acts):
+        if op == 2:
+            holder[b] = i
+        if op == 3 and b > 0:
+            j = i + 1
+            while j < len(acts) and acts[j][0] == 4:
+                j += 1
+            if j >= len(acts) or acts[j][0] != 5:
+                need.add(holder[b])
+    return need, sum(1 for op, _, _ in acts if op == 2)
+
+
+@pytest.mark.parametrize("N,M", [(500, 10), (1000, 21), (3000, 32), (3000, 1569), (200, 200)])
+def test_predict_counts_match_the_schedule(N, M):
+    import paper_1810_05268_amd as P
+    from oracle import schedule as SC
+    points = 10_000
+    S = 8 * points
+    pr = P.predict(N, points, (M - 1) * S, False, 1.0, 2.0, t_copy=0.5)
+    assert pr["slots"] == M
+    assert pr["advances"] == SC.p_closed(N + 1, M)
+    need, stores = _second_level_stores(SC.schedule(N, M))
+    assert pr["stores"] == stores
+    assert pr["fields"] == stores + len(need)
+    assert pr["ms_total"] == pytest.approx(1.0 * pr["advances"] + 2.0 * N + 0.5 * pr["fields"])
+    assert pr["ms_full_storage"] == pytest.approx(3.0 * N)
+
+
+def test_predict_compressed_slots_and_decodes():
+    import paper_1810_05268_amd as P
+    N, points, F = 3000, 64_000_000, 50.0
+    S = 8 * points
+    budget = int(16e9)
+    pr = P.predict(N, points, budget, True, 0.25, 0.57, t_c=0.14, t_d=0.08, ratio=F)
+    assert pr["slots"] == min(N, 1 + budget // (int(S / F) + 512))
+    # with every state stored, each reverse step restores its own checkpoint: one decode
+    # per restore except the zero state, and no advance ever follows a restore
+    full = P.predict(N, points, budget, True, 0.25, 0.57, t_c=0.14, t_d=0.08, ratio=1000.0)
+    assert full["slots"] == N and full["advances"] == N
+    assert full["decodes"] == N - 1 and full["fields"] == full["stores"] == N - 1
+    assert full["ms_total"] == pytest.approx(0.25 * N + 0.57 * N + 0.14 * (N - 1) + 0.08 * (N - 1))
+    # more memory never predicts more forward steps
+    a = [P.predict(N, points, int(b), True, 0.25, 0.57, t_c=0.14, t_d=0.08, ratio=F)["advances"]
+         for b in (2e9, 4e9, 8e9, 16e9)]
+    assert a == sorted(a, reverse=True)
+
+
+def test_predict_rejects_bad_input():
+    import paper_1810_05268_amd as P
+    with pytest.raises(P.WvError):
+        P.predict(100, 1000, 10, False, 1.0, 1.0)          # not one slot fits
+    with pytest.raises(P.WvError):
+        P.predict(100, 1000, 10**9, True, 1.0, 1.0, ratio=0.0)
