@@ -386,6 +386,13 @@ def main():
     ms_per_decode = st["ms_restore"] / st["decodes"] if st["decodes"] else None
 
     model = performance_model(shot.nt, Pn, budget, st_plain[0], st_comp[0], hint, sweep_stats)
+    # compressibility over time at the headline tolerance (untimed)
+    stride = max(1, shot.nt // 10)
+    cb = G.compressibility(args.tol, stride)
+    compressibility = {"tol": args.tol, "steps": [(i + 1) * stride for i in range(len(cb))],
+                       "ratio": [4.0 * Pn / b for b in cb]}
+    log("compressibility (ratio of u^n): " + ", ".join(f"{n}:{r:.0f}" for n, r in
+                                                         zip(compressibility["steps"], compressibility["ratio"])))
 
     ms_step = 1e3 * statistics.mean(w_comp)
     value = Pn * 2 * shot.nt / (ms_step * 1e-3) / 1e9
@@ -414,6 +421,7 @@ def main():
         "misfit": {"compressed": phi_comp, "plain": phi_plain},
         "sweep": sweep,
         "model": model,
+        "compressibility": compressibility,
         "roofline": roof,
     }
     if args.serving_requests > 0 and not args.quick:

@@ -123,6 +123,7 @@ double wv_cfl_dt(int ndim, const double *h, int space_order, double vmax);
 /* Operation selectors for wv_workspace_bytes. */
 #define WV_OP_FORWARD 0
 #define WV_OP_GRADIENT 1
+#define WV_OP_COMPRESSIBILITY 2   /* wv_compressibility (mem_budget ignored) */
 
 /* Workspace bytes needed by wv_forward (op = WV_OP_FORWARD, mem_budget ignored)
  * or by wv_gradient / wv_misfit_gradient / wv_adjoint_src (op = WV_OP_GRADIENT;
@@ -277,6 +278,17 @@ int wv_schedule(int nt, int M, int32_t *actions, size_t cap, size_t *n_actions);
 /* Forward steps of that schedule: t(nt+1, M) = r (nt+1) - C(M+1+r-1, r-1),
  * r = min{r : C(M+r, r) >= nt+1}. */
 long wv_schedule_forward_steps(int nt, int M);
+
+/* Compressibility over time: the paper studies how the compression ratio of the
+ * wavefield changes with the time step (Sec. "Results and discussion": early states,
+ * with little energy spread, compress far better; the last state is the worst case).
+ * Runs the forward problem and, after every `stride` steps, encodes u^n with the
+ * codec at tol; bytes[i] receives the stream size of u^{(i+1) stride} (header and
+ * block lengths included; the uncompressed field is 4 P bytes).  *count receives
+ * nt / stride; WV_ECAP if that exceeds cap.  ws: wv_workspace_bytes(...,
+ * WV_OP_COMPRESSIBILITY, 0) bytes.  Synchronises the stream after every sample. */
+int wv_compressibility(const wv_model *model, const wv_geom *geom, double tol, int stride, size_t *bytes,
+                       int cap, int *count, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------ performance model
  * The run-time model of Sec. "Checkpointing performance model" (eqs. (1)-(5)) and

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libwv.so")
 WV_OK, WV_EINVAL, WV_ECFL, WV_EBUDGET, WV_EARENA, WV_ENOMEM, WV_EHIP, WV_EUNSTABLE, WV_ENOTIMPL, WV_ECAP = (
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
 WV_ETIMEOUT = -10
-OP_FORWARD, OP_GRADIENT = 0, 1
+OP_FORWARD, OP_GRADIENT, OP_COMPRESSIBILITY = 0, 1, 2
 ADVANCE, STORE, RESTORE, FREE, REVERSE = 1, 2, 3, 4, 5
 
 
@@ -81,7 +81,7 @@ class WvResult(C.Structure):
 # every symbol include/wv.h declares
 SYMBOLS = ["wv_cfl_dt", "wv_workspace_bytes", "wv_forward", "wv_gradient", "wv_misfit_gradient", "wv_adjoint_src",
            "wv_pad_velocity", "wv_velocity_gradient", "wv_zfpk_workspace_bytes", "wv_zfpk_max_bytes",
-           "wv_zfpk_encode", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_predict", "wv_strerror",
+           "wv_zfpk_encode", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_predict", "wv_compressibility", "wv_strerror",
            "wv_last_error", "wv_version", "wv_engine_create", "wv_engine_submit", "wv_engine_wait",
            "wv_engine_pending", "wv_engine_destroy"]
 
@@ -120,6 +120,8 @@ def lib():
         L.wv_schedule_forward_steps.argtypes = [C.c_int, C.c_int]
         L.wv_schedule_forward_steps.restype = C.c_long
         L.wv_predict.argtypes = [C.c_int, C.c_longlong, sz, C.c_int, C.POINTER(WvCosts), C.POINTER(WvPrediction)]
+        L.wv_compressibility.argtypes = [mp, gp, C.c_double, C.c_int, C.POINTER(C.c_size_t), C.c_int,
+                                         C.POINTER(C.c_int), vp, sz, vp]
         L.wv_strerror.argtypes = [C.c_int]
         L.wv_strerror.restype = C.c_char_p
         L.wv_version.restype = C.c_char_p
@@ -185,6 +187,17 @@ def schedule(nt: int, M: int) -> np.ndarray:
 
 def schedule_forward_steps(nt: int, M: int) -> int:
     return int(lib().wv_schedule_forward_steps(nt, M))
+
+
+def compressibility(pb: Problem, tol: float, stride: int, ws, stream=None) -> list:
+    """Stream bytes of u^n for n = stride, 2 stride, ... (see wv_compressibility)."""
+    cap = pb.nt // stride
+    out = (C.c_size_t * max(1, cap))()
+    n = C.c_int(0)
+    _check(lib().wv_compressibility(C.byref(pb.model), C.byref(pb.geom), float(tol), int(stride), out, cap,
+                                    C.byref(n), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
+           "wv_compressibility")
+    return [int(out[i]) for i in range(n.value)]
 
 
 def predict(nt: int, points: int, mem_budget: int, compressed: bool, c_f: float, c_r: float, t_copy: float = 0.0,

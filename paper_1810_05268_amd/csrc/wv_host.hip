@@ -449,6 +449,13 @@ size_t tab_bytes(const Setup &su, bool rec)
            align_up(ne * 4, 256) * 2;
 }
 
+// Largest stream one wavefield can take (the arena of a compressibility run).
+size_t field_stream_max(const Setup &su)
+{
+    const int cdims[3] = {su.g.nx, su.ndim == 3 ? su.g.ny : su.g.nz, su.ndim == 3 ? su.g.nz : 1};
+    return codec_max_bytes(codec_dims(su.ndim, cdims)) + 256;
+}
+
 Layout plan_layout(const wv_model *m, const wv_geom *geo, const Setup &su, int op, size_t budget)
 {
     Layout L{};
@@ -775,6 +782,7 @@ size_t wv_workspace_bytes(const wv_model *m, const wv_geom *geo, int op, size_t 
 {
     Setup su;
     if (prepare(m, geo, su)) return 0;
+    if (op == WV_OP_COMPRESSIBILITY) return plan_layout(m, geo, su, WV_OP_GRADIENT, field_stream_max(su)).total;
     if (op != WV_OP_FORWARD && op != WV_OP_GRADIENT) return 0;
     return plan_layout(m, geo, su, op, mem_budget).total;
 }
@@ -1155,6 +1163,46 @@ int wv_adjoint_src(const wv_model *m, const wv_geom *geo, const float *residual,
     R.src_adj = src_adj;
     R.S = (size_t)su.P * 8;
     return run_gradient(R, 1, 1.0, nullptr, nullptr);
+}
+
+int wv_compressibility(const wv_model *m, const wv_geom *geo, double tol, int stride, size_t *bytes, int cap,
+                       int *count, void *ws, size_t ws_bytes, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    Setup su;
+    int rc = prepare(m, geo, su);
+    if (rc) return rc;
+    if (!(tol > 0) || !std::isfinite(tol) || stride < 1 || !bytes || !count || cap < 0) return WV_EINVAL;
+    const int nsamp = m->nt / stride;
+    if (nsamp > cap) return WV_ECAP;
+    const Layout L = plan_layout(m, geo, su, WV_OP_GRADIENT, field_stream_max(su));
+    Dev d{};
+    if ((rc = bind(d, ws, ws_bytes, L, WV_OP_GRADIENT))) return rc;
+    if ((rc = start(d, m, su, s))) return rc;
+    GradRun R{m, geo, su, d, s, tol, false, false};
+    const int cdims[3] = {su.g.nx, su.ndim == 3 ? su.g.ny : su.g.nz, su.ndim == 3 ? su.g.nz : 1};
+    R.cd = codec_dims(su.ndim, cdims);
+    R.S = (size_t)su.P * 8;
+    Fwd f{d, su, geo, s};
+    f.at(d.Z, d.Z);
+    int k = 0;
+    for (int n = 0; n < m->nt; ++n) {
+        if ((rc = f.step(n, nullptr))) return rc;
+        if ((n + 1) % stride == 0) {
+            // encode u^{n+1} at the start of the arena; its header holds the stream size
+            HIPCHK(launch_fill_u64(d.offs, 2, 0, s));
+            if ((rc = R.encode_field(f.u, nullptr, d.offs, d.offs + 1))) return rc;
+            uint64_t tot = 0;
+            HIPCHK(hipMemcpyAsync(&tot, d.arena + 56, sizeof(tot), hipMemcpyDeviceToHost, s));
+            unsigned e = 0;
+            if ((rc = read_err(d, s, &e))) return rc;
+            if (e & 2u) return WV_EUNSTABLE;
+            if (e) return WV_EHIP;
+            bytes[k++] = (size_t)tot;
+        }
+    }
+    *count = k;
+    return WV_OK;
 }
 
 int wv_pad_velocity(int ndim, const int *n, int nbl, const float *vin, float *vout, void *stream)

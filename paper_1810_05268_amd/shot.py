@@ -68,6 +68,10 @@ class DeviceShot:
         B.adjoint_src(self.pb, residual, out, self.workspace(B.OP_GRADIENT, 0))
         return out
 
+    def compressibility(self, tol: float, stride: int) -> list:
+        """Stream bytes of u^n every `stride` steps of a forward run (wv_compressibility)."""
+        return B.compressibility(self.pb, tol, stride, self.workspace(B.OP_COMPRESSIBILITY))
+
     def checkpoint_bytes(self) -> int:
         """Bytes of one uncompressed checkpoint (two binary32 fields)."""
         return 8 * self.P
