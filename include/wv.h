@@ -55,7 +55,7 @@ extern "C" {
 #define WV_OK 0
 #define WV_EINVAL (-1)     /* bad argument, dims, geometry, non-finite or out-of-range velocity */
 #define WV_ECFL (-2)       /* dt above the stability limit wv_cfl_dt */
-#define WV_EBUDGET (-3)    /* mem_budget below one checkpoint */
+#define WV_EBUDGET (-3)    /* memory too small: an engine request whose workspace exceeds the whole pool */
 #define WV_EARENA (-4)     /* compressed checkpoints overflowed mem_budget even after the retries (the gradient
                               calls re-plan with half the ratio, up to three times, the last time uncompressed-sized) */
 #define WV_ENOMEM (-5)     /* workspace too small */
@@ -144,7 +144,10 @@ int wv_forward(const wv_model *model, const wv_geom *geom, float *data, float *s
  * reversed with Revolve checkpointing inside mem_budget bytes of checkpoint memory.
  *   residual    device [nt+1][nrec] float (row 0 unused)
  *   mem_budget  bytes available for checkpoints (SI bytes); the slot count is
- *               M = min(nt, 1 + floor(mem_budget / (S / F + 512))), S = 8 P bytes per
+ *               M = min(nt, 1 + floor(mem_budget / slot)), the 1 being x_0 (the zero
+ *               state, which takes no memory; a budget below one checkpoint gives M = 1,
+ *               recomputation from x_0 alone); slot = S uncompressed, S / F + 512
+ *               compressed (two 256-byte aligned streams), S = 8 P bytes per
  *               uncompressed checkpoint (u^k and u^{k-1}; compressed, the pair is
  *               stored as u^k and the increment u^k - u^{k-1}),
  *               F = 1 if tol == 0, else ratio_hint if > 0, else the ratio measured
@@ -320,7 +323,7 @@ typedef struct {
 
 /* Predicted gradient time for nt steps on a grid of `points` padded points with
  * mem_budget bytes of checkpoint memory, uncompressed (compressed = 0) or compressed.
- * Host only.  WV_EBUDGET if not one slot fits. */
+ * Host only.  A budget below one checkpoint gives M = 1 (recomputation from x_0). */
 int wv_predict(int nt, long long points, size_t mem_budget, int compressed, const wv_costs *costs,
                wv_prediction *out);
 

@@ -281,15 +281,15 @@ DryRun dry_run(const std::vector<int32_t> &acts, int M, bool compressed)
     return r;
 }
 
-// Checkpoint slots M (x_0 included) for a budget: uncompressed slots hold S bytes; a
-// compressed slot S / F plus the 256-byte alignment of its two streams (F is a ratio of
-// whole streams, prefixes included).  0 if not even one slot fits (and nt > 1).
+// Checkpoint slots M for a budget: x_0 (the zero state, no memory) plus as many stored
+// states as fit; uncompressed slots hold S bytes, a compressed slot S / F plus the
+// 256-byte alignment of its two streams (F is a ratio of whole streams, prefixes
+// included).  M = 1 (a budget below one checkpoint) is recomputation from x_0 alone.
 int plan_slots(int nt, size_t mem_budget, size_t S, bool compressed, double F)
 {
     size_t slot_bytes = compressed ? (size_t)((double)S / F) + 512 : S;
     if (slot_bytes < 1) slot_bytes = 1;
     const size_t nslots = mem_budget / slot_bytes;
-    if (nslots < 1 && nt > 1) return 0;
     return std::max(1, (int)std::min<size_t>((size_t)nt, nslots + 1));
 }
 
@@ -713,7 +713,7 @@ const char *wv_strerror(int code)
     case WV_OK: return "ok";
     case WV_EINVAL: return "invalid argument";
     case WV_ECFL: return "time step above the stability limit";
-    case WV_EBUDGET: return "memory budget below one checkpoint";
+    case WV_EBUDGET: return "memory budget too small";
     case WV_EARENA: return "compressed checkpoints overflowed the memory budget";
     case WV_ENOMEM: return "workspace too small";
     case WV_EHIP: return "HIP runtime error";

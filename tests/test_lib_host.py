@@ -156,9 +156,12 @@ def test_predict_compressed_slots_and_decodes():
     assert a == sorted(a, reverse=True)
 
 
-def test_predict_rejects_bad_input():
+def test_predict_rejects_bad_input_and_budget_below_one_checkpoint_is_one_slot():
     import paper_1810_05268_amd as P
     with pytest.raises(P.WvError):
-        P.predict(100, 1000, 10, False, 1.0, 1.0)          # not one slot fits
-    with pytest.raises(P.WvError):
         P.predict(100, 1000, 10**9, True, 1.0, 1.0, ratio=0.0)
+    with pytest.raises(P.WvError):
+        P.predict(0, 1000, 10**9, False, 1.0, 1.0)
+    # x_0 is the zero state and takes no memory: recomputation from it alone
+    pr = P.predict(100, 1000, 10, False, 1.0, 1.0)
+    assert pr["slots"] == 1 and pr["advances"] == 100 * 101 // 2 and pr["stores"] == 0
