@@ -38,7 +38,8 @@ def build(force: bool = False) -> str:
 
 class _Model(C.Structure):
     _fields_ = [("ndim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double * 3), ("nbl", C.c_int),
-                ("order", C.c_int), ("nt", C.c_int), ("dt", C.c_double), ("vmax", C.c_double)]
+                ("order", C.c_int), ("nt", C.c_int), ("dt", C.c_double), ("vmax", C.c_double),
+                ("time_order", C.c_int)]
 
 
 def _dp(a):
@@ -54,6 +55,8 @@ def lib():
         L.or_fd_coeffs.argtypes = [C.c_int, dp]
         L.or_cfl_dt.argtypes = [C.c_int, dp, C.c_int, C.c_double]
         L.or_cfl_dt.restype = C.c_double
+        L.or_cfl_dt_to.argtypes = [C.c_int, dp, C.c_int, C.c_double, C.c_int]
+        L.or_cfl_dt_to.restype = C.c_double
         L.or_create.argtypes = [C.POINTER(_Model), dp, C.c_int, dp, dp, C.c_int, dp, C.c_int, ip]
         L.or_create.restype = vp
         L.or_destroy.argtypes = [vp]
@@ -111,10 +114,13 @@ def fd_coeffs(K: int) -> np.ndarray:
     return a
 
 
-def cfl_dt(ndim: int, h, order: int, vmax: float) -> float:
+def cfl_dt(ndim: int, h, order: int, vmax: float, time_order: int = 2) -> float:
+    """Stability limit of the leapfrog (OT2) or modified-equation (OT4) scheme."""
     hh = np.zeros(3)
     hh[:ndim] = h[:ndim]
-    return lib().or_cfl_dt(ndim, _dp(hh), order, vmax)
+    if time_order == 2:
+        return lib().or_cfl_dt(ndim, _dp(hh), order, vmax)
+    return lib().or_cfl_dt_to(ndim, _dp(hh), order, vmax, time_order)
 
 
 @dataclass
@@ -127,6 +133,7 @@ class ModelSpec:
     nt: int
     dt: float
     vmax: float
+    time_order: int = 2     # 2: OT2 leapfrog; 4: OT4 modified-equation scheme
 
     def padded(self) -> tuple:
         return tuple(self.n[d] + 2 * self.nbl for d in range(self.ndim))
@@ -148,6 +155,7 @@ class Solver:
             m.n[d] = spec.n[d] if d < spec.ndim else 1
             m.h[d] = spec.h[d] if d < spec.ndim else 1.0
         m.nbl, m.order, m.nt, m.dt, m.vmax = spec.nbl, spec.order, spec.nt, spec.dt, spec.vmax
+        m.time_order = spec.time_order
         self._m = m
         self.vel = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1)
         self.src = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, spec.ndim)

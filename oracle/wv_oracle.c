@@ -29,7 +29,12 @@
  *   - time stepping residual
  *       E_n = m[(1+a)u^{n+1} - 2u^n + (1-a)u^{n-1}]/dt^2 - lap u^n - s^n = 0,
  *     u^0 = u^-1 = 0, data d^n = R u^n for n = 0..N;
- *   - multilinear source/receiver weights, no 1/h^d scaling.
+ *   - multilinear source/receiver weights, no 1/h^d scaling;
+ *   - OT4 (the paper's fourth-order-in-time kernel, Sec. "Problem and test case"):
+ *     the modified-equation scheme, which adds the dt^2/12 u_tttt correction of
+ *     the leapfrog and takes u_tttt from the PDE itself, so the spatial operator
+ *     becomes B(m) u = lap u + (dt^2/12) lap((1/m) lap u) in E_n (source and
+ *     damping as in OT2).
  */
 #include <math.h>
 #include <stdint.h>
@@ -65,7 +70,22 @@ void or_fd_coeffs(int K, double *a)
 }
 
 /* von Neumann limit of the leapfrog scheme with this star stencil:
- *   c dt sqrt(sum_a S/h_a^2) <= 2,  S = |a_0| + 2 sum_k |a_k|.               */
+ *   c dt sqrt(sum_a S/h_a^2) <= 2,  S = |a_0| + 2 sum_k |a_k|.
+ * With lam = c^2 dt^2 times the largest eigenvalue of -lap, OT2 needs lam <= 4;
+ * OT4 advances u^{n+1} = 2u^n - u^{n-1} - (lam - lam^2/12) u^n per mode, which is
+ * stable while 0 <= lam - lam^2/12 <= 4, i.e. lam <= 12: a limit sqrt(3) larger.   */
+double or_cfl_dt_to(int ndim, const double *h, int order, double vmax, int time_order)
+{
+    double a[9];
+    int K = order / 2;
+    or_fd_coeffs(K, a);
+    double S = fabs(a[0]);
+    for (int k = 1; k <= K; k++) S += 2.0 * fabs(a[k]);
+    double q = 0.0;
+    for (int d = 0; d < ndim; d++) q += S / (h[d] * h[d]);
+    return (time_order == 4 ? sqrt(12.0) : 2.0) / (vmax * sqrt(q));
+}
+
 double or_cfl_dt(int ndim, const double *h, int order, double vmax)
 {
     double a[9];
@@ -87,6 +107,7 @@ typedef struct {
     int nt;         /* number of time steps N */
     double dt;      /* seconds */
     double vmax;    /* m/s, sets the damping strength */
+    int time_order; /* 2 (OT2) or 4 (OT4); 0 means 2 */
 } or_model;
 
 typedef struct {
@@ -146,6 +167,7 @@ or_ctx *or_create(const or_model *m, const double *vel, int nsrc, const double *
     if (m->ndim != 2 && m->ndim != 3) return NULL;
     if (m->order < 2 || m->order > 16 || (m->order & 1)) return NULL;
     if (m->nbl < 0 || m->nt < 0 || !(m->dt > 0) || !(m->vmax > 0)) return NULL;
+    if (m->time_order != 0 && m->time_order != 2 && m->time_order != 4) return NULL;
     or_ctx *c = calloc(1, sizeof(or_ctx));
     if (!c) { *status = OR_ENOMEM; return NULL; }
     c->m = *m;
@@ -254,6 +276,23 @@ void or_laplacian(const or_ctx *c, const double *u, double *out)
             }
 }
 
+static int is_ot4(const or_ctx *c) { return c->m.time_order == 4; }
+
+/* out = B u: lap u for OT2; lap u + (1/12) lap(w lap u) for OT4, where
+ * w = dt^2/m, so that (1/12) lap(w lap u) = (dt^2/12) lap((1/m) lap u). */
+int or_apply_B(const or_ctx *c, const double *u, double *out)
+{
+    or_laplacian(c, u, out);
+    if (!is_ot4(c)) return OR_OK;
+    double *wl = malloc(sizeof(double) * c->P), *l2 = malloc(sizeof(double) * c->P);
+    if (!wl || !l2) { free(wl); free(l2); return OR_ENOMEM; }
+    for (long p = 0; p < c->P; p++) wl[p] = c->w[p] * out[p];
+    or_laplacian(c, wl, l2);
+    for (long p = 0; p < c->P; p++) out[p] += l2[p] / 12.0;
+    free(wl); free(l2);
+    return OR_OK;
+}
+
 /* Multilinear gather: val[r] = sum_c wt u[idx] */
 static void gather(const or_ctx *c, int which, const double *u, double *val)
 {
@@ -280,10 +319,11 @@ static void scatter(const or_ctx *c, int which, const double *val, double *f)
 }
 
 /* One forward step, eq. (7) discretised: given u^n (cur) and u^{n-1} (prev),
- * solve E_n = 0 for u^{n+1} and write it to next. lap is scratch [P]. */
+ * solve E_n = 0 for u^{n+1} and write it to next. lap is scratch [P].
+ *   E_n = m[(1+a)u^{n+1} - 2u^n + (1-a)u^{n-1}]/dt^2 - B u^n - s^n           */
 void or_forward_step(const or_ctx *c, int n, const double *cur, const double *prev, double *next, double *lap)
 {
-    or_laplacian(c, cur, lap);
+    or_apply_B(c, cur, lap);
     double q = c->wavelet[n];
     double qv[64];
     for (int s = 0; s < c->nsrc && s < 64; s++) qv[s] = q;
@@ -336,12 +376,13 @@ double or_misfit(long n, const double *dsim, const double *dobs)
 }
 
 /* One adjoint step k (k = N..1): the transpose of the forward recursion,
- *   lam^{k-1} = [2 lam^k - (1-a) lam^{k+1} + w (lap lam^k + R^T r^k)] / (1+a).
+ *   lam^{k-1} = [2 lam^k - (1-a) lam^{k+1} + w (B lam^k + R^T r^k)] / (1+a)
+ * (B is symmetric: lap is, with the zero halo, and w is diagonal).
  * res_k is residual row k.  Writes lam^{k-1} to out.  lap is scratch [P].   */
 void or_adjoint_step(const or_ctx *c, const double *res_k, const double *lam_k, const double *lam_kp1,
                      double *out, double *lap)
 {
-    or_laplacian(c, lam_k, lap);
+    or_apply_B(c, lam_k, lap);
     scatter(c, 1, res_k, lap);
 #pragma omp parallel for schedule(static) num_threads(c->nthreads)
     for (long p = 0; p < c->P; p++) {
@@ -350,8 +391,25 @@ void or_adjoint_step(const or_ctx *c, const double *res_k, const double *lam_k, 
     }
 }
 
+/* OT4 only: the part of the gradient from the m in B(m),
+ *   d/dm [lam . (dt^2/12) lap((1/m) lap u)] = -(dt^2/12)(1/m^2) (lap lam)(lap u),
+ * which enters E_n with a minus sign; with w = dt^2/m it is (w^2/12)(lap lam)(lap u)
+ * (scaled by -1/dt^2 at the end like the rest). */
+static int grad_accum_B(const or_ctx *c, const double *u, const double *lam, double *g)
+{
+    if (!is_ot4(c)) return OR_OK;
+    double *lu = malloc(sizeof(double) * c->P), *ll = malloc(sizeof(double) * c->P);
+    if (!lu || !ll) { free(lu); free(ll); return OR_ENOMEM; }
+    or_laplacian(c, u, lu);
+    or_laplacian(c, lam, ll);
+    for (long p = 0; p < c->P; p++) g[p] += c->w[p] * c->w[p] / 12.0 * ll[p] * lu[p];
+    free(lu); free(ll);
+    return OR_OK;
+}
+
 /* gradient contribution of reverse step k:
- *   g += u^k * [(1+a) lam^{k-1} - 2 lam^k + (1-a) lam^{k+1}]   (scaled by -1/dt^2 at the end) */
+ *   g += u^k * [(1+a) lam^{k-1} - 2 lam^k + (1-a) lam^{k+1}]
+ *        (+ (w^2/12)(lap lam^k)(lap u^k) for OT4)   (scaled by -1/dt^2 at the end) */
 static void grad_accum(const or_ctx *c, const double *uk, const double *lkm1, const double *lk,
                        const double *lkp1, double *g)
 {
@@ -360,6 +418,7 @@ static void grad_accum(const or_ctx *c, const double *uk, const double *lkm1, co
         double a = c->damp[p];
         g[p] += uk[p] * ((1.0 + a) * lkm1[p] - 2.0 * lk[p] + (1.0 - a) * lkp1[p]);
     }
+    grad_accum_B(c, uk, lk, g);
 }
 
 static void grad_finish(const or_ctx *c, double *g)
@@ -395,7 +454,8 @@ int or_gradient_full(const or_ctx *c, const double *traj, const double *residual
 /* The same gradient written as the derivative of the discrete Lagrangian
  * with respect to m (sum over the forward residuals E_n, n = 0..N-1):
  *   g_m = -(1/dt^2) sum_n lam^n [(1+a) u^{n+1} - 2 u^n + (1-a) u^{n-1}],
- * u^{-1} = 0.  Used to pin the summation-by-parts identity.               */
+ * u^{-1} = 0 (plus the OT4 term at the same n).  Used to pin the
+ * summation-by-parts identity.                                            */
 void or_gradient_nform(const or_ctx *c, const double *traj, const double *lam_all, double *grad)
 {
     long P = c->P;
@@ -410,6 +470,7 @@ void or_gradient_nform(const or_ctx *c, const double *traj, const double *lam_al
             double um = unm1 ? unm1[p] : 0.0;
             grad[p] += ln[p] * ((1.0 + a) * un1[p] - 2.0 * un[p] + (1.0 - a) * um);
         }
+        grad_accum_B(c, un, ln, grad);
     }
     grad_finish(c, grad);
 }
