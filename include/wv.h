@@ -29,6 +29,16 @@
  *       g = -(1/dt^2) sum_{k=1..nt} u^k [(1+a)lam^{k-1} - 2lam^k + (1-a)lam^{k+1}]
  *     with the discrete adjoint lam (exact transpose of the recursion above).
  *
+ * OT4 (time_order = 4): the paper's fourth-order-in-time kernel (Sec. "Problem and
+ * test case" names it without formulas), read as the modified-equation scheme: the
+ * spatial term lap u^n of the step becomes
+ *   B u^n = lap u^n + (dt^2/12) lap((1/m) lap u^n),
+ * i.e. u^{n+1} = [2u^n - (1-a)u^{n-1} + w lap u^n + (w/12) lap(w lap u^n) + w s^n]/(1+a),
+ * w = c^2 dt^2; the adjoint is the same recursion (B is symmetric), and the gradient
+ * gains the term from the m inside B:
+ *   g += -(1/dt^2) sum_k (w^2/12) (lap lam^k)(lap u^k).
+ * Stability: sqrt(3) times the OT2 limit (wv_cfl_dt_to).
+ *
  * Precision: wavefields are binary32; the gradient accumulates in binary64;
  * misfit and other reductions are binary64.
  *
@@ -75,6 +85,7 @@ typedef struct {
     double dt;           /* time step, seconds; must satisfy dt <= wv_cfl_dt(...) */
     double vmax;         /* m/s: upper bound of vel; sets the damping strength and CFL check */
     const float *vel;    /* device [P] padded velocity, m/s, 0 < vel <= vmax */
+    int time_order;      /* 2 (or 0): the OT2 leapfrog; 4: the OT4 kernel, see below */
 } wv_model;
 
 typedef struct {
@@ -119,6 +130,11 @@ typedef struct {
  *   dt_max = 2 / (vmax sqrt(sum_a S / h[a]^2)),  S = |a_0| + 2 sum_k |a_k|.
  * Host only; returns <= 0 on bad arguments. */
 double wv_cfl_dt(int ndim, const double *h, int space_order, double vmax);
+
+/* The same limit for a time order: 2 as wv_cfl_dt; 4 (OT4): sqrt(3) times it, since
+ * the OT4 step advances each mode with lam - lam^2/12 in place of lam = c^2 dt^2 times
+ * its eigenvalue of -lap, which stays in [0, 4] while lam <= 12.  <= 0 on bad arguments. */
+double wv_cfl_dt_to(int ndim, const double *h, int space_order, double vmax, int time_order);
 
 /* Operation selectors for wv_workspace_bytes. */
 #define WV_OP_FORWARD 0

@@ -38,7 +38,7 @@ class WvError(RuntimeError):
 class WvModel(C.Structure):
     _fields_ = [("ndim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double * 3), ("nbl", C.c_int),
                 ("space_order", C.c_int), ("nt", C.c_int), ("dt", C.c_double), ("vmax", C.c_double),
-                ("vel", C.c_void_p)]
+                ("vel", C.c_void_p), ("time_order", C.c_int)]
 
 
 class WvGeom(C.Structure):
@@ -79,7 +79,7 @@ class WvResult(C.Structure):
 
 
 # every symbol include/wv.h declares
-SYMBOLS = ["wv_cfl_dt", "wv_workspace_bytes", "wv_forward", "wv_gradient", "wv_misfit_gradient", "wv_adjoint_src",
+SYMBOLS = ["wv_cfl_dt", "wv_cfl_dt_to", "wv_workspace_bytes", "wv_forward", "wv_gradient", "wv_misfit_gradient", "wv_adjoint_src",
            "wv_pad_velocity", "wv_velocity_gradient", "wv_zfpk_workspace_bytes", "wv_zfpk_max_bytes",
            "wv_zfpk_encode", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_predict", "wv_compressibility", "wv_strerror",
            "wv_last_error", "wv_version", "wv_engine_create", "wv_engine_submit", "wv_engine_wait",
@@ -102,6 +102,8 @@ def lib():
         mp, gp, stp = C.POINTER(WvModel), C.POINTER(WvGeom), C.POINTER(WvStats)
         L.wv_cfl_dt.argtypes = [C.c_int, dp, C.c_int, C.c_double]
         L.wv_cfl_dt.restype = C.c_double
+        L.wv_cfl_dt_to.argtypes = [C.c_int, dp, C.c_int, C.c_double, C.c_int]
+        L.wv_cfl_dt_to.restype = C.c_double
         L.wv_workspace_bytes.argtypes = [mp, gp, C.c_int, sz]
         L.wv_workspace_bytes.restype = sz
         L.wv_forward.argtypes = [mp, gp, vp, vp, vp, sz, vp]
@@ -172,9 +174,11 @@ def _dims(ndim, dims):
 
 # ------------------------------------------------------------------ host-only calls
 
-def cfl_dt(ndim: int, h, space_order: int, vmax: float) -> float:
+def cfl_dt(ndim: int, h, space_order: int, vmax: float, time_order: int = 2) -> float:
     hh = (C.c_double * 3)(*(list(h)[:ndim] + [1.0] * (3 - ndim)))
-    return float(lib().wv_cfl_dt(ndim, hh, space_order, vmax))
+    if time_order == 2:
+        return float(lib().wv_cfl_dt(ndim, hh, space_order, vmax))
+    return float(lib().wv_cfl_dt_to(ndim, hh, space_order, vmax, time_order))
 
 
 def schedule(nt: int, M: int) -> np.ndarray:
@@ -231,9 +235,10 @@ class Problem:
     """C structs for one shot.  vel and wavelet are device tensors (float32);
     src/rec are host float64 arrays (metres, axis order x[, y], z)."""
 
-    def __init__(self, ndim, n, h, nbl, space_order, nt, dt, vmax, vel, src, wavelet, rec):
+    def __init__(self, ndim, n, h, nbl, space_order, nt, dt, vmax, vel, src, wavelet, rec, time_order=2):
         self.model = WvModel()
         self.model.ndim = ndim
+        self.model.time_order = int(time_order)
         for a in range(3):
             self.model.n[a] = int(n[a]) if a < ndim else 1
             self.model.h[a] = float(h[a]) if a < ndim else 1.0

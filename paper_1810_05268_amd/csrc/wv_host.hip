@@ -38,7 +38,9 @@ void fd_weights(int K, double *a)
     a[0] = -2.0 * s;
 }
 
-double cfl_limit(int ndim, const double *h, int order, double vmax)
+// Stability limit: a mode with lam = c^2 dt^2 times its eigenvalue of -lap is stable for
+// lam <= 4 under OT2 and for lam <= 12 under OT4 (which advances it with lam - lam^2/12).
+double cfl_limit(int ndim, const double *h, int order, double vmax, int time_order = 2)
 {
     if (ndim < 2 || ndim > 3 || order < 2 || order > 16 || (order & 1) || !(vmax > 0)) return -1.0;
     double a[kMaxK + 1];
@@ -51,7 +53,7 @@ double cfl_limit(int ndim, const double *h, int order, double vmax)
         if (!(h[d] > 0)) return -1.0;
         q += S / (h[d] * h[d]);
     }
-    return 2.0 / (vmax * std::sqrt(q));
+    return (time_order == 4 ? std::sqrt(12.0) : 2.0) / (vmax * std::sqrt(q));
 }
 
 // ------------------------------------------------------------------ schedule
@@ -181,7 +183,7 @@ int hip_fail(hipError_t e, const char *what, int line)
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    size_t bk, U0, U1, L0, L1, W, Z, UB, DB;
+    size_t bk, U0, U1, L0, L1, W, Z, UB, DB, V, VU;
     size_t src_tab, rec_tab, tab_bytes;
     size_t res, dsim, partials, flags, offs, arena;
     size_t total;
@@ -299,6 +301,7 @@ int validate_model(const wv_model *m, Setup &su)
     if (m->space_order < 2 || m->space_order > 16 || (m->space_order & 1)) return WV_EINVAL;
     if (m->nbl < 0 || m->nt < 1 || !(m->dt > 0) || !(m->vmax > 0) || !std::isfinite(m->vmax) || !m->vel)
         return WV_EINVAL;
+    if (m->time_order != 0 && m->time_order != 2 && m->time_order != 4) return WV_EINVAL;
     long long P = 1;
     for (int a = 0; a < m->ndim; ++a) {
         if (m->n[a] < 1 || !(m->h[a] > 0) || !std::isfinite(m->h[a])) return WV_EINVAL;
@@ -308,13 +311,14 @@ int validate_model(const wv_model *m, Setup &su)
     if (P >= (1LL << 31)) return WV_EINVAL;
     su.P = P;
     su.ndim = m->ndim;
-    const double lim = cfl_limit(m->ndim, m->h, m->space_order, m->vmax);
+    const double lim = cfl_limit(m->ndim, m->h, m->space_order, m->vmax, m->time_order == 4 ? 4 : 2);
     if (!(lim > 0)) return WV_EINVAL;
     if (m->dt > lim * (1.0 + 1e-12)) return WV_ECFL;
     Grid &g = su.g;
     std::memset(&g, 0, sizeof(g));
     g.ndim = m->ndim;
     g.K = m->space_order / 2;
+    g.time_order = m->time_order == 4 ? 4 : 2;
     g.P = P;
     double a[kMaxK + 1];
     fd_weights(g.K, a);
@@ -471,6 +475,8 @@ Layout plan_layout(const wv_model *m, const wv_geom *geo, const Setup &su, int o
     L.U1 = take(fb);
     L.W = take(fb);
     L.Z = take(fb);
+    const bool ot4 = su.g.time_order == 4;
+    if (ot4) L.V = take(fb);                    // OT4: v = w lap u (first pass of a step)
     L.src_tab = take(tab_bytes(su, false));
     L.rec_tab = take(tab_bytes(su, true));
     const size_t data_bytes = (size_t)(m->nt + 1) * geo->nrec * 4;
@@ -479,6 +485,7 @@ Layout plan_layout(const wv_model *m, const wv_geom *geo, const Setup &su, int o
         L.L1 = take(fb);
         L.UB = take(fb);
         L.DB = take(fb);
+        if (ot4) L.VU = take(fb);               // OT4 adjoint: w lap u^k for the gradient term
         L.res = take(data_bytes);
         L.dsim = take(data_bytes);
         L.partials = take(kParts * 8);
@@ -501,7 +508,7 @@ struct Dev {
     uint8_t *base;
     Layout L;
     Sparse src, rec;
-    float *U[2], *Lm[2], *W, *Z, *UB, *DB;
+    float *U[2], *Lm[2], *W, *Z, *UB, *DB, *V = nullptr, *VU = nullptr;
     unsigned *err;
     double *misfit;
     unsigned long long *stats;
@@ -557,6 +564,7 @@ int bind(Dev &d, void *ws, size_t ws_bytes, const Layout &L, int op)
     d.L = L;
     d.U[0] = at<float>(d.base, L.U0);
     d.U[1] = at<float>(d.base, L.U1);
+    if (L.V) d.V = at<float>(d.base, L.V);
     d.W = at<float>(d.base, L.W);
     d.Z = at<float>(d.base, L.Z);
     d.err = at<unsigned>(d.base, L.bk + kErr);
@@ -567,6 +575,7 @@ int bind(Dev &d, void *ws, size_t ws_bytes, const Layout &L, int op)
     if (op == WV_OP_GRADIENT) {
         d.Lm[0] = at<float>(d.base, L.L0);
         d.Lm[1] = at<float>(d.base, L.L1);
+        if (L.VU) d.VU = at<float>(d.base, L.VU);
         d.UB = at<float>(d.base, L.UB);
         d.DB = at<float>(d.base, L.DB);
         d.res = at<float>(d.base, L.res);
@@ -690,7 +699,13 @@ struct Fwd {
         int rc;
         LaunchEvents le;
         if (kt && (rc = kt->pair(0, &le))) return rc;
-        HIPCHK(launch_fwd_step(su.g, u, up, out, d.W, s, le));
+        if (su.g.time_order == 4) {
+            HIPCHK(launch_lapw(su.g, u, d.V, d.W, nullptr, nullptr, 0.0, s, le));
+            if (kt && (rc = kt->pair(0, &le))) return rc;
+            HIPCHK(launch_ot4_update(su.g, d.V, u, up, out, d.W, nullptr, nullptr, 0.0, s, le));
+        } else {
+            HIPCHK(launch_fwd_step(su.g, u, up, out, d.W, s, le));
+        }
         HIPCHK(launch_inject_src(su.g, d.src, geo->wavelet, n, d.W, out, s));
         up = u;
         u = out;
@@ -733,6 +748,12 @@ double wv_cfl_dt(int ndim, const double *h, int space_order, double vmax)
 {
     if (!h) return -1.0;
     return cfl_limit(ndim, h, space_order, vmax);
+}
+
+double wv_cfl_dt_to(int ndim, const double *h, int space_order, double vmax, int time_order)
+{
+    if (!h || (time_order != 2 && time_order != 4)) return -1.0;
+    return cfl_limit(ndim, h, space_order, vmax, time_order);
 }
 
 long wv_schedule_forward_steps(int nt, int M)
@@ -983,7 +1004,21 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
             LaunchEvents le;
             if ((rc = ktimer.pair(1, &le))) break;
             // lam^{k-1} overwrites lam^{k+1}
-            HIPCHK(launch_adj_step(R.su.g, d.Lm[lc], d.Lm[lc ^ 1], d.Lm[lc ^ 1], d.W, uk, R.G, gscale, s, le));
+            if (R.su.g.time_order == 4) {
+                // v_u = w lap u^k; v = w lap lam^k with G += (gscale/12) v v_u (the term
+                // from the m inside B); then the update with G += gscale u^k (v + (w/12) lap v)
+                if (uk) {
+                    HIPCHK(launch_lapw(R.su.g, uk, d.VU, d.W, nullptr, nullptr, 0.0, s, le));
+                    if ((rc = ktimer.pair(1, &le))) break;
+                }
+                HIPCHK(launch_lapw(R.su.g, d.Lm[lc], d.V, d.W, uk ? d.VU : nullptr, uk ? R.G : nullptr,
+                                   gscale / 12.0, s, le));
+                if ((rc = ktimer.pair(1, &le))) break;
+                HIPCHK(launch_ot4_update(R.su.g, d.V, d.Lm[lc], d.Lm[lc ^ 1], d.Lm[lc ^ 1], d.W, uk, R.G, gscale, s,
+                                         le));
+            } else {
+                HIPCHK(launch_adj_step(R.su.g, d.Lm[lc], d.Lm[lc ^ 1], d.Lm[lc ^ 1], d.W, uk, R.G, gscale, s, le));
+            }
             HIPCHK(launch_inject_res(R.su.g, d.rec, res + (size_t)a * R.geo->nrec, d.W, d.Lm[lc ^ 1], uk, R.G,
                                      gscale, s));
             lc ^= 1;

@@ -62,6 +62,9 @@ __device__ __forceinline__ float damping(const Grid &g, int x, int y, int z)
     return g.dampx * (float)(dx * dx) + g.dampy * (float)(dy * dy) + g.dampz * (float)(dz * dz);
 }
 
+// what a stencil launch does with the Laplacian (see stencil3d)
+constexpr int kOT2 = 0, kLapW = 1, kOT4 = 2;
+
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float4 ntload4(const float *p)
@@ -93,11 +96,23 @@ __device__ __forceinline__ void ntstore4(float *p, float a, float b, float c, fl
 // VEC: nx % 4 == 0, every float4 of a row is either inside or outside the grid.
 // `prev` (u^{n-1}) and `fout` (u^{n+1}) may be the same array: each point of it is
 // read and then written by the same lane only.
-template <int K, bool GRAD, bool VEC>
+//
+// MODE selects what is done with the Laplacian L of the marched field `fin`:
+//   kOT2:  the OT2 step above: out = c + ((1-a)(c - prev) + w L)/(1+a), c = fin's
+//          centre; GRAD adds gscale u^k (w L) to G.
+//   kLapW: out = w L (the first pass of an OT4 step); GRAD adds gscale out * xtra
+//          (xtra = w lap u^k, gscale already divided by 12: the OT4 gradient term
+//          (w^2/12)(lap lam)(lap u)).
+//   kOT4:  the second pass of an OT4 step: fin is v = w lap u^n, the centre
+//          c = u^n comes pointwise from xtra, and
+//          out = c + ((1-a)(c - prev) + v + (w/12) L)/(1+a);
+//          GRAD adds gscale u^k (v + (w/12) L) to G.
+template <int K, bool GRAD, bool VEC, int MODE>
 __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *__restrict__ fin,
                                                  const float *prev, float *fout, const float *__restrict__ w,
-                                                 const float *__restrict__ uk, double *__restrict__ G,
-                                                 double gscale, int tiles_x, int tiles_y, int zchunks, int zlen)
+                                                 const float *__restrict__ uk, const float *__restrict__ xtra,
+                                                 double *__restrict__ G, double gscale, int tiles_x, int tiles_y,
+                                                 int zchunks, int zlen)
 {
     constexpr int TX = 32, TY = 32;
     constexpr int HX = (K + 3) / 4 * 4;          // x halo columns (>= K, multiple of 4)
@@ -178,7 +193,7 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
     };
 
     struct Stage {
-        float4 p, w, u, h, f;
+        float4 p, w, u, c, h, f;
         double g[GRAD ? 4 : 1];
     };
     // loads that computing plane z needs: its point operands (with GRAD also u^k and
@@ -193,10 +208,11 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
                            row[min(gx + 3, nx - 1)]);
     };
     auto fill = [&](Stage &S, int z) {
-        S.p = load4p(prev, z, x0);
+        if constexpr (MODE != kLapW) S.p = load4p(prev, z, x0);
         S.w = load4p(w, z, x0);
+        if constexpr (MODE == kOT4 || (MODE == kLapW && GRAD)) S.c = load4p(xtra, z, x0);
         if constexpr (GRAD) {
-            S.u = load4p(uk, z, x0);
+            if constexpr (MODE != kLapW) S.u = load4p(uk, z, x0);
             const long long pg = (long long)min(z, nz - 1) * sxy + (long long)min(y, ny - 1) * nx;
             if constexpr (VEC) {
                 // two 16-byte loads per lane, normally cached: the line a lane pair shares
@@ -308,16 +324,22 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
         const float pin[4] = {S.p.x, S.p.y, S.p.z, S.p.w};
         const float win[4] = {S.w.x, S.w.y, S.w.z, S.w.w};
         const float uin[4] = {S.u.x, S.u.y, S.u.z, S.u.w};
-        float dn[4], on[4], wl[4];
+        const float cin[4] = {S.c.x, S.c.y, S.c.z, S.c.w};
+        float on[4], wl[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int dx_ = layer_depth(x0 + i, g.ix0[0], g.ix1[0]);
-            const float a = fmaf(g.dampx, (float)(dx_ * dx_), ayz);
             const float l = fmaf(c1, sy[i], lap[i]);
-            wl[i] = win[i] * l;
-            const float r = __builtin_amdgcn_rcpf(1.0f + a);
-            dn[i] = ((1.0f - a) * (q[i][K] - pin[i]) + wl[i]) * r;
-            on[i] = q[i][K] + dn[i];
+            if constexpr (MODE == kLapW) {
+                on[i] = win[i] * l;
+            } else {
+                // wl: w B u^n, the whole spatial term of the step
+                const float ctr = MODE == kOT4 ? cin[i] : q[i][K];
+                wl[i] = MODE == kOT4 ? fmaf(win[i] * (1.0f / 12.0f), l, q[i][K]) : win[i] * l;
+                const int dx_ = layer_depth(x0 + i, g.ix0[0], g.ix1[0]);
+                const float a = fmaf(g.dampx, (float)(dx_ * dx_), ayz);
+                const float r = __builtin_amdgcn_rcpf(1.0f + a);
+                on[i] = ctr + ((1.0f - a) * (ctr - pin[i]) + wl[i]) * r;
+            }
         }
         if (ptin) {
             const long long p0 = (long long)z * sxy + rowoff + x0;
@@ -331,7 +353,9 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
             if constexpr (GRAD) {
                 double gn[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) gn[i] = gold[i] + gscale * (double)uin[i] * (double)wl[i];
+                for (int i = 0; i < 4; ++i)
+                    gn[i] = MODE == kLapW ? gold[i] + gscale * (double)on[i] * (double)cin[i]
+                                          : gold[i] + gscale * (double)uin[i] * (double)wl[i];
                 if constexpr (VEC) {
                     *reinterpret_cast<double2 *>(&G[p0]) = make_double2(gn[0], gn[1]);
                     *reinterpret_cast<double2 *>(&G[p0 + 2]) = make_double2(gn[2], gn[3]);
@@ -386,11 +410,13 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
 
 // 2-D: a workgroup owns 256 consecutive x and marches down z (the second axis).
 // `prev` and `fout` may be the same array (read, then written, by the same lane).
-template <int K, bool GRAD>
+// MODE as for the 3-D kernel.
+template <int K, bool GRAD, int MODE>
 __global__ __launch_bounds__(256) void stencil2d(Grid g, const float *__restrict__ fin, const float *prev,
                                                  float *fout, const float *__restrict__ w,
-                                                 const float *__restrict__ uk, double *__restrict__ G,
-                                                 double gscale, int tiles_x, int zchunks, int zlen)
+                                                 const float *__restrict__ uk, const float *__restrict__ xtra,
+                                                 double *__restrict__ G, double gscale, int tiles_x, int zchunks,
+                                                 int zlen)
 {
     constexpr int TX = 256;
     __shared__ float row[TX + 2 * K];
@@ -437,15 +463,20 @@ __global__ __launch_bounds__(256) void stencil2d(Grid g, const float *__restrict
             }
             const float lap = sx + sz;
             const long long p = (long long)z * nx + x;
-            const float a = damping(g, x, 0, z);
-            const float wl = __builtin_nontemporal_load(&w[p]) * lap;
-            const float d = c - __builtin_nontemporal_load(&prev[p]);
-            const float dn = (a == 0.0f) ? d + wl : ((1.0f - a) * d + wl) / (1.0f + a);
-            __builtin_nontemporal_store(c + dn, &fout[p]);
-            if constexpr (GRAD) {
-                const double gn = __builtin_nontemporal_load(&G[p]) +
-                                  gscale * (double)__builtin_nontemporal_load(&uk[p]) * (double)wl;
-                __builtin_nontemporal_store(gn, &G[p]);
+            const float wp = __builtin_nontemporal_load(&w[p]);
+            if constexpr (MODE == kLapW) {
+                const float v = wp * lap;
+                __builtin_nontemporal_store(v, &fout[p]);
+                if constexpr (GRAD)
+                    G[p] += gscale * (double)v * (double)__builtin_nontemporal_load(&xtra[p]);
+            } else {
+                const float ctr = MODE == kOT4 ? __builtin_nontemporal_load(&xtra[p]) : c;
+                const float wl = MODE == kOT4 ? fmaf(wp * (1.0f / 12.0f), lap, c) : wp * lap;
+                const float a = damping(g, x, 0, z);
+                const float d = ctr - __builtin_nontemporal_load(&prev[p]);
+                const float dn = (a == 0.0f) ? d + wl : ((1.0f - a) * d + wl) / (1.0f + a);
+                __builtin_nontemporal_store(ctr + dn, &fout[p]);
+                if constexpr (GRAD) G[p] += gscale * (double)__builtin_nontemporal_load(&uk[p]) * (double)wl;
             }
         }
         __syncthreads();
@@ -655,51 +686,52 @@ void launch_timed(Kern kern, dim3 grid, hipStream_t s, LaunchEvents ev, Args... 
         hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, args...);
 }
 
-template <int K, bool GRAD, bool VEC>
+template <int K, bool GRAD, bool VEC, int MODE>
 hipError_t launch3d(const Grid &g, const float *fin, const float *prev, float *fout, const float *w,
-                    const float *uk, double *G, double gscale, hipStream_t s, LaunchEvents ev)
+                    const float *uk, const float *xtra, double *G, double gscale, hipStream_t s, LaunchEvents ev)
 {
-    auto kern = stencil3d<K, GRAD, VEC>;
+    auto kern = stencil3d<K, GRAD, VEC, MODE>;
     const int tiles_x = (g.nx + 31) / 32, tiles_y = (g.ny + 31) / 32;
     // one resident round of workgroups: z chunks as long as possible (the 2K-plane
     // warm-up of each chunk re-reads the field), but enough of them to fill the GPU
     int zchunks, zlen;
     choose_chunks((long long)tiles_x * tiles_y, g.nz, K, resident_workgroups(kern), zchunks, zlen);
     const int nwg = tiles_x * tiles_y * zchunks;
-    launch_timed(kern, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, G, gscale, tiles_x, tiles_y, zchunks, zlen);
+    launch_timed(kern, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, xtra, G, gscale, tiles_x, tiles_y, zchunks,
+                 zlen);
     return hipGetLastError();
 }
 
-template <int K, bool GRAD>
+template <int K, bool GRAD, int MODE>
 hipError_t launch_k(const Grid &g, const float *fin, const float *prev, float *fout, const float *w,
-                    const float *uk, double *G, double gscale, hipStream_t s, LaunchEvents ev)
+                    const float *uk, const float *xtra, double *G, double gscale, hipStream_t s, LaunchEvents ev)
 {
     if (g.ndim == 3) {
-        if (g.nx % 4 == 0) return launch3d<K, GRAD, true>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
-        return launch3d<K, GRAD, false>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
+        if (g.nx % 4 == 0) return launch3d<K, GRAD, true, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
+        return launch3d<K, GRAD, false, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
     }
     const int tiles_x = (g.nx + 255) / 256;
     int zchunks, zlen;
     choose_chunks(tiles_x, g.nz, K, 512, zchunks, zlen);
     const int nwg = tiles_x * zchunks;
-    launch_timed(stencil2d<K, GRAD>, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, G, gscale, tiles_x, zchunks,
-                 zlen);
+    launch_timed(stencil2d<K, GRAD, MODE>, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, xtra, G, gscale, tiles_x,
+                 zchunks, zlen);
     return hipGetLastError();
 }
 
-template <bool GRAD>
+template <bool GRAD, int MODE>
 hipError_t launch_any(const Grid &g, const float *fin, const float *prev, float *fout, const float *w,
-                      const float *uk, double *G, double gscale, hipStream_t s, LaunchEvents ev)
+                      const float *uk, const float *xtra, double *G, double gscale, hipStream_t s, LaunchEvents ev)
 {
     switch (g.K) {
-    case 1: return launch_k<1, GRAD>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
-    case 2: return launch_k<2, GRAD>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
-    case 3: return launch_k<3, GRAD>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
-    case 4: return launch_k<4, GRAD>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
-    case 5: return launch_k<5, GRAD>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
-    case 6: return launch_k<6, GRAD>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
-    case 7: return launch_k<7, GRAD>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
-    case 8: return launch_k<8, GRAD>(g, fin, prev, fout, w, uk, G, gscale, s, ev);
+    case 1: return launch_k<1, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
+    case 2: return launch_k<2, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
+    case 3: return launch_k<3, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
+    case 4: return launch_k<4, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
+    case 5: return launch_k<5, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
+    case 6: return launch_k<6, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
+    case 7: return launch_k<7, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
+    case 8: return launch_k<8, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
     default: return hipErrorInvalidValue;
     }
 }
@@ -709,15 +741,30 @@ hipError_t launch_any(const Grid &g, const float *fin, const float *prev, float 
 hipError_t launch_fwd_step(const Grid &g, const float *u_in, const float *u_prev, float *u_out, const float *w,
                            hipStream_t s, LaunchEvents ev)
 {
-    return launch_any<false>(g, u_in, u_prev, u_out, w, nullptr, nullptr, 0.0, s, ev);
+    return launch_any<false, kOT2>(g, u_in, u_prev, u_out, w, nullptr, nullptr, nullptr, 0.0, s, ev);
 }
 
 hipError_t launch_adj_step(const Grid &g, const float *lam_in, const float *lam_next, float *lam_out,
                            const float *w, const float *uk, double *G, double gscale, hipStream_t s,
                            LaunchEvents ev)
 {
-    if (G) return launch_any<true>(g, lam_in, lam_next, lam_out, w, uk, G, gscale, s, ev);
-    return launch_any<false>(g, lam_in, lam_next, lam_out, w, nullptr, nullptr, 0.0, s, ev);
+    if (G) return launch_any<true, kOT2>(g, lam_in, lam_next, lam_out, w, uk, nullptr, G, gscale, s, ev);
+    return launch_any<false, kOT2>(g, lam_in, lam_next, lam_out, w, nullptr, nullptr, nullptr, 0.0, s, ev);
+}
+
+hipError_t launch_lapw(const Grid &g, const float *f, float *v_out, const float *w, const float *x, double *G,
+                       double gscale, hipStream_t s, LaunchEvents ev)
+{
+    if (G) return launch_any<true, kLapW>(g, f, nullptr, v_out, w, nullptr, x, G, gscale, s, ev);
+    return launch_any<false, kLapW>(g, f, nullptr, v_out, w, nullptr, nullptr, nullptr, 0.0, s, ev);
+}
+
+hipError_t launch_ot4_update(const Grid &g, const float *v, const float *u_in, const float *u_prev, float *u_out,
+                             const float *w, const float *uk, double *G, double gscale, hipStream_t s,
+                             LaunchEvents ev)
+{
+    if (G) return launch_any<true, kOT4>(g, v, u_prev, u_out, w, uk, u_in, G, gscale, s, ev);
+    return launch_any<false, kOT4>(g, v, u_prev, u_out, w, nullptr, u_in, nullptr, 0.0, s, ev);
 }
 
 hipError_t launch_inject_src(const Grid &g, const Sparse &sp, const float *q, int n, const float *w,

@@ -14,11 +14,12 @@ from . import _binding as B
 
 class DeviceShot:
     def __init__(self, ndim, n, h, nbl, space_order, nt, dt, vmax, vel_padded, wavelet, src, rec,
-                 device="cuda"):
+                 device="cuda", time_order=2):
         self.device = torch.device(device)
         self.vel = torch.as_tensor(np.ascontiguousarray(vel_padded, dtype=np.float32), device=self.device)
         self.wavelet = torch.as_tensor(np.ascontiguousarray(wavelet, dtype=np.float32), device=self.device)
-        self.pb = B.Problem(ndim, n, h, nbl, space_order, nt, dt, vmax, self.vel, src, self.wavelet, rec)
+        self.pb = B.Problem(ndim, n, h, nbl, space_order, nt, dt, vmax, self.vel, src, self.wavelet, rec,
+                            time_order=time_order)
         self.shape = tuple(reversed(self.pb.padded))
         self.nt, self.nrec, self.P = self.pb.nt, self.pb.nrec, self.pb.P
         self._ws = None

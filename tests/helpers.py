@@ -18,21 +18,22 @@ def has_gpu() -> bool:
         return False
 
 
-def oracle_side(shot: W.Shot, which: str = "vel", nthreads=None):
-    dt = shot.cfl_frac * oracle.cfl_dt(shot.ndim, shot.h, shot.order, shot.vmax)
-    spec = oracle.ModelSpec(shot.ndim, shot.n, shot.h, shot.nbl, shot.order, shot.nt, dt, shot.vmax)
+def oracle_side(shot: W.Shot, which: str = "vel", nthreads=None, time_order: int = 2):
+    dt = shot.cfl_frac * oracle.cfl_dt(shot.ndim, shot.h, shot.order, shot.vmax, time_order=time_order)
+    spec = oracle.ModelSpec(shot.ndim, shot.n, shot.h, shot.nbl, shot.order, shot.nt, dt, shot.vmax,
+                            time_order=time_order)
     q = W.ricker(shot.f0, dt, shot.nt)
     vel = shot.padded(which).astype(np.float64)
     return oracle.Solver(spec, vel, shot.src, q, shot.rec, nthreads=nthreads), dt
 
 
-def gpu_side(shot: W.Shot, which: str = "vel"):
+def gpu_side(shot: W.Shot, which: str = "vel", time_order: int = 2):
     import paper_1810_05268_amd as P
     from paper_1810_05268_amd.shot import DeviceShot
-    dt = shot.cfl_frac * P.cfl_dt(shot.ndim, shot.h, shot.order, shot.vmax)
+    dt = shot.cfl_frac * P.cfl_dt(shot.ndim, shot.h, shot.order, shot.vmax, time_order=time_order)
     q = W.ricker(shot.f0, dt, shot.nt).astype(np.float32)
     return DeviceShot(shot.ndim, shot.n, shot.h, shot.nbl, shot.order, shot.nt, dt, shot.vmax,
-                      shot.padded(which), q, shot.src, shot.rec), dt
+                      shot.padded(which), q, shot.src, shot.rec, time_order=time_order), dt
 
 
 def rel_l2(a, b) -> float:

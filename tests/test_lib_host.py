@@ -165,3 +165,14 @@ def test_predict_rejects_bad_input_and_budget_below_one_checkpoint_is_one_slot()
     # x_0 is the zero state and takes no memory: recomputation from it alone
     pr = P.predict(100, 1000, 10, False, 1.0, 1.0)
     assert pr["slots"] == 1 and pr["advances"] == 100 * 101 // 2 and pr["stores"] == 0
+
+
+@pytest.mark.parametrize("order", [2, 4, 8, 16])
+def test_ot4_cfl_matches_oracle(order):
+    import oracle
+    import paper_1810_05268_amd as P
+    for ndim, h in ((2, (10.0, 7.5)), (3, (12.5, 10.0, 8.0))):
+        a = P.cfl_dt(ndim, h, order, 3500.0, time_order=4)
+        b = oracle.cfl_dt(ndim, h, order, 3500.0, time_order=4)
+        assert a == b
+        assert a == pytest.approx(3 ** 0.5 * P.cfl_dt(ndim, h, order, 3500.0), rel=1e-15)
