@@ -64,43 +64,78 @@ def make_shot(args):
     raise SystemExit(f"unknown workload {args.workload}")
 
 
-def plan_hint(st, points):
-    """Planning ratio for the next call of the same shot and tolerance: the uncompressed
-    bytes of the slots the previous call held at its peak over the arena bytes they
-    took, with a 15 % margin.  The peak is what the budget must hold; it is made of
-    states from the whole time range, most of them more compressible than the final
-    state the first call planned with.  If it still overflows, the library re-plans."""
-    S = 8.0 * points
-    if st["peak_bytes"] <= 0 or st["slots"] < 2:
-        return 0.95 * st["ratio_planned"]
-    return max(1.0, 0.85 * S * (st["slots"] - 1) / st["peak_bytes"])
+def ot4_block(shot, budget, tol, steps):
+    """The same shot with the OT4 kernel (fourth order in time: two stencil passes per
+    forward step, three per adjoint step), at 0.4 of its own stability limit: plain
+    against compressed Revolve at the same memory budget, with the model's predictions."""
+    import numpy as np
+    import torch
 
-
-def performance_model(nt, points, budget, st_plain, st_comp, hint, sweep_stats):
-    """The run-time model (wv_predict) fed with the per-unit costs of the timed plain
-    and compressed calls: predicted against measured device time of each run, as the
-    paper validates its model.  Sweep runs are predicted with the headline costs and
-    their own planning ratio."""
     import paper_1810_05268_amd as P
+    import workloads as W
+    from paper_1810_05268_amd.shot import DeviceShot
+    dt = shot.cfl_frac * P.cfl_dt(shot.ndim, shot.h, shot.order, shot.vmax, time_order=4)
+    q = W.ricker(shot.f0, dt, shot.nt).astype(np.float32)
+    G = DeviceShot(shot.ndim, shot.n, shot.h, shot.nbl, shot.order, shot.nt, dt, shot.vmax, shot.padded("true"),
+                   q, shot.src, shot.rec, time_order=4)
+    d_obs = G.forward()
+    G.set_velocity(shot.padded("vel"))
+    gp = torch.empty(G.shape, dtype=torch.float64, device="cuda")
+    gc = torch.empty(G.shape, dtype=torch.float64, device="cuda")
 
-    def phases(st):
-        return st["ms_forward"] + st["ms_adjoint"] + st["ms_store"] + st["ms_restore"]
-    cp, cc = P.costs_from_stats(st_plain), P.costs_from_stats(st_comp)
-    rows = []
-    pr = P.predict(nt, points, budget, False, cp["c_f"], cp["c_r"], t_copy=cp["t_store"])
-    rows.append({"run": "plain", "predicted_ms": pr["ms_total"], "measured_ms": phases(st_plain),
-                 "slots": pr["slots"], "advances": pr["advances"]})
-    pr = P.predict(nt, points, budget, True, cc["c_f"], cc["c_r"], t_c=cc["t_store"], t_d=cc["t_d"], ratio=hint)
-    rows.append({"run": "compressed", "predicted_ms": pr["ms_total"], "measured_ms": phases(st_comp),
-                 "slots": pr["slots"], "advances": pr["advances"]})
-    for tol, h, st in sweep_stats:
-        pr = P.predict(nt, points, budget, True, cc["c_f"], cc["c_r"], t_c=cc["t_store"], t_d=cc["t_d"], ratio=h)
-        rows.append({"run": f"compressed tol {tol:g}", "predicted_ms": pr["ms_total"], "measured_ms": phases(st),
-                     "slots": pr["slots"], "advances": pr["advances"]})
-    for r in rows:
-        r["rel_err"] = (r["predicted_ms"] - r["measured_ms"]) / r["measured_ms"]
-    full = P.predict(nt, points, budget, False, cp["c_f"], cp["c_r"], t_copy=cp["t_store"])["ms_full_storage"]
-    return {"costs_plain": cp, "costs_compressed": cc, "full_storage_ms": full, "runs": rows}
+    def run(tol_, hint, out, n):
+        walls, st = [], None
+        for _ in range(n):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, st = G.misfit_gradient(d_obs, budget, tol_, hint, timing=3, out=out)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+        return walls, st
+    log("OT4 plain ...")
+    wp, sp = run(0.0, 0.0, gp, steps)
+    log("OT4 compressed ...")
+    _, s0 = run(tol, 0.0, gc, 1)
+    h = plan_hint(s0, G.P, shot.nt, budget)
+    wc, sc = run(tol, h, gc, steps)
+    err = float(torch.linalg.vector_norm(gc - gp) / torch.linalg.vector_norm(gp))
+    cp, cc = P.costs_from_stats(sp), P.costs_from_stats(sc)
+    pp = P.predict(shot.nt, G.P, budget, False, cp["c_f"], cp["c_r"], t_copy=cp["t_store"])
+    pc = P.predict(shot.nt, G.P, budget, True, cc["c_f"], cc["c_r"], t_c=cc["t_store"], t_d=cc["t_d"], ratio=h)
+    out = {"dt": dt, "shot_gradient_s": {"plain": statistics.mean(wp), "compressed": statistics.mean(wc)},
+           "speedup_vs_plain": statistics.mean(wp) / statistics.mean(wc), "grad_rel_err_vs_plain": err,
+           "schedule": {"plain": {k: sp[k] for k in ("slots", "advances", "stores")},
+                        "compressed": {k: sc[k] for k in ("slots", "advances", "stores", "decodes", "ratio")}},
+           "step_ms": {"forward": sp["ms_fwd_kernel"] / sp["advances"], "adjoint": sp["ms_adj_kernel"] / sp["reverses"]},
+           "model": {"plain": {"predicted_ms": pp["ms_total"], "measured_ms": sum(sp[k] for k in (
+                         "ms_forward", "ms_adjoint", "ms_store", "ms_restore"))},
+                     "full_storage_ms": pp["ms_full_storage"]}}
+    log(f"OT4: plain {out['shot_gradient_s']['plain']:.3f} s, compressed {out['shot_gradient_s']['compressed']:.3f} s "
+        f"({out['speedup_vs_plain']:.2f}x), grad err {err:.2e}")
+    return out
+
+
+def plan_hint(st, points, nt, budget):
+    """Planning ratio for the next call of the same shot and tolerance, as an
+    optimisation loop would carry it from one iteration to the next: the slot count
+    wv_plan finds for the compressibility profile the previous call measured (stream
+    sizes of its stored states over time), as the ratio that makes the call plan it."""
+    import paper_1810_05268_amd as P
+    prof = st["profile"]
+    if all(x > 0 for x in prof):
+        _, h = P.plan(nt, points, budget, prof)
+        if h > 0:
+            return h
+    return 0.95 * st["ratio_planned"]
+
+
+def full_trajectory_bytes(st, nt):
+    """Compressed bytes of all states u^1..u^nt from a call's profile (linear between
+    the samples), each stream rounded up to 256 bytes."""
+    import numpy as np
+    ks = [0] + [-(-(j * nt) // 16) for j in range(1, 17)]
+    sizes = np.interp(np.arange(1, nt + 1), ks, st["profile"])
+    return float(np.sum(np.ceil(sizes / 256.0) * 256.0))
 
 
 def traffic_per_launch():
@@ -160,9 +195,9 @@ def kernels_mode():
 
 def serving_leg(nreq, rate, pool_bytes, max_active, tol, cap):
     """The serving stream: seeded Poisson arrivals of mixed shots through the engine.
-    Per request: checkpoint budget = 1.2 x the compressed full trajectory at the class's
-    planned ratio, capped; the planned ratio (the final state's, measured once per class
-    in an untimed call, as an optimisation loop would carry it over) is passed as the hint."""
+    Per class, one untimed call measures the compressibility profile; each request of the
+    class then gets a checkpoint budget of 1.1 x the compressed full trajectory (capped)
+    and the plan for it as the hint."""
     import numpy as np
     import torch
 
@@ -171,7 +206,7 @@ def serving_leg(nreq, rate, pool_bytes, max_active, tol, cap):
     from paper_1810_05268_amd.serving import Engine, replay
     from paper_1810_05268_amd.shot import DeviceShot
     reqs = W.serving_stream(nreq=nreq, rate=rate, seed=5)
-    items, hints, cls = [], {}, []
+    items, hints, budgets, cls = [], {}, {}, []
     for i, r in enumerate(reqs):
         s = r.shot
         dt = s.cfl_frac * P.cfl_dt(s.ndim, s.h, s.order, s.vmax)
@@ -180,14 +215,15 @@ def serving_leg(nreq, rate, pool_bytes, max_active, tol, cap):
         d_obs = G.forward()
         G.set_velocity(s.padded("vel"))
         c = s.extra["class"]
-        full = 8 * G.P * (s.nt + 1)
         if c not in hints:
-            _, _, st = G.misfit_gradient(d_obs, min(full, cap), tol)
-            hints[c] = 0.95 * st["ratio_planned"]
+            # one untimed call per class measures its compressibility profile; requests of
+            # the class get 1.1 x the compressed full trajectory (capped) and the plan for it
+            _, _, st = G.misfit_gradient(d_obs, min(4 * G.P * (s.nt + 1), cap), tol)
+            budgets[c] = int(min(cap, 1.1 * full_trajectory_bytes(st, s.nt)))
+            _, hints[c] = P.plan(s.nt, G.P, budgets[c], st["profile"])
             G._ws = None
             torch.cuda.empty_cache()
-        budget = int(min(cap, 1.2 * full / hints[c]))
-        items.append((r.arrival, G, d_obs, budget, tol, hints[c]))
+        items.append((r.arrival, G, d_obs, budgets[c], tol, hints[c]))
         cls.append(c)
         if (i + 1) % 50 == 0:
             log(f"serving set-up: {i + 1}/{nreq} requests prepared")
@@ -214,7 +250,7 @@ def serving_leg(nreq, rate, pool_bytes, max_active, tol, cap):
             "retried": sum(1 for r in res if r["stats"]["retries"]),
             "p50_ms": pct(lat, 0.5), "p99_ms": pct(lat, 0.99), "req_per_s": nreq / wall,
             "gpts": pts / wall / 1e9, "per_class": per_class, "pool_bytes": pool_bytes, "max_active": max_active,
-            "tol": tol, "ratio_hints": hints,
+            "tol": tol, "ratio_hints": hints, "budgets": budgets,
             "classes": "0: 2-D 512^2 order 8 1500 steps; 1: 3-D 160^3 order 8 1200 steps; "
                        "2: 3-D 256^3 order 12 2000 steps (interior; 20-cell layer; h = 10 m)"}
 
@@ -286,6 +322,7 @@ def main():
     ap.add_argument("--serving-pool", type=float, default=200e9)
     ap.add_argument("--serving-active", type=int, default=8)
     ap.add_argument("--kernels", action="store_true", help="short kernel workload for counter passes only")
+    ap.add_argument("--no-ot4", action="store_true", help="skip the OT4 comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of it"}))
@@ -340,7 +377,7 @@ def main():
     # iteration to the next
     log("compressed ...")
     _, st0, _ = timed(args.tol, 0.0, g_comp, max(1, args.warmup))
-    hint = plan_hint(st0[-1], Pn)
+    hint = plan_hint(st0[-1], Pn, shot.nt, budget)
     w_comp, st_comp, phi_comp = timed(args.tol, hint, g_comp, args.steps)
     err = float(torch.linalg.vector_norm(g_comp - g_plain) / torch.linalg.vector_norm(g_plain))
     log(f"compressed tol {args.tol}: {statistics.mean(w_comp):.3f} s  M={st_comp[0]['slots']} "
@@ -349,7 +386,7 @@ def main():
     sweep, sweep_stats = [], []
     for tol in [float(t) for t in args.sweep.split(",") if t.strip()]:
         _, sp0, _ = timed(tol, 0.0, g_comp, 1)
-        h = plan_hint(sp0[-1], Pn)
+        h = plan_hint(sp0[-1], Pn, shot.nt, budget)
         ws_, ss_, _ = timed(tol, h, g_comp, 1)
         e = float(torch.linalg.vector_norm(g_comp - g_plain) / torch.linalg.vector_norm(g_plain))
         sweep.append({"tol": tol, "shot_s": ws_[0], "slots": ss_[0]["slots"], "ratio": ss_[0]["ratio"],
@@ -424,6 +461,13 @@ def main():
         "compressibility": compressibility,
         "roofline": roof,
     }
+    if not args.no_ot4:
+        del g_plain, g_comp
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        out["ot4"] = ot4_block(shot, budget, args.tol, 1)
+        torch.cuda.empty_cache()
+        g_plain = g_comp = None
     if args.serving_requests > 0 and not args.quick:
         del G, g_plain, g_comp, d_obs
         torch.cuda.synchronize()

@@ -96,6 +96,8 @@ typedef struct {
     const double *rec_xyz;   /* host [nrec][ndim], same convention */
 } wv_geom;
 
+#define WV_PROFILE 17    /* samples of a compressibility profile */
+
 typedef struct {
     int timing;          /* input: bit 0 = time every schedule action with HIP events;
                             bit 1 = also time every stencil launch on its own */
@@ -122,6 +124,9 @@ typedef struct {
     double ms_fwd_kernel;/* with timing bit 1: device ms inside the forward stencil launches (one per advance) */
     double ms_adj_kernel;/* with timing bit 1: device ms inside the adjoint+gradient stencil launches (one per reverse) */
     long retries;        /* compressed runs repeated because checkpoints outgrew mem_budget (see WV_EARENA) */
+    double profile[WV_PROFILE];  /* compressed runs: stream bytes of one field of u^k at k = 0 (the empty
+                            field) and k = ceil(j nt / (WV_PROFILE-1)), j = 1..WV_PROFILE-1, taken from
+                            the states this call stored (nearest stored k); 0 where unknown.  For wv_plan. */
 } wv_stats;
 
 /* ------------------------------------------------------------------ queries */
@@ -166,9 +171,11 @@ int wv_forward(const wv_model *model, const wv_geom *geom, float *data, float *s
  *               compressed (two 256-byte aligned streams), S = 8 P bytes per
  *               uncompressed checkpoint (u^k and u^{k-1}; compressed, the pair is
  *               stored as u^k and the increment u^k - u^{k-1}),
- *               F = 1 if tol == 0, else ratio_hint if > 0, else the ratio measured
- *               on the final state of a probe forward run (the paper uses the
- *               last time step as the worst-case compressibility);
+ *               F = 1 if tol == 0, else ratio_hint if > 0; without a hint a probe
+ *               forward run measures the compressibility profile (stream sizes over
+ *               time; the paper notes that late states compress worst) and M is the
+ *               largest slot count whose peak arena use, simulated over the exact
+ *               schedule with those sizes, fits (as wv_plan);
  *   tol         0: checkpoints are exact copies; > 0: absolute error bound of the codec
  *   grad_m      device [P] double, overwritten (layer cells included)
  *   stats       host, may be NULL
@@ -308,6 +315,16 @@ long wv_schedule_forward_steps(int nt, int M);
  * WV_OP_COMPRESSIBILITY, 0) bytes.  Synchronises the stream after every sample. */
 int wv_compressibility(const wv_model *model, const wv_geom *geom, double tol, int stride, size_t *bytes,
                        int cap, int *count, void *ws, size_t ws_bytes, void *stream);
+
+/* Checkpoint slots for a compressibility profile (WV_PROFILE stream sizes as in
+ * wv_stats.profile, e.g. from an earlier call with the same shot and tolerance): the
+ * largest M whose peak arena use fits 97 % of mem_budget, simulated over the exact
+ * schedule (slots freed last-in first-out, the second level stored where the schedule
+ * advances from a checkpoint, each stream rounded up to 256 bytes, sizes interpolated
+ * linearly between the samples).  *ratio_hint receives the planning ratio with which a
+ * gradient call plans exactly these M slots (0 when M = 1).  Host only. */
+int wv_plan(int nt, long long points, size_t mem_budget, const double *profile, int nprofile, int *slots,
+            double *ratio_hint);
 
 /* ------------------------------------------------------------ performance model
  * The run-time model of Sec. "Checkpointing performance model" (eqs. (1)-(5)) and

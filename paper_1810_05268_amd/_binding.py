@@ -52,10 +52,13 @@ class WvStats(C.Structure):
                 ("peak_bytes", C.c_double), ("ratio", C.c_double), ("ratio_planned", C.c_double),
                 ("misfit", C.c_double), ("ms_total", C.c_double), ("ms_forward", C.c_double),
                 ("ms_adjoint", C.c_double), ("ms_store", C.c_double), ("ms_restore", C.c_double),
-                ("ms_fwd_kernel", C.c_double), ("ms_adj_kernel", C.c_double), ("retries", C.c_long)]
+                ("ms_fwd_kernel", C.c_double), ("ms_adj_kernel", C.c_double), ("retries", C.c_long),
+                ("profile", C.c_double * 17)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "profile"}
+        d["profile"] = list(self.profile)
+        return d
 
 
 class WvCosts(C.Structure):
@@ -81,7 +84,7 @@ class WvResult(C.Structure):
 # every symbol include/wv.h declares
 SYMBOLS = ["wv_cfl_dt", "wv_cfl_dt_to", "wv_workspace_bytes", "wv_forward", "wv_gradient", "wv_misfit_gradient", "wv_adjoint_src",
            "wv_pad_velocity", "wv_velocity_gradient", "wv_zfpk_workspace_bytes", "wv_zfpk_max_bytes",
-           "wv_zfpk_encode", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_predict", "wv_compressibility", "wv_strerror",
+           "wv_zfpk_encode", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_predict", "wv_plan", "wv_compressibility", "wv_strerror",
            "wv_last_error", "wv_version", "wv_engine_create", "wv_engine_submit", "wv_engine_wait",
            "wv_engine_pending", "wv_engine_destroy"]
 
@@ -122,6 +125,8 @@ def lib():
         L.wv_schedule_forward_steps.argtypes = [C.c_int, C.c_int]
         L.wv_schedule_forward_steps.restype = C.c_long
         L.wv_predict.argtypes = [C.c_int, C.c_longlong, sz, C.c_int, C.POINTER(WvCosts), C.POINTER(WvPrediction)]
+        L.wv_plan.argtypes = [C.c_int, C.c_longlong, sz, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_int),
+                              C.POINTER(C.c_double)]
         L.wv_compressibility.argtypes = [mp, gp, C.c_double, C.c_int, C.POINTER(C.c_size_t), C.c_int,
                                          C.POINTER(C.c_int), vp, sz, vp]
         L.wv_strerror.argtypes = [C.c_int]
@@ -202,6 +207,14 @@ def compressibility(pb: Problem, tol: float, stride: int, ws, stream=None) -> li
                                     C.byref(n), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)),
            "wv_compressibility")
     return [int(out[i]) for i in range(n.value)]
+
+
+def plan(nt: int, points: int, mem_budget: int, profile) -> tuple[int, float]:
+    """(slots, ratio_hint) for a compressibility profile (see wv_plan)."""
+    prof = (C.c_double * 17)(*[float(x) for x in profile])
+    m, h = C.c_int(0), C.c_double(0.0)
+    _check(lib().wv_plan(int(nt), int(points), int(mem_budget), prof, 17, C.byref(m), C.byref(h)), "wv_plan")
+    return int(m.value), float(h.value)
 
 
 def predict(nt: int, points: int, mem_budget: int, compressed: bool, c_f: float, c_r: float, t_copy: float = 0.0,

@@ -43,8 +43,10 @@ class WaveMisfit(torch.autograd.Function):
         phi, gm, st = problem.shot.misfit_gradient(problem.d_obs, problem.mem_budget, problem.tol,
                                                    problem.ratio_hint)
         problem.last_stats = st
-        if problem.tol > 0 and problem.ratio_hint <= 0:
-            problem.ratio_hint = 0.95 * st["ratio_planned"]    # reuse the measured ratio next time
+        if problem.tol > 0 and problem.ratio_hint <= 0 and all(x > 0 for x in st["profile"]):
+            # plan later calls from the compressibility this one measured (no probe run)
+            _, h = B.plan(problem.shot.nt, problem.shot.P, problem.mem_budget, st["profile"])
+            problem.ratio_hint = h if h > 0 else 0.95 * st["ratio_planned"]
         gv = torch.empty(v.shape, dtype=torch.float64, device=v.device)
         B.velocity_gradient(problem.ndim, problem.n, problem.nbl, problem.vel_padded, gm, gv)
         ctx.save_for_backward(gv)

@@ -232,6 +232,7 @@ struct EncArgs {
     uint64_t *flags;
     uint32_t epoch;
     unsigned *ticket;        // chunk order = start order (0 at launch, reset by the last taker)
+    uint64_t *size_out;      // nullable: receives the stream's size in bytes
     unsigned *err;
     unsigned long long *stats;
 };
@@ -552,6 +553,7 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
         }
         const unsigned long long nxt = base + ((total + 255ull) & ~255ull);
         *A.next = nxt;
+        if (A.size_out) *A.size_out = total;
         atomicAdd(&A.stats[0], total);
         atomicMax(&A.stats[1], nxt);
     }
@@ -757,7 +759,8 @@ size_t codec_max_bytes(const CodecDims &cd)
 
 hipError_t launch_encode(const CodecDims &cd, const float *field, const float *sub, double tol, uint8_t *out,
                          uint64_t cap, const uint64_t *base, uint64_t *next, uint64_t *flags, uint32_t epoch,
-                         unsigned *ticket, unsigned *err, unsigned long long *stats, hipStream_t s)
+                         unsigned *ticket, unsigned *err, unsigned long long *stats, hipStream_t s,
+                         uint64_t *size_out)
 {
     EncArgs A{};
     A.field = field;
@@ -781,6 +784,7 @@ hipError_t launch_encode(const CodecDims &cd, const float *field, const float *s
     A.flags = flags;
     A.epoch = epoch;
     A.ticket = ticket;
+    A.size_out = size_out;
     A.err = err;
     A.stats = stats;
     const bool vec = cd.dims[0] % 4 == 0;

@@ -185,7 +185,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
     size_t bk, U0, U1, L0, L1, W, Z, UB, DB, V, VU;
     size_t src_tab, rec_tab, tab_bytes;
-    size_t res, dsim, partials, flags, offs, arena;
+    size_t res, dsim, partials, flags, offs, sizes, arena;
     size_t total;
     size_t arena_bytes;
     long long nchunks_max;
@@ -293,6 +293,97 @@ int plan_slots(int nt, size_t mem_budget, size_t S, bool compressed, double F)
     if (slot_bytes < 1) slot_bytes = 1;
     const size_t nslots = mem_budget / slot_bytes;
     return std::max(1, (int)std::min<size_t>((size_t)nt, nslots + 1));
+}
+
+// ------------------------------------------------- compressibility profile planning
+// A profile is kProfile stream sizes (bytes) of one compressed field: prof[0] at k = 0
+// (the empty field) and prof[j] at k_j = ceil(j N / (kProfile - 1)), j >= 1; 0 = unknown.
+constexpr int kProfile = WV_PROFILE;
+
+long long profile_step(int N, int j) { return (j * (long long)N + kProfile - 2) / (kProfile - 1); }
+
+void profile_from_sizes(const std::vector<uint64_t> &sz, int N, double empty_bytes, double *prof)
+{
+    prof[0] = empty_bytes;
+    for (int j = 1; j < kProfile; ++j) {
+        const long long kj = std::min<long long>(std::max<long long>(profile_step(N, j), 1), N);
+        prof[j] = 0.0;
+        for (long long dk = 0; dk <= N; ++dk) {   // nearest state that was stored
+            if (kj - dk >= 1 && sz[kj - dk]) { prof[j] = (double)sz[kj - dk]; break; }
+            if (kj + dk <= N && sz[kj + dk]) { prof[j] = (double)sz[kj + dk]; break; }
+        }
+    }
+}
+
+bool profile_valid(const double *prof)
+{
+    for (int j = 0; j < kProfile; ++j)
+        if (!(prof[j] > 0)) return false;
+    return true;
+}
+
+// stream bytes of u^k, linear between the samples
+double profile_size(const double *prof, int N, long long k)
+{
+    for (int j = 1; j < kProfile; ++j) {
+        const long long k0 = j == 1 ? 0 : profile_step(N, j - 1), k1 = profile_step(N, j);
+        if (k <= k1 || j == kProfile - 1) {
+            const double t = k1 > k0 ? (double)(k - k0) / (double)(k1 - k0) : 1.0;
+            return prof[j - 1] + std::min(1.0, std::max(0.0, t)) * (prof[j] - prof[j - 1]);
+        }
+    }
+    return prof[kProfile - 1];
+}
+
+// Peak bytes of the checkpoint arena for M slots: every stored state takes its stream
+// (twice for the checkpoints that keep both levels, the increment taken as large as u),
+// each rounded up to 256 bytes; slots are freed last-in first-out.
+double simulate_peak(int N, int M, const double *prof)
+{
+    std::vector<int32_t> acts;
+    make_schedule(N, M, acts);
+    const std::vector<char> need2 = second_level_needed(acts, M);
+    std::vector<double> held((size_t)M + 2, 0.0);
+    double live = 0.0, peak = 0.0;
+    for (size_t i = 0; i < acts.size() / 3; ++i) {
+        const int op = acts[3 * i], a = acts[3 * i + 1], b = acts[3 * i + 2];
+        if (op == STORE) {
+            const double one = std::ceil(profile_size(prof, N, a) / 256.0) * 256.0;
+            held[b] = need2[i] ? 2.0 * one : one;
+            live += held[b];
+            peak = std::max(peak, live);
+        } else if (op == FREE) {
+            live -= held[b];
+            held[b] = 0.0;
+        }
+    }
+    return peak;
+}
+
+// Largest M whose simulated peak fits mem_budget (3 % kept for the estimate's error).
+int plan_slots_profile(int N, size_t mem_budget, const double *prof)
+{
+    const double lim = 0.97 * (double)mem_budget;
+    if (simulate_peak(N, N, prof) <= lim) return N;
+    int lo = 1, hi = N;   // peak(lo) fits (M = 1 stores nothing), peak(hi) does not
+    while (hi - lo > 1) {
+        const int mid = lo + (hi - lo) / 2;
+        if (simulate_peak(N, mid, prof) <= lim) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// The uniform planning ratio with which plan_slots gives exactly M slots (0 if M = 1).
+double ratio_for_slots(int N, size_t mem_budget, size_t S, int M)
+{
+    if (M <= 1) return 0.0;
+    double slot = std::floor((double)mem_budget / (double)(M - 1)) - 512.0;
+    if (slot < 1.0) slot = 1.0;
+    double F = (double)S / slot;
+    for (int it = 0; it < 64 && plan_slots(N, mem_budget, S, true, F) < M; ++it) F *= 1.0 + 1e-9;
+    for (int it = 0; it < 64 && plan_slots(N, mem_budget, S, true, F) > M; ++it) F *= 1.0 - 1e-9;
+    return F;
 }
 
 int validate_model(const wv_model *m, Setup &su)
@@ -497,6 +588,7 @@ Layout plan_layout(const wv_model *m, const wv_geom *geo, const Setup &su, int o
         L.flags = take((size_t)cd.nchunks * 8);
         L.offs_n = 2 * (m->nt + 3);
         L.offs = take((size_t)L.offs_n * 8);
+        L.sizes = take((size_t)(m->nt + 1) * 8);   // stream bytes of u^k for each stored state k
         L.arena_bytes = align_up(budget, 256);
         L.arena = take(L.arena_bytes);
     }
@@ -512,7 +604,7 @@ struct Dev {
     unsigned *err;
     double *misfit;
     unsigned long long *stats;
-    uint64_t *zero, *probe_next, *flags, *offs;
+    uint64_t *zero, *probe_next, *flags, *offs, *sizes;
     uint8_t *arena;
     float *res, *dsim;
     double *partials;
@@ -583,6 +675,7 @@ int bind(Dev &d, void *ws, size_t ws_bytes, const Layout &L, int op)
         d.partials = at<double>(d.base, L.partials);
         d.flags = at<uint64_t>(d.base, L.flags);
         d.offs = at<uint64_t>(d.base, L.offs);
+        d.sizes = at<uint64_t>(d.base, L.sizes);
         d.arena = at<uint8_t>(d.base, L.arena);
     }
     return WV_OK;
@@ -762,6 +855,17 @@ long wv_schedule_forward_steps(int nt, int M)
     return (long)forward_steps(nt, M);
 }
 
+int wv_plan(int nt, long long points, size_t mem_budget, const double *profile, int nprofile, int *slots,
+            double *ratio_hint)
+{
+    if (nt < 1 || points < 1 || !profile || nprofile != kProfile || !slots || !ratio_hint) return WV_EINVAL;
+    if (!profile_valid(profile)) return WV_EINVAL;
+    const int M = plan_slots_profile(nt, mem_budget, profile);
+    *slots = M;
+    *ratio_hint = ratio_for_slots(nt, mem_budget, (size_t)points * 8, M);
+    return WV_OK;
+}
+
 int wv_predict(int nt, long long points, size_t mem_budget, int compressed, const wv_costs *costs,
                wv_prediction *out)
 {
@@ -857,14 +961,20 @@ struct GradRun {
     size_t S = 0;                      // bytes of one uncompressed checkpoint
     uint32_t epoch = 0;
     long advances = 0, stores = 0, restores = 0, reverses = 0, decodes = 0, fields = 0;
+    // stream bytes of an all-zero field: prefix plus one bit per block
+    double empty_field_bytes() const
+    {
+        return (double)cd.prefix_bytes + 8.0 * (double)((cd.nblocks + 63) / 64);
+    }
     int max_depth = 0;
 
-    // encodes f (or f - sub) at the device offset *base; *next receives the end
-    int encode_field(const float *f, const float *sub, uint64_t *base, uint64_t *next)
+    // encodes f (or f - sub) at the device offset *base; *next receives the end and
+    // size_out (nullable) the stream's bytes
+    int encode_field(const float *f, const float *sub, uint64_t *base, uint64_t *next, uint64_t *size_out = nullptr)
     {
         ++epoch;
         HIPCHK(launch_encode(cd, f, sub, tol, d.arena, d.L.arena_bytes, base, next, d.flags, epoch,
-                             at<unsigned>(d.base, d.L.bk + kTicket), d.err, d.stats, s));
+                             at<unsigned>(d.base, d.L.bk + kTicket), d.err, d.stats, s, size_out));
         return WV_OK;
     }
 };
@@ -891,6 +1001,7 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
     if (R.G) HIPCHK(launch_fill_f64(R.G, P, 0.0, s));
     HIPCHK(launch_fill_u64(d.offs, d.L.offs_n, 0, s));
     HIPCHK(launch_fill_u64(d.flags, d.L.nchunks_max, 0, s));
+    HIPCHK(launch_fill_u64(d.sizes, N + 1, 0, s));
     if (data) HIPCHK(launch_fill_f32(data, R.geo->nrec, 0.0f, s));
     int gathered = 0;
     bool residual_ready = !R.misfit_mode;
@@ -954,10 +1065,10 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
                 // u^k at offs[2b]; with both levels the increment u^k - u^{k-1} follows at
                 // offs[2b+1]; the next slot starts at offs[2b+2]
                 if (need2[i]) {
-                    if ((rc = R.encode_field(f.u, nullptr, d.offs + 2 * b, d.offs + 2 * b + 1))) break;
+                    if ((rc = R.encode_field(f.u, nullptr, d.offs + 2 * b, d.offs + 2 * b + 1, d.sizes + a))) break;
                     if ((rc = R.encode_field(f.u, f.up, d.offs + 2 * b + 1, d.offs + 2 * b + 2))) break;
                 } else {
-                    if ((rc = R.encode_field(f.u, nullptr, d.offs + 2 * b, d.offs + 2 * b + 2))) break;
+                    if ((rc = R.encode_field(f.u, nullptr, d.offs + 2 * b, d.offs + 2 * b + 2, d.sizes + a))) break;
                 }
                 if (hot_slot == b) hot_slot = -1;
             } else {
@@ -1044,6 +1155,14 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (misfit_out) *misfit_out = mis;
+    double prof[kProfile];
+    for (int j = 0; j < kProfile; ++j) prof[j] = 0.0;
+    if (comp && stats) {
+        // the compressibility profile of this run from the sizes of the states it stored
+        std::vector<uint64_t> sz((size_t)N + 1, 0);
+        HIPCHK(hipMemcpy(sz.data(), d.sizes, sz.size() * 8, hipMemcpyDeviceToHost));
+        profile_from_sizes(sz, N, R.empty_field_bytes(), prof);
+    }
     double kind_ms[6] = {0, 0, 0, 0, 0, 0}, kern_ms[6] = {0, 0, 0, 0, 0, 0};
     if (timer.on && (rc = timer.totals(kind_ms))) return rc;
     if (ktimer.on && (rc = ktimer.totals(kern_ms))) return rc;
@@ -1071,6 +1190,7 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
         stats->ratio_planned = ratio_planned;
         stats->misfit = mis;
         stats->ms_total = ms;
+        for (int j = 0; j < kProfile; ++j) stats->profile[j] = prof[j];
     }
     if (e & 4u) return WV_EARENA;
     if (e & 16u) return WV_EHIP;
@@ -1080,35 +1200,49 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
 
 // Compression ratio of the final state of a plain forward run (the paper's
 // worst-case proxy): encode (u^N, d^N) at the start of the arena.
-int probe_ratio(GradRun &R, double *ratio)
+// A plain forward run of the shot that measures its compressibility: the stream size
+// of u^k at the profile's sample steps and the ratio of the final state (u^N and its
+// increment), the paper's worst-case proxy.  The arena serves as scratch.
+int probe_ratio(GradRun &R, double *ratio, double *prof)
 {
     Dev &d = R.d;
     hipStream_t s = R.s;
-    const long long P = R.su.P;
-    float *data = R.misfit_mode ? (R.dsim_out ? R.dsim_out : d.dsim) : nullptr;
+    const int N = R.m->nt;
     Fwd f{d, R.su, R.geo, s};
     f.at(d.Z, d.Z);
     HIPCHK(launch_fill_u64(d.offs, d.L.offs_n, 0, s));
     HIPCHK(launch_fill_u64(d.flags, d.L.nchunks_max, 0, s));
+    HIPCHK(launch_fill_u64(d.sizes, N + 1, 0, s));
     HIPCHK(launch_fill_u64(at<uint64_t>(d.base, d.L.bk + kStats), 2, 0, s));
-    for (int n = 0; n < R.m->nt; ++n) {
-        int rc = f.step(n, nullptr);
-        if (rc) return rc;
-    }
     int rc;
+    int next_sample = 1;
+    for (int n = 0; n < N; ++n) {
+        if ((rc = f.step(n, nullptr))) return rc;
+        while (next_sample < kProfile && profile_step(N, next_sample) < n + 1) ++next_sample;
+        if (next_sample < kProfile && profile_step(N, next_sample) == n + 1) {
+            // u^{n+1} at the start of the arena, for its size only
+            if ((rc = R.encode_field(f.u, nullptr, d.offs + 2, d.offs + 3, d.sizes + n + 1))) return rc;
+            ++next_sample;
+        }
+    }
+    HIPCHK(launch_fill_u64(at<uint64_t>(d.base, d.L.bk + kStats), 2, 0, s));
     if ((rc = R.encode_field(f.u, nullptr, d.offs + 2, d.offs + 3))) return rc;
     if ((rc = R.encode_field(f.u, f.up, d.offs + 3, d.offs + 4))) return rc;
     unsigned long long st[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(st, d.stats, sizeof(st), hipMemcpyDeviceToHost, s));
+    std::vector<uint64_t> sz((size_t)N + 1, 0);
+    HIPCHK(hipMemcpyAsync(sz.data(), d.sizes, sz.size() * 8, hipMemcpyDeviceToHost, s));
     unsigned e = 0;
     if ((rc = read_err(d, s, &e))) return rc;
-    (void)data;
-    if (e & 4u) {   // did not fit the whole arena: ratio below budget / S
+    if (e & 4u) {   // not even one field fits the arena: plan uncompressed-sized slots
         *ratio = 1.0;
+        for (int j = 0; j < kProfile; ++j) prof[j] = 0.0;
+        HIPCHK(launch_fill_u64(at<uint64_t>(d.base, d.L.bk), kBk / 8, 0, s));
         return WV_OK;
     }
     if (e) return WV_EUNSTABLE;
     *ratio = st[0] > 0 ? (double)R.S / (double)st[0] : 1.0;
+    profile_from_sizes(sz, N, R.empty_field_bytes(), prof);
     HIPCHK(launch_fill_u64(at<uint64_t>(d.base, d.L.bk), kBk / 8, 0, s));
     return WV_OK;
 }
@@ -1136,12 +1270,22 @@ int gradient_common(const wv_model *m, const wv_geom *geo, const float *residual
     const int cdims[3] = {su.g.nx, su.ndim == 3 ? su.g.ny : su.g.nz, su.ndim == 3 ? su.g.nz : 1};
     R.cd = codec_dims(su.ndim, cdims);
     R.S = (size_t)su.P * 8;
+    const int N = m->nt;
     double F = 1.0;
     if (tol > 0) {
-        if (ratio_hint > 0) F = ratio_hint;
-        else if ((rc = probe_ratio(R, &F))) return rc;
+        if (ratio_hint > 0) {
+            F = ratio_hint;
+        } else {
+            // probe the compressibility, then take the largest slot count whose peak
+            // arena use, simulated over the exact schedule with the measured sizes, fits
+            double prof[kProfile];
+            if ((rc = probe_ratio(R, &F, prof))) return rc;
+            if (profile_valid(prof)) {
+                const int Mp = plan_slots_profile(N, mem_budget, prof);
+                if (Mp > 1) F = ratio_for_slots(N, mem_budget, R.S, Mp);
+            }
+        }
     }
-    const int N = m->nt;
     // A compressed run whose checkpoints outgrow the budget (the planned ratio was too
     // optimistic) is repeated with half the planned ratio, i.e. fewer slots; the last
     // attempt plans with the uncompressed size, which always fits.

@@ -176,3 +176,60 @@ def test_ot4_cfl_matches_oracle(order):
         b = oracle.cfl_dt(ndim, h, order, 3500.0, time_order=4)
         assert a == b
         assert a == pytest.approx(3 ** 0.5 * P.cfl_dt(ndim, h, order, 3500.0), rel=1e-15)
+
+
+# ------------------------------------------------------------------ profile planning
+
+def _peak(N, M, prof):
+    """Peak arena bytes of the oracle schedule for M slots with the given profile
+    (independent of the library: oracle schedule, level scan above, linear sizes)."""
+    import math
+    from oracle import schedule as SC
+    acts = [tuple(a) for a in SC.schedule(N, M)]
+    need, _ = _second_level_stores(acts)
+    ks = [0] + [-(-(j * N) // 16) for j in range(1, 17)]
+
+    def size(k):
+        for j in range(1, 17):
+            if k <= ks[j] or j == 16:
+                t = (k - ks[j - 1]) / (ks[j] - ks[j - 1]) if ks[j] > ks[j - 1] else 1.0
+                return prof[j - 1] + min(1.0, max(0.0, t)) * (prof[j] - prof[j - 1])
+    held, live, peak = {}, 0.0, 0.0
+    for i, (op, a, b) in enumerate(acts):
+        if op == 2:
+            one = math.ceil(size(a) / 256.0) * 256.0
+            held[b] = 2 * one if i in need else one
+            live += held[b]
+            peak = max(peak, live)
+        elif op == 4:
+            live -= held.pop(b, 0.0)
+    return peak
+
+
+@pytest.mark.parametrize("shape", ["flat", "growing"])
+def test_plan_is_the_largest_fitting_slot_count(shape):
+    import paper_1810_05268_amd as P
+    N, points = 600, 1_000_000
+    if shape == "flat":
+        prof = [2e5] + [1e6] * 16
+    else:
+        prof = [2e5] + [2e5 + 1e6 * (j / 16) ** 2 for j in range(1, 17)]
+    budget = 120_000_000
+    M, hint = P.plan(N, points, budget, prof)
+    assert 1 < M < N
+    assert _peak(N, M, prof) <= 0.97 * budget < _peak(N, M + 1, prof)
+    # the hint makes a gradient call plan the same M
+    assert P.predict(N, points, budget, True, 1.0, 1.0, t_c=1.0, t_d=1.0, ratio=hint)["slots"] == M
+
+
+def test_plan_growing_profile_holds_more_slots_than_the_final_state_ratio():
+    """Early states are small: planning with the profile beats planning every slot at
+    the final state's size (the paper's worst-case proxy)."""
+    import paper_1810_05268_amd as P
+    N, points, budget = 600, 1_000_000, 120_000_000
+    prof = [2e5] + [2e5 + 1e6 * (j / 16) ** 2 for j in range(1, 17)]
+    M, _ = P.plan(N, points, budget, prof)
+    worst = P.predict(N, points, budget, True, 1.0, 1.0, t_c=1.0, t_d=1.0, ratio=8 * points / (2 * prof[-1]))
+    assert M > worst["slots"]
+    with pytest.raises(P.WvError):
+        P.plan(N, points, budget, [0.0] * 17)
