@@ -138,6 +138,33 @@ def full_trajectory_bytes(st, nt):
     return float(np.sum(np.ceil(sizes / 256.0) * 256.0))
 
 
+def performance_model(nt, points, budget, st_plain, st_comp, hint, sweep_stats):
+    """The run-time model (wv_predict) fed with the per-unit costs of the timed plain
+    and compressed calls: predicted against measured device time of each run, as the
+    paper validates its model.  Sweep runs are predicted with the headline costs and
+    their own planning ratio."""
+    import paper_1810_05268_amd as P
+
+    def phases(st):
+        return st["ms_forward"] + st["ms_adjoint"] + st["ms_store"] + st["ms_restore"]
+    cp, cc = P.costs_from_stats(st_plain), P.costs_from_stats(st_comp)
+    rows = []
+    pr = P.predict(nt, points, budget, False, cp["c_f"], cp["c_r"], t_copy=cp["t_store"])
+    rows.append({"run": "plain", "predicted_ms": pr["ms_total"], "measured_ms": phases(st_plain),
+                 "slots": pr["slots"], "advances": pr["advances"]})
+    pr = P.predict(nt, points, budget, True, cc["c_f"], cc["c_r"], t_c=cc["t_store"], t_d=cc["t_d"], ratio=hint)
+    rows.append({"run": "compressed", "predicted_ms": pr["ms_total"], "measured_ms": phases(st_comp),
+                 "slots": pr["slots"], "advances": pr["advances"]})
+    for tol, h, st in sweep_stats:
+        pr = P.predict(nt, points, budget, True, cc["c_f"], cc["c_r"], t_c=cc["t_store"], t_d=cc["t_d"], ratio=h)
+        rows.append({"run": f"compressed tol {tol:g}", "predicted_ms": pr["ms_total"], "measured_ms": phases(st),
+                     "slots": pr["slots"], "advances": pr["advances"]})
+    for r in rows:
+        r["rel_err"] = (r["predicted_ms"] - r["measured_ms"]) / r["measured_ms"]
+    full = P.predict(nt, points, budget, False, cp["c_f"], cp["c_r"], t_copy=cp["t_store"])["ms_full_storage"]
+    return {"costs_plain": cp, "costs_compressed": cc, "full_storage_ms": full, "runs": rows}
+
+
 def traffic_per_launch():
     """HBM bytes per launch of the forward and adjoint stencils from the committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each
