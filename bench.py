@@ -100,7 +100,7 @@ def ot4_block(shot, budget, tol, steps):
     wc, sc = run(tol, h, gc, steps)
     err = float(torch.linalg.vector_norm(gc - gp) / torch.linalg.vector_norm(gp))
     cp, cc = P.costs_from_stats(sp), P.costs_from_stats(sc)
-    pp = P.predict(shot.nt, G.P, budget, False, cp["c_f"], cp["c_r"], t_copy=cp["t_store"])
+    pp = P.predict(shot.nt, G.P, budget, False, cp["c_f"], cp["c_r"], t_copy=cp["t_store"], slot_bytes=G.slot_bytes)
     pc = P.predict(shot.nt, G.P, budget, True, cc["c_f"], cc["c_r"], t_c=cc["t_store"], t_d=cc["t_d"], ratio=h)
     out = {"dt": dt, "shot_gradient_s": {"plain": statistics.mean(wp), "compressed": statistics.mean(wc)},
            "speedup_vs_plain": statistics.mean(wp) / statistics.mean(wc), "grad_rel_err_vs_plain": err,
@@ -138,7 +138,7 @@ def full_trajectory_bytes(st, nt):
     return float(np.sum(np.ceil(sizes / 256.0) * 256.0))
 
 
-def performance_model(nt, points, budget, st_plain, st_comp, hint, sweep_stats):
+def performance_model(nt, points, slot_bytes, budget, st_plain, st_comp, hint, sweep_stats):
     """The run-time model (wv_predict) fed with the per-unit costs of the timed plain
     and compressed calls: predicted against measured device time of each run, as the
     paper validates its model.  Sweep runs are predicted with the headline costs and
@@ -149,7 +149,7 @@ def performance_model(nt, points, budget, st_plain, st_comp, hint, sweep_stats):
         return st["ms_forward"] + st["ms_adjoint"] + st["ms_store"] + st["ms_restore"]
     cp, cc = P.costs_from_stats(st_plain), P.costs_from_stats(st_comp)
     rows = []
-    pr = P.predict(nt, points, budget, False, cp["c_f"], cp["c_r"], t_copy=cp["t_store"])
+    pr = P.predict(nt, points, budget, False, cp["c_f"], cp["c_r"], t_copy=cp["t_store"], slot_bytes=slot_bytes)
     rows.append({"run": "plain", "predicted_ms": pr["ms_total"], "measured_ms": phases(st_plain),
                  "slots": pr["slots"], "advances": pr["advances"]})
     pr = P.predict(nt, points, budget, True, cc["c_f"], cc["c_r"], t_c=cc["t_store"], t_d=cc["t_d"], ratio=hint)
@@ -161,7 +161,8 @@ def performance_model(nt, points, budget, st_plain, st_comp, hint, sweep_stats):
                      "slots": pr["slots"], "advances": pr["advances"]})
     for r in rows:
         r["rel_err"] = (r["predicted_ms"] - r["measured_ms"]) / r["measured_ms"]
-    full = P.predict(nt, points, budget, False, cp["c_f"], cp["c_r"], t_copy=cp["t_store"])["ms_full_storage"]
+    full = P.predict(nt, points, budget, False, cp["c_f"], cp["c_r"], t_copy=cp["t_store"],
+                     slot_bytes=slot_bytes)["ms_full_storage"]
     return {"costs_plain": cp, "costs_compressed": cc, "full_storage_ms": full, "runs": rows}
 
 
@@ -460,7 +461,7 @@ def main():
     ms_per_store = st["ms_store"] / st["stores"] if st["stores"] else None
     ms_per_decode = st["ms_restore"] / st["decodes"] if st["decodes"] else None
 
-    model = performance_model(shot.nt, Pn, budget, st_plain[0], st_comp[0], hint, sweep_stats)
+    model = performance_model(shot.nt, Pn, G.slot_bytes, budget, st_plain[0], st_comp[0], hint, sweep_stats)
     # compressibility over time at the headline tolerance (untimed)
     stride = max(1, shot.nt // 10)
     cb = G.compressibility(args.tol, stride)

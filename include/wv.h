@@ -152,6 +152,14 @@ double wv_cfl_dt_to(int ndim, const double *h, int space_order, double vmax, int
  * on invalid arguments.  Host only. */
 size_t wv_workspace_bytes(const wv_model *model, const wv_geom *geom, int op, size_t mem_budget);
 
+/* Elements of one solver field array.  The library keeps its own wavefields, w and
+ * uncompressed checkpoints with every row of a 3-D grid padded to a multiple of 32
+ * elements (128 bytes), so that rows start on cache lines; the caller's arrays stay
+ * dense.  An uncompressed checkpoint slot takes 8 times this many bytes; compressed
+ * slots and all ratios refer to the dense 4 P bytes of a field.  Returns 0 on an
+ * invalid model.  Host only. */
+long long wv_field_elements(const wv_model *model);
+
 /* ------------------------------------------------------------------ solver */
 
 /* Forward modelling, eq. (7): data[n][r] = (R u^n)_r for n = 0..nt (row 0 is 0).
@@ -345,6 +353,8 @@ typedef struct {
     double t_c;      /* ms to encode one field */
     double t_d;      /* ms to decode one field */
     double ratio;    /* compression ratio of checkpoint streams (required if compressed) */
+    double slot_bytes; /* bytes of one uncompressed checkpoint slot (8 wv_field_elements);
+                          0 = 8 points */
 } wv_costs;
 
 typedef struct {

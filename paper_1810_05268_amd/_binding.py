@@ -63,7 +63,7 @@ class WvStats(C.Structure):
 
 class WvCosts(C.Structure):
     _fields_ = [("c_f", C.c_double), ("c_r", C.c_double), ("t_copy", C.c_double), ("t_c", C.c_double),
-                ("t_d", C.c_double), ("ratio", C.c_double)]
+                ("t_d", C.c_double), ("ratio", C.c_double), ("slot_bytes", C.c_double)]
 
 
 class WvPrediction(C.Structure):
@@ -82,7 +82,7 @@ class WvResult(C.Structure):
 
 
 # every symbol include/wv.h declares
-SYMBOLS = ["wv_cfl_dt", "wv_cfl_dt_to", "wv_workspace_bytes", "wv_forward", "wv_gradient", "wv_misfit_gradient", "wv_adjoint_src",
+SYMBOLS = ["wv_cfl_dt", "wv_cfl_dt_to", "wv_workspace_bytes", "wv_field_elements", "wv_forward", "wv_gradient", "wv_misfit_gradient", "wv_adjoint_src",
            "wv_pad_velocity", "wv_velocity_gradient", "wv_zfpk_workspace_bytes", "wv_zfpk_max_bytes",
            "wv_zfpk_encode", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_predict", "wv_plan", "wv_compressibility", "wv_strerror",
            "wv_last_error", "wv_version", "wv_engine_create", "wv_engine_submit", "wv_engine_wait",
@@ -109,6 +109,8 @@ def lib():
         L.wv_cfl_dt_to.restype = C.c_double
         L.wv_workspace_bytes.argtypes = [mp, gp, C.c_int, sz]
         L.wv_workspace_bytes.restype = sz
+        L.wv_field_elements.argtypes = [mp]
+        L.wv_field_elements.restype = C.c_longlong
         L.wv_forward.argtypes = [mp, gp, vp, vp, vp, sz, vp]
         L.wv_gradient.argtypes = [mp, gp, vp, sz, C.c_double, C.c_double, vp, stp, vp, sz, vp]
         L.wv_misfit_gradient.argtypes = [mp, gp, vp, sz, C.c_double, C.c_double, dp, vp, vp, stp, vp, sz, vp]
@@ -218,9 +220,10 @@ def plan(nt: int, points: int, mem_budget: int, profile) -> tuple[int, float]:
 
 
 def predict(nt: int, points: int, mem_budget: int, compressed: bool, c_f: float, c_r: float, t_copy: float = 0.0,
-            t_c: float = 0.0, t_d: float = 0.0, ratio: float = 1.0) -> dict:
-    """Predicted gradient time (ms) and counts for the given per-unit costs (host only)."""
-    costs = WvCosts(float(c_f), float(c_r), float(t_copy), float(t_c), float(t_d), float(ratio))
+            t_c: float = 0.0, t_d: float = 0.0, ratio: float = 1.0, slot_bytes: float = 0.0) -> dict:
+    """Predicted gradient time (ms) and counts for the given per-unit costs (host only).
+    slot_bytes: bytes of one uncompressed slot (8 x wv_field_elements; 0 = 8 x points)."""
+    costs = WvCosts(float(c_f), float(c_r), float(t_copy), float(t_c), float(t_d), float(ratio), float(slot_bytes))
     out = WvPrediction()
     _check(lib().wv_predict(int(nt), int(points), int(mem_budget), 1 if compressed else 0, C.byref(costs),
                             C.byref(out)), "wv_predict")
@@ -275,6 +278,13 @@ class Problem:
     def set_vel(self, vel) -> None:
         self.vel = vel
         self.model.vel = _ptr(vel)
+
+    def field_elements(self) -> int:
+        """Elements of one solver field array (rows pitched; 8 x this = one uncompressed slot)."""
+        n = int(lib().wv_field_elements(C.byref(self.model)))
+        if n <= 0:
+            raise WvError(WV_EINVAL, "wv_field_elements")
+        return n
 
     def workspace_bytes(self, op: int, mem_budget: int = 0) -> int:
         b = int(lib().wv_workspace_bytes(C.byref(self.model), C.byref(self.geom), op, int(mem_budget)))

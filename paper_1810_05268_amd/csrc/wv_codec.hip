@@ -220,6 +220,7 @@ struct EncArgs {
     const float *field;
     const float *sub;        // nullable: encode field - sub
     int dims[3];
+    int pitch;               // elements between rows of field and sub
     int nb[3];
     long long nblocks, nchunks, prefix_bytes;
     int ndim;
@@ -249,7 +250,8 @@ __device__ __forceinline__ uint64_t make_flag(uint64_t status, uint32_t epoch, u
 // VEC (dims[0] % 4 == 0) every block is complete along x and each row is one
 // float4 load with no branch, so all 16 row loads of a lane are in flight together.
 template <int ND, bool VEC>
-__device__ __forceinline__ void load_raw(const float *f, const int *dims, int bx, int by, int bz, float *v)
+__device__ __forceinline__ void load_raw(const float *f, const int *dims, int pitch, int bx, int by, int bz,
+                                         float *v)
 {
     constexpr int KZ = ND == 3 ? 4 : 1;
     const int ny = dims[1];
@@ -260,7 +262,7 @@ __device__ __forceinline__ void load_raw(const float *f, const int *dims, int bx
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int y = min(4 * by + j, ny - 1);
-            const float *row = f + ((long long)z * ny + y) * dims[0];
+            const float *row = f + ((long long)z * ny + y) * pitch;
             if constexpr (VEC) {
                 const float4 t = *reinterpret_cast<const float4 *>(row + 4 * bx);
                 v[16 * k + 4 * j + 0] = t.x;
@@ -277,14 +279,14 @@ __device__ __forceinline__ void load_raw(const float *f, const int *dims, int bx
 
 // The block of f, or of f - sub (one binary32 subtraction per value) when sub is set.
 template <int ND, bool VEC>
-__device__ __forceinline__ void load_block(const float *f, const float *sub, const int *dims, int bx, int by, int bz,
-                                           float *v)
+__device__ __forceinline__ void load_block(const float *f, const float *sub, const int *dims, int pitch, int bx,
+                                           int by, int bz, float *v)
 {
     constexpr int S = ND == 3 ? 64 : 16;
-    load_raw<ND, VEC>(f, dims, bx, by, bz, v);
+    load_raw<ND, VEC>(f, dims, pitch, bx, by, bz, v);
     if (sub) {
         float t[S];
-        load_raw<ND, VEC>(sub, dims, bx, by, bz, t);
+        load_raw<ND, VEC>(sub, dims, pitch, bx, by, bz, t);
 #pragma unroll
         for (int i = 0; i < S; ++i) v[i] -= t[i];
     }
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
         bz = (int)(b / ((long long)A.nb[0] * A.nb[1]));
     }
     float v[S];
-    if (valid) load_block<ND, VEC>(A.field, A.sub, A.dims, bx, by, bz, v);
+    if (valid) load_block<ND, VEC>(A.field, A.sub, A.dims, A.pitch, bx, by, bz, v);
     else {
 #pragma unroll
         for (int i = 0; i < S; ++i) v[i] = 0.0f;
@@ -566,6 +568,7 @@ struct DecArgs {
     uint64_t cap;        // bytes readable from `in`
     float *field;
     int dims[3];
+    int pitch;           // elements between rows of the field
     int nb[3];
     long long nblocks, nchunks, prefix_bytes;
 };
@@ -593,7 +596,7 @@ __global__ __launch_bounds__(256) void decode_kernel(DecArgs A)
                     for (int i = 0; i < 4; ++i) {
                         const int x = 4 * bx + i, y = 4 * by + j, z = 4 * bz + k;
                         if (x < A.dims[0] && y < A.dims[1] && z < nzz) {
-                            const long long p = ((long long)z * A.dims[1] + y) * A.dims[0] + x;
+                            const long long p = ((long long)z * A.dims[1] + y) * A.pitch + x;
                             A.field[p] = A.sub ? A.sub[p] : 0.0f;
                         }
                     }
@@ -710,7 +713,7 @@ __global__ __launch_bounds__(256) void decode_kernel(DecArgs A)
         for (int j = 0; j < 4; ++j) {
             const int y = 4 * by + j;
             if (y >= A.dims[1] || z >= nzz) continue;
-            const long long r0 = ((long long)z * A.dims[1] + y) * A.dims[0];
+            const long long r0 = ((long long)z * A.dims[1] + y) * A.pitch;
             float *row = A.field + r0;
             if (VEC) {
                 float4 o = make_float4(out[16 * k + 4 * j + 0], out[16 * k + 4 * j + 1], out[16 * k + 4 * j + 2],
@@ -734,10 +737,11 @@ __global__ __launch_bounds__(256) void decode_kernel(DecArgs A)
 
 }  // namespace
 
-CodecDims codec_dims(int ndim, const int *dims)
+CodecDims codec_dims(int ndim, const int *dims, int pitch)
 {
     CodecDims cd{};
     cd.ndim = ndim;
+    cd.pitch = pitch > 0 ? pitch : dims[0];
     for (int a = 0; a < 3; ++a) {
         cd.dims[a] = (a < ndim) ? dims[a] : 1;
         cd.nb[a] = (a < ndim) ? (dims[a] + 3) / 4 : 1;
@@ -769,6 +773,7 @@ hipError_t launch_encode(const CodecDims &cd, const float *field, const float *s
         A.dims[a] = cd.dims[a];
         A.nb[a] = cd.nb[a];
     }
+    A.pitch = cd.pitch;
     A.nblocks = cd.nblocks;
     A.nchunks = cd.nchunks;
     A.prefix_bytes = cd.prefix_bytes;
@@ -787,7 +792,7 @@ hipError_t launch_encode(const CodecDims &cd, const float *field, const float *s
     A.size_out = size_out;
     A.err = err;
     A.stats = stats;
-    const bool vec = cd.dims[0] % 4 == 0;
+    const bool vec = cd.dims[0] % 4 == 0 && cd.pitch % 4 == 0;
     const dim3 grid((unsigned)cd.nchunks);
     if (cd.ndim == 3) {
         if (vec) hipLaunchKernelGGL((encode_kernel<3, true>), grid, dim3(256), 0, s, A);
@@ -812,10 +817,11 @@ hipError_t launch_decode(const CodecDims &cd, const uint8_t *in, const uint64_t 
         A.dims[a] = cd.dims[a];
         A.nb[a] = cd.nb[a];
     }
+    A.pitch = cd.pitch;
     A.nblocks = cd.nblocks;
     A.nchunks = cd.nchunks;
     A.prefix_bytes = cd.prefix_bytes;
-    const bool vec = cd.dims[0] % 4 == 0;
+    const bool vec = cd.dims[0] % 4 == 0 && cd.pitch % 4 == 0;
     const dim3 grid((unsigned)cd.nchunks);
     if (cd.ndim == 3) {
         if (vec) hipLaunchKernelGGL((decode_kernel<3, true>), grid, dim3(256), 0, s, A);

@@ -199,7 +199,8 @@ constexpr int kParts = 1024;
 
 struct Setup {
     Grid g;
-    long long P = 0;
+    long long P = 0;        // grid points (the caller's dense arrays)
+    long long Pf = 0;       // elements of one solver field array (rows pitched, see Grid)
     int ndim = 0, N[3] = {1, 1, 1};
     int nc = 4;
     // host tables, packed
@@ -410,7 +411,6 @@ int validate_model(const wv_model *m, Setup &su)
     g.ndim = m->ndim;
     g.K = m->space_order / 2;
     g.time_order = m->time_order == 4 ? 4 : 2;
-    g.P = P;
     double a[kMaxK + 1];
     fd_weights(g.K, a);
     // array axes: x = model axis 0; 3-D: y = axis 1, z = axis 2; 2-D: z = axis 1
@@ -418,6 +418,10 @@ int validate_model(const wv_model *m, Setup &su)
     g.nx = su.N[0];
     g.ny = ax_y >= 0 ? su.N[ax_y] : 1;
     g.nz = su.N[ax_z];
+    g.px = m->ndim == 3 ? (g.nx + 31) / 32 * 32 : g.nx;
+    su.Pf = (long long)g.px * g.ny * g.nz;
+    if (su.Pf >= (1LL << 31)) return WV_EINVAL;
+    g.P = su.Pf;
     const int axes[3] = {0, ax_y, ax_z};
     float *cc[3] = {g.cx, g.cy, g.cz};
     float *dd[3] = {&g.dampx, &g.dampy, &g.dampz};
@@ -470,7 +474,7 @@ int point_weights(const wv_model *m, const Setup &su, const double *xyz, int *id
             const int bit = (c >> d) & 1;
             const int ii = std::min(i0[d] + bit, su.N[d] - 1);
             p += (long long)ii * stride;
-            stride *= su.N[d];
+            stride *= d == 0 ? su.g.px : su.N[d];   // pitched field arrays
             w *= bit ? fr[d] : 1.0 - fr[d];
         }
         idx[c] = (int)p;
@@ -548,7 +552,7 @@ size_t tab_bytes(const Setup &su, bool rec)
 size_t field_stream_max(const Setup &su)
 {
     const int cdims[3] = {su.g.nx, su.ndim == 3 ? su.g.ny : su.g.nz, su.ndim == 3 ? su.g.nz : 1};
-    return codec_max_bytes(codec_dims(su.ndim, cdims)) + 256;
+    return codec_max_bytes(codec_dims(su.ndim, cdims, su.g.px)) + 256;
 }
 
 Layout plan_layout(const wv_model *m, const wv_geom *geo, const Setup &su, int op, size_t budget)
@@ -560,7 +564,7 @@ Layout plan_layout(const wv_model *m, const wv_geom *geo, const Setup &su, int o
         off = align_up(off + bytes, 256);
         return o;
     };
-    const size_t fb = (size_t)su.P * 4;
+    const size_t fb = (size_t)su.Pf * 4;
     L.bk = take(kBk);
     L.U0 = take(fb);
     L.U1 = take(fb);
@@ -583,7 +587,7 @@ Layout plan_layout(const wv_model *m, const wv_geom *geo, const Setup &su, int o
         const int dims[3] = {su.g.nx, su.g.ny, su.g.nz};
         const int cdims[3] = {su.g.nx, su.ndim == 3 ? su.g.ny : su.g.nz, su.ndim == 3 ? su.g.nz : 1};
         (void)dims;
-        const CodecDims cd = codec_dims(su.ndim, cdims);
+        const CodecDims cd = codec_dims(su.ndim, cdims, su.g.px);
         L.nchunks_max = cd.nchunks;
         L.flags = take((size_t)cd.nchunks * 8);
         L.offs_n = 2 * (m->nt + 3);
@@ -694,8 +698,13 @@ int start(Dev &d, const wv_model *m, const Setup &su, hipStream_t s)
     HIPCHK(launch_fill_u64(at<uint64_t>(d.base, d.L.bk), kBk / 8, 0, s));
     int rc = upload_tables(d, su, s);
     if (rc) return rc;
-    HIPCHK(launch_setup_w(m->vel, d.W, su.P, m->dt, m->vmax, d.err, s));
-    HIPCHK(launch_fill_f32(d.Z, su.P, 0.0f, s));
+    HIPCHK(launch_setup_w(su.g, m->vel, d.W, m->dt, m->vmax, d.err, s));
+    // every field array starts at zero: kernels write only the nx valid columns of a
+    // pitched row, so the pad columns keep this zero for the whole call (and whole-array
+    // scans such as the finiteness check read no stale workspace bytes)
+    float *const fields[] = {d.Z, d.U[0], d.U[1], d.Lm[0], d.Lm[1], d.UB, d.DB, d.V, d.VU};
+    for (float *f : fields)
+        if (f) HIPCHK(launch_fill_f32(f, su.Pf, 0.0f, s));
     unsigned e = 0;
     rc = read_err(d, s, &e);
     if (rc) return rc;
@@ -843,6 +852,13 @@ double wv_cfl_dt(int ndim, const double *h, int space_order, double vmax)
     return cfl_limit(ndim, h, space_order, vmax);
 }
 
+long long wv_field_elements(const wv_model *m)
+{
+    Setup su;
+    if (validate_model(m, su)) return 0;
+    return su.Pf;
+}
+
 double wv_cfl_dt_to(int ndim, const double *h, int space_order, double vmax, int time_order)
 {
     if (!h || (time_order != 2 && time_order != 4)) return -1.0;
@@ -871,7 +887,7 @@ int wv_predict(int nt, long long points, size_t mem_budget, int compressed, cons
 {
     if (nt < 1 || points < 1 || !costs || !out) return WV_EINVAL;
     if (compressed && !(costs->ratio > 0)) return WV_EINVAL;
-    const size_t S = (size_t)points * 8;
+    const size_t S = compressed || !(costs->slot_bytes > 0) ? (size_t)points * 8 : (size_t)costs->slot_bytes;
     const int M = plan_slots(nt, mem_budget, S, compressed != 0, compressed ? costs->ratio : 1.0);
     if (M < 1) return WV_EBUDGET;
     std::vector<int32_t> acts;
@@ -930,10 +946,12 @@ int wv_forward(const wv_model *m, const wv_geom *geo, float *data, float *state_
     for (int n = 0; n < m->nt; ++n)
         if ((rc = f.step(n, data + (size_t)(n + 1) * geo->nrec))) return rc;
     if (state_out) {
-        HIPCHK(hipMemcpyAsync(state_out, f.u, (size_t)su.P * 4, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(state_out + su.P, f.up, (size_t)su.P * 4, hipMemcpyDeviceToDevice, s));
+        // pitched solver rows to the caller's dense layout
+        const size_t row = (size_t)su.g.nx * 4, pitch = (size_t)su.g.px * 4, rows = (size_t)su.g.ny * su.g.nz;
+        HIPCHK(hipMemcpy2DAsync(state_out, row, f.u, pitch, row, rows, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpy2DAsync(state_out + su.P, row, f.up, pitch, row, rows, hipMemcpyDeviceToDevice, s));
     }
-    HIPCHK(launch_check_finite(f.u, su.P, d.err, s));
+    HIPCHK(launch_check_finite(f.u, su.Pf, d.err, s));
     unsigned e = 0;
     if ((rc = read_err(d, s, &e))) return rc;
     return (e & 8u) ? WV_EUNSTABLE : WV_OK;
@@ -958,7 +976,8 @@ struct GradRun {
     float *src_adj = nullptr;
     double *G = nullptr;
     CodecDims cd{};
-    size_t S = 0;                      // bytes of one uncompressed checkpoint
+    size_t S = 0;                      // bytes of one uncompressed checkpoint (two field arrays)
+    size_t Sd = 0;                     // 8 bytes per grid point: the dense pair that ratios refer to
     uint32_t epoch = 0;
     long advances = 0, stores = 0, restores = 0, reverses = 0, decodes = 0, fields = 0;
     // stream bytes of an all-zero field: prefix plus one bit per block
@@ -985,7 +1004,7 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
     Dev &d = R.d;
     hipStream_t s = R.s;
     const int N = m->nt;
-    const long long P = R.su.P;
+    const long long P = R.su.Pf;   // one field array
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -998,7 +1017,7 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
     int hot_slot = -1, hot_k = -1;   // checkpoint currently decoded in the base pair
     HIPCHK(launch_fill_f32(d.Lm[0], P, 0.0f, s));
     HIPCHK(launch_fill_f32(d.Lm[1], P, 0.0f, s));
-    if (R.G) HIPCHK(launch_fill_f64(R.G, P, 0.0, s));
+    if (R.G) HIPCHK(launch_fill_f64(R.G, R.su.P, 0.0, s));   // the caller's dense gradient
     HIPCHK(launch_fill_u64(d.offs, d.L.offs_n, 0, s));
     HIPCHK(launch_fill_u64(d.flags, d.L.nchunks_max, 0, s));
     HIPCHK(launch_fill_u64(d.sizes, N + 1, 0, s));
@@ -1183,7 +1202,7 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
         stats->decodes = R.decodes;
         stats->reverses = R.reverses;
         stats->slots = M;
-        const double raw = (double)R.fields * (double)(R.S / 2);   // binary32 fields written
+        const double raw = (double)R.fields * (double)(R.Sd / 2);   // binary32 fields written (dense)
         stats->bytes_stored = comp ? (double)st[0] : raw;
         stats->peak_bytes = comp ? (double)st[1] : (double)R.max_depth * (double)R.S;
         stats->ratio = stats->bytes_stored > 0 ? raw / stats->bytes_stored : 1.0;
@@ -1241,7 +1260,7 @@ int probe_ratio(GradRun &R, double *ratio, double *prof)
         return WV_OK;
     }
     if (e) return WV_EUNSTABLE;
-    *ratio = st[0] > 0 ? (double)R.S / (double)st[0] : 1.0;
+    *ratio = st[0] > 0 ? (double)R.Sd / (double)st[0] : 1.0;
     profile_from_sizes(sz, N, R.empty_field_bytes(), prof);
     HIPCHK(launch_fill_u64(at<uint64_t>(d.base, d.L.bk), kBk / 8, 0, s));
     return WV_OK;
@@ -1268,8 +1287,9 @@ int gradient_common(const wv_model *m, const wv_geom *geo, const float *residual
     R.dsim_out = d_sim;
     R.G = grad_m;
     const int cdims[3] = {su.g.nx, su.ndim == 3 ? su.g.ny : su.g.nz, su.ndim == 3 ? su.g.nz : 1};
-    R.cd = codec_dims(su.ndim, cdims);
-    R.S = (size_t)su.P * 8;
+    R.cd = codec_dims(su.ndim, cdims, su.g.px);
+    R.S = (size_t)su.Pf * 8;
+    R.Sd = (size_t)su.P * 8;
     const int N = m->nt;
     double F = 1.0;
     if (tol > 0) {
@@ -1282,7 +1302,7 @@ int gradient_common(const wv_model *m, const wv_geom *geo, const float *residual
             if ((rc = probe_ratio(R, &F, prof))) return rc;
             if (profile_valid(prof)) {
                 const int Mp = plan_slots_profile(N, mem_budget, prof);
-                if (Mp > 1) F = ratio_for_slots(N, mem_budget, R.S, Mp);
+                if (Mp > 1) F = ratio_for_slots(N, mem_budget, R.Sd, Mp);
             }
         }
     }
@@ -1290,7 +1310,9 @@ int gradient_common(const wv_model *m, const wv_geom *geo, const float *residual
     // optimistic) is repeated with half the planned ratio, i.e. fewer slots; the last
     // attempt plans with the uncompressed size, which always fits.
     for (int attempt = 0;; ++attempt) {
-        const int M = plan_slots(N, mem_budget, R.S, tol > 0, F);
+        // an uncompressed slot is two field arrays; a compressed one is sized from the
+        // dense field bytes and the ratio
+        const int M = plan_slots(N, mem_budget, tol > 0 ? R.Sd : R.S, tol > 0, F);
         if (M < 1) return WV_EBUDGET;
         rc = run_gradient(R, M, F, stats, misfit);
         if (rc != WV_EARENA || tol <= 0 || F <= 1.0 || attempt >= kArenaRetries) {
@@ -1340,7 +1362,8 @@ int wv_adjoint_src(const wv_model *m, const wv_geom *geo, const float *residual,
     GradRun R{m, geo, su, d, s, 0.0, false, true};
     R.residual = residual;
     R.src_adj = src_adj;
-    R.S = (size_t)su.P * 8;
+    R.S = (size_t)su.Pf * 8;
+    R.Sd = (size_t)su.P * 8;
     return run_gradient(R, 1, 1.0, nullptr, nullptr);
 }
 
@@ -1360,8 +1383,9 @@ int wv_compressibility(const wv_model *m, const wv_geom *geo, double tol, int st
     if ((rc = start(d, m, su, s))) return rc;
     GradRun R{m, geo, su, d, s, tol, false, false};
     const int cdims[3] = {su.g.nx, su.ndim == 3 ? su.g.ny : su.g.nz, su.ndim == 3 ? su.g.nz : 1};
-    R.cd = codec_dims(su.ndim, cdims);
-    R.S = (size_t)su.P * 8;
+    R.cd = codec_dims(su.ndim, cdims, su.g.px);
+    R.S = (size_t)su.Pf * 8;
+    R.Sd = (size_t)su.P * 8;
     Fwd f{d, su, geo, s};
     f.at(d.Z, d.Z);
     int k = 0;

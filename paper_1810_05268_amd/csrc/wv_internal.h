@@ -15,8 +15,14 @@ constexpr int kBlocksPerChunk = 256; // codec: blocks per chunk (one workgroup)
 // Geometry and coefficients of one padded grid, as the stencil kernels see it.
 // Axes are named for the array layout: x contiguous, z slowest.  In 2-D, y is
 // absent (ny = 1) and the model's second axis is z.
+// The solver's field arrays (wavefields, w, checkpoint slots) are pitched: point
+// (x, y, z) sits at x + px (y + ny z), with px = nx rounded up to 32 in 3-D, so that
+// every row starts on a 128-byte line (columns nx..px-1 hold zeros and are never
+// read as grid points).  In 2-D px = nx.  Arrays the caller owns (velocity,
+// gradient, final state) are dense: x + nx (y + ny z).
 struct Grid {
     int nx, ny, nz;          // padded extents
+    int px;                  // row pitch of the solver's field arrays (elements)
     int ix0[3], ix1[3];      // interior index range [ix0, ix1] per array axis (x, y, z)
     float cx[kMaxK + 1];     // a_k / h^2 per axis, k = 1..K;
     float cy[kMaxK + 1];     // cy[0] = h_x^2/h_y^2 and cz[0] = h_x^2/h_z^2 (the 3-D kernel
@@ -26,7 +32,7 @@ struct Grid {
     int K;
     int ndim;
     int time_order;          // 2 (OT2) or 4 (OT4)
-    long long P;
+    long long P;             // elements of one field array: px * ny * nz
 };
 
 // Sparse point operators (sources / receivers), built on the host.
@@ -74,8 +80,9 @@ hipError_t launch_inject_res(const Grid &g, const Sparse &sp, const float *r_row
 hipError_t launch_gather(const Sparse &sp, const float *f, float *out, hipStream_t s);
 // Sum over sources of the gathered field: out[0] = sum_s (S f)_s.
 hipError_t launch_gather_sum(const Sparse &sp, const float *f, float *out, hipStream_t s);
-// w = dt^2 vel^2 and validation; err bit 1: non-finite or out of (0, vmax].
-hipError_t launch_setup_w(const float *vel, float *w, long long P, double dt, double vmax, unsigned *err,
+// w = dt^2 vel^2 (vel dense, w pitched, pad columns 0) and validation; err bit 1:
+// non-finite or out of (0, vmax].
+hipError_t launch_setup_w(const Grid &g, const float *vel, float *w, double dt, double vmax, unsigned *err,
                           hipStream_t s);
 hipError_t launch_fill_f32(float *p, long long n, float v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, long long n, double v, hipStream_t s);
@@ -92,12 +99,14 @@ hipError_t launch_check_finite(const float *f, long long n, unsigned *err, hipSt
 struct CodecDims {
     int ndim;
     int dims[3];       // axis 0 fastest; 2-D: dims[2] = 1
+    int pitch;         // elements from one row (axis 0) of the field array to the next (>= dims[0])
     int nb[3];         // blocks per axis
     long long nblocks;
     long long nchunks;
     long long prefix_bytes;  // header + chunk table + block lengths
 };
-CodecDims codec_dims(int ndim, const int *dims);
+// pitch 0: dense rows (pitch = dims[0])
+CodecDims codec_dims(int ndim, const int *dims, int pitch = 0);
 size_t codec_max_bytes(const CodecDims &cd);
 // Encode field (or field - sub, in binary32, when sub is not null) into out + *base
 // (device offset), capacity cap bytes from `out`.

@@ -30,6 +30,11 @@
 //
 // Workgroup ids are remapped so that every XCD (each has its own L2) receives a
 // contiguous run of neighbouring tiles, whose halos then hit the same L2.
+//
+// Field arrays are pitched (rows of px >= nx elements, px a multiple of 32 in 3-D):
+// a 32-wide tile row is then exactly one 128-byte line.  With a row length that is
+// not a multiple of 32 (e.g. 400), every other tile row straddles two lines, which
+// measured 10-15 % slower.  The binary64 gradient belongs to the caller and is dense.
 #include <hip/hip_ext.h>
 
 #include "wv_internal.h"
@@ -85,14 +90,14 @@ __device__ __forceinline__ void ntstore4(float *p, float a, float b, float c, fl
 //   * x, y neighbours: the centre plane staged in LDS with its halos (x halo padded to
 //     a multiple of four columns so that every LDS access is an aligned float4),
 //     double buffered, one barrier per plane;
-//   * software pipeline: while plane z is computed, the global loads plane z+1
-//     needs (its point operands and the next queue front) are already in flight in a
-//     second register stage;
-//   * halos are read K+1 planes ahead, together with the queue front of the same
-//     plane, i.e. when the neighbouring tiles stream that plane from HBM, so they
-//     hit in L2; each lane parks its halo float4 in its own LDS ring slots;
+//   * software pipeline: the global loads a plane needs (its point operands, its
+//     halo and the queue front K planes further on) are issued into a register
+//     stage AHEAD planes before the plane is computed (two where a third stage fits
+//     in the registers, else one);
+//   * the halo of plane z+1 goes from its stage straight into the next LDS buffer;
 //   * interior LDS values come from the queue, so HBM is read once per value
-//     (plus the 2K-plane warm-up of each z chunk); halos come from L2.
+//     (plus the 2K-plane warm-up of each z chunk); halos are lines the neighbouring
+//     tiles of the same XCD read as their interior.
 // VEC: nx % 4 == 0, every float4 of a row is either inside or outside the grid.
 // `prev` (u^{n-1}) and `fout` (u^{n+1}) may be the same array: each point of it is
 // read and then written by the same lane only.
@@ -122,9 +127,10 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
     constexpr int NHX = 2 * TY * (HX / 4);        // x-halo float4s per plane
     constexpr int NH = NHX + 2 * K * (TX / 4);    // all halo float4s per plane (<= 256)
     static_assert(NH <= 256, "one halo float4 per lane at most");
-    constexpr int R = K + 2;                     // halo ring: planes z+1 .. z+1+K in flight
+    // planes between a stage's loads and its use: two where three stages fit in 256
+    // registers without spilling (no gradient, aligned rows, not the OT4 update)
+    constexpr int AHEAD = (!GRAD && VEC && MODE != kOT4) ? 2 : 1;
     __shared__ __align__(16) float tile[2][LY][LX];
-    __shared__ __align__(16) float4 ring[R][256];   // lane-private slots: no barrier needed
 
     const int nwg = tiles_x * tiles_y * zchunks;
     const int lid = xcd_remap(blockIdx.x, nwg);
@@ -136,13 +142,13 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
 
     const int tid = threadIdx.x;
     const int tx4 = tid & 7, ty = tid >> 3;
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
-    const long long sxy = (long long)nx * ny;
+    const int nx = g.nx, ny = g.ny, nz = g.nz, px = g.px;
+    const long long sxy = (long long)px * ny;     // pitched field plane
     const int x0 = tix * TX + 4 * tx4;
     const int y = tiy * TY + ty;
     const bool rowin = y < ny;
     const bool ptin = rowin && x0 < nx;
-    const long long rowoff = (long long)(rowin ? y : 0) * nx;
+    const long long rowoff = (long long)(rowin ? y : 0) * px;
 
     // halo float4 of this lane: source in the plane and place in the tile
     int hrow = 0, hcol = 0, hgx = -1, hgy = -1;
@@ -172,7 +178,7 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
     auto load4 = [&](const float *base, int z, int yy, int gx, bool ok) -> float4 {
         const bool in = ok && z >= 0 && z < nz && yy >= 0 && yy < ny;
         const int zc = min(max(z, 0), nz - 1), yc = min(max(yy, 0), ny - 1);
-        const float *row = base + (long long)zc * sxy + (long long)yc * nx;
+        const float *row = base + (long long)zc * sxy + (long long)yc * px;
         float4 v;
         if constexpr (VEC) {
             const bool inx = in && gx >= 0 && gx < nx;
@@ -202,7 +208,7 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
     // they are loaded from the clamped address without zeroing
     auto load4p = [&](const float *base, int z, int gx) -> float4 {
         const int zc = min(z, nz - 1), yc = min(y, ny - 1);
-        const float *row = base + (long long)zc * sxy + (long long)yc * nx;
+        const float *row = base + (long long)zc * sxy + (long long)yc * px;
         if constexpr (VEC) return ntload4(row + min(gx, nx - 4));
         return make_float4(row[min(gx + 0, nx - 1)], row[min(gx + 1, nx - 1)], row[min(gx + 2, nx - 1)],
                            row[min(gx + 3, nx - 1)]);
@@ -213,7 +219,7 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
         if constexpr (MODE == kOT4 || (MODE == kLapW && GRAD)) S.c = load4p(xtra, z, x0);
         if constexpr (GRAD) {
             if constexpr (MODE != kLapW) S.u = load4p(uk, z, x0);
-            const long long pg = (long long)min(z, nz - 1) * sxy + (long long)min(y, ny - 1) * nx;
+            const long long pg = ((long long)min(z, nz - 1) * ny + min(y, ny - 1)) * nx;   // dense
             if constexpr (VEC) {
                 // two 16-byte loads per lane, normally cached: the line a lane pair shares
                 // stays in L2 between them
@@ -226,10 +232,7 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
             }
         }
         const bool more = z + 1 < z1;
-        // the halo of plane z+1+K is read together with the queue front of the same
-        // plane (which is the neighbouring tiles' interior), so it hits in L2; it waits
-        // K+1 planes in the lane's ring slots before the tile needs it
-        S.h = load4(fin, z + 1 + K, hgy, hgx, hact && z + 1 + K < z1);
+        S.h = load4(fin, z + 1, hgy, hgx, hact && more);
         S.f = load4(fin, z + 1 + K, y, x0, more && rowin);
     };
 
@@ -240,16 +243,13 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
         const float4 v = load4(fin, z0 - K + j, y, x0, rowin);
         q[0][j] = v.x; q[1][j] = v.y; q[2][j] = v.z; q[3][j] = v.w;
     }
-    Stage A, B;
+    Stage A, B, C;
     fill(A, z0);
+    if constexpr (AHEAD == 2) fill(B, z0 + 1);
     {
         const float4 hv = load4(fin, z0, hgy, hgx, hact);
         *reinterpret_cast<float4 *>(&tile[0][ty + K][HX + 4 * tx4]) = make_float4(q[0][K], q[1][K], q[2][K], q[3][K]);
-        if (tid < NH) {
-            *reinterpret_cast<float4 *>(&tile[0][hrow][hcol]) = hv;
-#pragma unroll
-            for (int j = 1; j <= K; ++j) ring[(z0 + j) % R][tid] = load4(fin, z0 + j, hgy, hgx, hact && z0 + j < z1);
-        }
+        if (tid < NH) *reinterpret_cast<float4 *>(&tile[0][hrow][hcol]) = hv;
     }
     __syncthreads();
 
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
 #pragma unroll
             for (int i = 0; i < 4; ++i) gold[i] = S.g[i];
         }
-        fill(N, z + 1);
+        fill(N, z + AHEAD);
         const int cur = (z - z0) & 1;
         // x neighbours: NXV aligned float4 around the lane's four points
         float xr[4 * NXV];
@@ -343,6 +343,7 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
         }
         if (ptin) {
             const long long p0 = (long long)z * sxy + rowoff + x0;
+            const long long p0g = ((long long)z * ny + y) * nx + x0;   // dense gradient
             if constexpr (VEC) {
                 ntstore4(fout + p0, on[0], on[1], on[2], on[3]);
             } else {
@@ -357,22 +358,19 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
                     gn[i] = MODE == kLapW ? gold[i] + gscale * (double)on[i] * (double)cin[i]
                                           : gold[i] + gscale * (double)uin[i] * (double)wl[i];
                 if constexpr (VEC) {
-                    *reinterpret_cast<double2 *>(&G[p0]) = make_double2(gn[0], gn[1]);
-                    *reinterpret_cast<double2 *>(&G[p0 + 2]) = make_double2(gn[2], gn[3]);
+                    *reinterpret_cast<double2 *>(&G[p0g]) = make_double2(gn[0], gn[1]);
+                    *reinterpret_cast<double2 *>(&G[p0g + 2]) = make_double2(gn[2], gn[3]);
                 } else {
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
-                        if (x0 + i < nx) G[p0 + i] = gn[i];
+                        if (x0 + i < nx) G[p0g + i] = gn[i];
                 }
             }
         }
         // stage plane z+1 (after the last plane this buffer is simply not read)
         *reinterpret_cast<float4 *>(&tile[cur ^ 1][ty + K][HX + 4 * tx4]) =
             make_float4(q[0][K + 1], q[1][K + 1], q[2][K + 1], q[3][K + 1]);
-        if (tid < NH) {
-            ring[(z + 1 + K) % R][tid] = S.h;
-            *reinterpret_cast<float4 *>(&tile[cur ^ 1][hrow][hcol]) = ring[(z + 1) % R][tid];
-        }
+        if (tid < NH) *reinterpret_cast<float4 *>(&tile[cur ^ 1][hrow][hcol]) = S.h;
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -381,30 +379,47 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
         }
         q[0][2 * K] = S.f.x; q[1][2 * K] = S.f.y; q[2][2 * K] = S.f.z; q[3][2 * K] = S.f.w;
     };
-    // several planes per trip for the forward step (the wait pass drains outstanding
-    // loads at the back-edge); the adjoint step, whose stage also carries u^k and the
-    // binary64 gradient of the next plane, runs one plane per trip and hands the stage
-    // over by copy, which keeps it within 256 registers without spilling
+    // AHEAD = 2: three stages in rotation, six planes per trip; otherwise without the
+    // gradient two stages, four planes per trip (the wait pass drains outstanding loads
+    // at the back-edge); with the gradient, whose stage also carries u^k and the
+    // binary64 gradient, one plane per trip and the stage handed over by copy, which
+    // keeps it within 256 registers without spilling
     int z = z0;
-    if constexpr (!GRAD) {
+    if constexpr (AHEAD == 2) {
+        for (; z + 5 < z1; z += 6) {
+            step(z, A, C);
+            step(z + 1, B, A);
+            step(z + 2, C, B);
+            step(z + 3, A, C);
+            step(z + 4, B, A);
+            step(z + 5, C, B);
+        }
+        for (; z + 2 < z1; z += 3) {
+            step(z, A, C);
+            step(z + 1, B, A);
+            step(z + 2, C, B);
+        }
+        if (z < z1) step(z, A, C);
+        if (z + 1 < z1) step(z + 1, B, A);
+    } else if constexpr (!GRAD) {
+        (void)C;
         for (; z + 3 < z1; z += 4) {
             step(z, A, B);
             step(z + 1, B, A);
             step(z + 2, A, B);
             step(z + 3, B, A);
         }
-    }
-    if constexpr (GRAD) {
-        for (; z < z1; ++z) {
-            step(z, A, B);
-            A = B;
-        }
-    } else {
         for (; z + 1 < z1; z += 2) {
             step(z, A, B);
             step(z + 1, B, A);
         }
         if (z < z1) step(z, A, B);
+    } else {
+        (void)C;
+        for (; z < z1; ++z) {
+            step(z, A, B);
+            A = B;
+        }
     }
 }
 
@@ -496,15 +511,15 @@ __global__ void inject_kernel(Grid g, Sparse sp, const float *__restrict__ vals,
     const int p = sp.s_pts[i];
     float s = 0.0f;
     for (int e = sp.s_start[i]; e < sp.s_start[i + 1]; ++e) s = fmaf(sp.s_wt[e], vals[sp.s_col[e]], s);
-    const long long sxy = (long long)g.nx * g.ny;
+    const long long sxy = (long long)g.px * g.ny;   // p indexes the pitched field arrays
     const int z = (int)(p / sxy);
     const int rem = (int)(p - z * sxy);
-    const int y = rem / g.nx, x = rem - (rem / g.nx) * g.nx;
+    const int y = rem / g.px, x = rem - (rem / g.px) * g.px;
     const float a = damping(g, x, y, z);
     const float wi = w[p] * s;
     const float inj = (a == 0.0f) ? wi : wi / (1.0f + a);
     fout[p] += inj;
-    if constexpr (GRAD) G[p] += gscale * (double)uk[p] * (double)wi;
+    if constexpr (GRAD) G[((long long)z * g.ny + y) * g.nx + x] += gscale * (double)uk[p] * (double)wi;
 }
 
 __global__ void gather_kernel(Sparse sp, const float *__restrict__ f, float *__restrict__ out)
@@ -528,12 +543,19 @@ __global__ void gather_sum_kernel(Sparse sp, const float *__restrict__ f, float 
     out[0] = tot;
 }
 
-__global__ void setup_w_kernel(const float *__restrict__ vel, float *__restrict__ w, long long P, double dt,
-                               double vmax, unsigned *err)
+// w over the pitched field array from the dense velocity; pad columns get 0
+__global__ void setup_w_kernel(const float *__restrict__ vel, float *__restrict__ w, long long P, int nx, int px,
+                               double dt, double vmax, unsigned *err)
 {
     for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < P;
          p += (long long)gridDim.x * blockDim.x) {
-        const float v = vel[p];
+        const long long row = p / px;
+        const int x = (int)(p - row * px);
+        if (x >= nx) {
+            w[p] = 0.0f;
+            continue;
+        }
+        const float v = vel[row * nx + x];
         const double vd = (double)v;
         if (!(vd > 0.0) || !(vd <= vmax)) atomicOr(err, 1u);
         w[p] = (float)(dt * dt * vd * vd);
@@ -802,10 +824,11 @@ hipError_t launch_gather_sum(const Sparse &sp, const float *f, float *out, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_setup_w(const float *vel, float *w, long long P, double dt, double vmax, unsigned *err,
+hipError_t launch_setup_w(const Grid &g, const float *vel, float *w, double dt, double vmax, unsigned *err,
                           hipStream_t s)
 {
-    hipLaunchKernelGGL(setup_w_kernel, dim3(grid_for(P, 256)), dim3(256), 0, s, vel, w, P, dt, vmax, err);
+    hipLaunchKernelGGL(setup_w_kernel, dim3(grid_for(g.P, 256)), dim3(256), 0, s, vel, w, g.P, g.nx, g.px, dt,
+                       vmax, err);
     return hipGetLastError();
 }
 

@@ -22,6 +22,8 @@ class DeviceShot:
                             time_order=time_order)
         self.shape = tuple(reversed(self.pb.padded))
         self.nt, self.nrec, self.P = self.pb.nt, self.pb.nrec, self.pb.P
+        # bytes of one uncompressed checkpoint slot (two pitched field arrays)
+        self.slot_bytes = 8 * self.pb.field_elements()
         self._ws = None
 
     def set_velocity(self, vel_padded) -> None:

@@ -45,7 +45,7 @@ def test_compressed_gradient_within_codec_bound(case, tol):
     budget = int(8 * G.P * (M - 1) * 1.05)
     g, st = G.gradient(rt, budget, tol=tol, ratio_hint=1.0)
     e_gpu = rel_l2(g.cpu().numpy(), g0)
-    g_plain, _ = G.gradient(rt, 8 * G.P * (M - 1))
+    g_plain, _ = G.gradient(rt, G.slot_bytes * (M - 1))
     e_plain = rel_l2(g_plain.cpu().numpy(), g0)
     print(f"{case} tol {tol:g}: oracle compressed {e_or:.3e}  GPU compressed {e_gpu:.3e}  GPU plain {e_plain:.3e}"
           f"  ratio {st['ratio']:.1f}")

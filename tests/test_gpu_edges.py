@@ -20,7 +20,10 @@ def _gradient_case(shot, slots, tol=0.0):
     gref = S.gradient_full(fw["traj"], res)
     G, _ = gpu_side(shot)
     rt = torch.as_tensor(res.astype(np.float32), device="cuda")
-    g, st = G.gradient(rt, 8 * G.P * (slots - 1), tol=tol, ratio_hint=1.0 if tol else 0.0)
+    # uncompressed slots are two pitched field arrays; compressed ones are sized from the
+    # dense field bytes and the hint
+    budget = 8 * G.P * (slots - 1) if tol else G.slot_bytes * (slots - 1)
+    g, st = G.gradient(rt, budget, tol=tol, ratio_hint=1.0 if tol else 0.0)
     return rel_l2(g.cpu().numpy(), gref), st, res
 
 
@@ -68,3 +71,30 @@ def test_compressed_2d_gradient_and_thin_grid():
     ref = S.forward(want_last=True)
     data, state = G.forward(want_state=True)
     assert rel_l2(state[0].cpu().numpy(), ref["last"][0]) <= 1e-5
+
+
+@pytest.mark.parametrize("order,tol", [(8, 0.0), (12, 1e-4)])
+def test_workspace_contents_do_not_matter(order, tol):
+    """Field rows are pitched (pad columns beyond nx): a workspace full of NaN bytes must
+    give bit-identical data, final state and gradient to a zeroed one (76 x 72 x 70
+    padded points, rows pitched to 96)."""
+    import torch
+    shot = W.random_layers((36, 32, 30), (10.0,) * 3, 20, order, 120, np.random.default_rng(4), 15.0)
+    G, _ = gpu_side(shot)
+    rng = np.random.default_rng(1)
+    res = torch.as_tensor((rng.standard_normal((shot.nt + 1, len(shot.rec))) * 1e-3).astype(np.float32),
+                          device="cuda")
+    budget = G.slot_bytes * 10
+    out = []
+    for fill in (0, 0xFF):          # 0xFF bytes are NaN in binary32 and binary64
+        ws = G.workspace(1, budget)
+        G._ws.fill_(fill)
+        data, state = G.forward(want_state=True)
+        G._ws.fill_(fill)
+        g, st = G.gradient(res, budget, tol=tol, ratio_hint=4.0 if tol else 0.0)
+        assert torch.isfinite(g).all()
+        out.append((data.clone(), state.clone(), g.clone(), st["slots"]))
+        del ws
+    for a, b in zip(out[0][:3], out[1][:3]):
+        assert torch.equal(a, b)
+    assert out[0][3] == out[1][3]

@@ -41,7 +41,7 @@ def test_fault_body_full_grid_revolve_gradient():
     acts = SC.schedule(nt, M)
     g_or, st_or = S.gradient_actions(res, acts, M)
     G, _ = gpu_side(shot)
-    g, st = G.gradient(torch.as_tensor(res.astype(np.float32), device="cuda"), 8 * G.P * (M - 1))
+    g, st = G.gradient(torch.as_tensor(res.astype(np.float32), device="cuda"), G.slot_bytes * (M - 1))
     e = rel_l2(g.cpu().numpy(), g_or)
     print(f"full grid gradient rel-L2 {e:.2e}", st)
     assert st["slots"] == M and st["advances"] == st_or["advances"]
@@ -86,7 +86,7 @@ def test_layered_noise_full_size_forward_and_revolve():
     M = 21                  # 20 stored checkpoints plus the initial (zero) state
     acts = SC.schedule(shot.nt, M)
     g_or, st_or = S.gradient_actions(res, acts, M)
-    g, st = G.gradient(torch.as_tensor(res.astype(np.float32), device="cuda"), 8 * G.P * (M - 1))
+    g, st = G.gradient(torch.as_tensor(res.astype(np.float32), device="cuda"), G.slot_bytes * (M - 1))
     e_g = rel_l2(g.cpu().numpy(), g_or)
     print(f"168^3: data {e_d:.2e} gradient {e_g:.2e} advances {st['advances']}")
     assert e_d <= WAVEFIELD_TOL

@@ -65,7 +65,7 @@ def test_gradient_uncompressed(ndim):
     shot = W.near_anomaly_2d() if ndim == 2 else small_3d(nt=100)
     S, res, gref = _residual(shot)
     G, _ = gpu_side(shot, time_order=4)
-    g, st = G.gradient(torch.as_tensor(res.astype(np.float32), device="cuda"), 8 * G.P * shot.nt)
+    g, st = G.gradient(torch.as_tensor(res.astype(np.float32), device="cuda"), G.slot_bytes * shot.nt)
     e = rel_l2(g.cpu().numpy(), gref)
     print("OT4 gradient rel-L2", e)
     assert e <= GRAD_TOL
@@ -77,9 +77,9 @@ def test_revolve_bit_identical_and_compressed():
     S, res, gref = _residual(shot)
     G, _ = gpu_side(shot, time_order=4)
     rt = torch.as_tensor(res.astype(np.float32), device="cuda")
-    full, _ = G.gradient(rt, 8 * G.P * shot.nt)
+    full, _ = G.gradient(rt, G.slot_bytes * shot.nt)
     for M in (3, 12):
-        g, st = G.gradient(rt, 8 * G.P * (M - 1))
+        g, st = G.gradient(rt, G.slot_bytes * (M - 1))
         assert st["advances"] == SC.p_closed(shot.nt + 1, M)
         assert torch.equal(g, full), M
     M, tol = 8, 1e-5

@@ -30,7 +30,8 @@ def test_model_predicts_other_budgets(tol):
             pr = P.predict(shot.nt, G.P, slots * S, True, c["c_f"], c["c_r"], t_c=c["t_store"], t_d=c["t_d"],
                            ratio=8.0)
         else:
-            pr = P.predict(shot.nt, G.P, slots * S, False, c["c_f"], c["c_r"], t_copy=c["t_store"])
+            pr = P.predict(shot.nt, G.P, slots * S, False, c["c_f"], c["c_r"], t_copy=c["t_store"],
+                           slot_bytes=G.slot_bytes)
         phases = sm["ms_forward"] + sm["ms_adjoint"] + sm["ms_store"] + sm["ms_restore"]
         print(f"tol {tol:g} budget {slots} S: predicted {pr['ms_total']:.2f} ms, measured {phases:.2f} ms "
               f"(call {sm['ms_total']:.2f} ms), advances {pr['advances']} / {sm['advances']}")

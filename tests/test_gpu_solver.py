@@ -86,7 +86,7 @@ def test_gradient_uncompressed(ndim):
     S, res, dobs, gref = _residual(shot)
     G, _ = gpu_side(shot)
     rt = torch.as_tensor(res.astype(np.float32), device="cuda")
-    budget = 8 * G.P * shot.nt
+    budget = G.slot_bytes * shot.nt      # every state stored
     g, st = G.gradient(rt, budget)
     e = rel_l2(g.cpu().numpy(), gref)
     print("gradient rel-L2", e, st)
@@ -100,9 +100,9 @@ def test_revolve_bit_identical_to_full_storage():
     S, res, dobs, gref = _residual(shot)
     G, _ = gpu_side(shot)
     rt = torch.as_tensor(res.astype(np.float32), device="cuda")
-    full, st_full = G.gradient(rt, 8 * G.P * shot.nt)
+    full, st_full = G.gradient(rt, G.slot_bytes * shot.nt)
     for M in (2, 5, 12):
-        g, st = G.gradient(rt, 8 * G.P * (M - 1))
+        g, st = G.gradient(rt, G.slot_bytes * (M - 1))
         assert st["slots"] == M
         assert st["advances"] == SC.p_closed(shot.nt + 1, M)
         assert torch.equal(g, full), M

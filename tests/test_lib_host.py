@@ -94,6 +94,34 @@ def test_workspace_query_and_validation():
         host_problem(rec=np.array([[1e6, 20.0]])).workspace_bytes(B.OP_FORWARD)
 
 
+@pytest.mark.parametrize("n,nbl", [((31, 29), 6), ((44, 38, 41), 8), ((320, 320, 320), 40), ((48, 20, 20), 8)])
+def test_field_elements_pitch_rows_to_128_bytes_in_3d(n, nbl):
+    """3-D field arrays pad each row to a multiple of 32 elements; 2-D rows stay dense."""
+    import paper_1810_05268_amd._binding as B
+    import workloads as W
+    nd = len(n)
+    h = (10.0,) * nd
+    dt = 0.4 * B.cfl_dt(nd, h, 8, 3000.0)
+    src = np.array([[(n[0] - 1) * 5.0] + [20.0] * (nd - 1)])
+    pb = B.Problem(ndim=nd, n=n, h=h, nbl=nbl, space_order=8, nt=10, dt=dt, vmax=3000.0, vel=0x1000, src=src,
+                   wavelet=0x2000, rec=src.copy())
+    N = [x + 2 * nbl for x in n]
+    px = -(-N[0] // 32) * 32 if nd == 3 else N[0]
+    assert pb.field_elements() == px * int(np.prod(N[1:]))
+    assert pb.field_elements() >= pb.P
+    # the forward workspace holds four field arrays (u^n, u^{n-1}, w, zero) at least
+    assert pb.workspace_bytes(B.OP_FORWARD) >= 4 * 4 * pb.field_elements()
+
+
+def test_predict_plain_slots_follow_slot_bytes():
+    import paper_1810_05268_amd as P
+    N, points = 500, 10 ** 6
+    slot = 8 * 1_040_000                      # pitched rows: 4 % more than 8 points
+    budget = 30 * slot + 5
+    assert P.predict(N, points, budget, False, 1.0, 1.0, t_copy=1.0, slot_bytes=slot)["slots"] == 31
+    assert P.predict(N, points, budget, False, 1.0, 1.0, t_copy=1.0)["slots"] == 1 + budget // (8 * points)
+
+
 def test_cfl_violation_reported_before_device_work():
     """An unstable dt is rejected in host validation (no kernel is launched)."""
     import paper_1810_05268_amd._binding as B
