@@ -67,7 +67,7 @@ def test_velocity_gradient_matches_oracle():
 def test_central_finite_differences_smooth_random():
     """The 2-D smooth random medium (400^2 at 5 m, 2000 steps, order 8) with checkpoints
     compressed at 1e-5, checked against central differences of the misfit itself.
-    Directions: the normalised gradient and 8 seeded smooth unit directions (white
+    Directions: the normalised gradient and 10 seeded smooth unit directions (white
     noise filtered by a Gaussian of 10 cells).  The truncation error of a central
     difference is O(eps^2) (it is what separates the two at eps = 1e-3 ||v||), so
     eps = 3e-5 ||v||, where binary32 rounding of the misfit is the floor (about
@@ -95,7 +95,7 @@ def test_central_finite_differences_smooth_random():
         return (fp - fm) / (2 * eps)
 
     dirs = [g / gnorm]
-    for seed in range(30, 38):
+    for seed in range(30, 40):
         noise = np.random.default_rng(seed).standard_normal(tuple(vel.shape))
         dv = torch.as_tensor(gaussian_filter(noise, sigma=10.0, mode="reflect"), device="cuda")
         dirs.append(dv / torch.linalg.vector_norm(dv))
