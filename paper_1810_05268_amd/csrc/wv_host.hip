@@ -802,9 +802,9 @@ struct Fwd {
         LaunchEvents le;
         if (kt && (rc = kt->pair(0, &le))) return rc;
         if (su.g.time_order == 4) {
-            HIPCHK(launch_lapw(su.g, u, d.V, d.W, nullptr, nullptr, 0.0, s, le));
+            HIPCHK(launch_lapw(su.g, u, d.V, d.W, s, le));
             if (kt && (rc = kt->pair(0, &le))) return rc;
-            HIPCHK(launch_ot4_update(su.g, d.V, u, up, out, d.W, nullptr, nullptr, 0.0, s, le));
+            HIPCHK(launch_ot4_update(su.g, d.V, u, up, out, d.W, nullptr, nullptr, nullptr, 0.0, s, le));
         } else {
             HIPCHK(launch_fwd_step(su.g, u, up, out, d.W, s, le));
         }
@@ -1135,17 +1135,17 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
             if ((rc = ktimer.pair(1, &le))) break;
             // lam^{k-1} overwrites lam^{k+1}
             if (R.su.g.time_order == 4) {
-                // v_u = w lap u^k; v = w lap lam^k with G += (gscale/12) v v_u (the term
-                // from the m inside B); then the update with G += gscale u^k (v + (w/12) lap v)
+                // v_u = w lap u^k; v = w lap lam^k; then the update, which adds both
+                // gradient terms, gscale [u^k (v + (w/12) lap v) + v v_u / 12] (the second
+                // is the term of the m inside the OT4 operator)
                 if (uk) {
-                    HIPCHK(launch_lapw(R.su.g, uk, d.VU, d.W, nullptr, nullptr, 0.0, s, le));
+                    HIPCHK(launch_lapw(R.su.g, uk, d.VU, d.W, s, le));
                     if ((rc = ktimer.pair(1, &le))) break;
                 }
-                HIPCHK(launch_lapw(R.su.g, d.Lm[lc], d.V, d.W, uk ? d.VU : nullptr, uk ? R.G : nullptr,
-                                   gscale / 12.0, s, le));
+                HIPCHK(launch_lapw(R.su.g, d.Lm[lc], d.V, d.W, s, le));
                 if ((rc = ktimer.pair(1, &le))) break;
-                HIPCHK(launch_ot4_update(R.su.g, d.V, d.Lm[lc], d.Lm[lc ^ 1], d.Lm[lc ^ 1], d.W, uk, R.G, gscale, s,
-                                         le));
+                HIPCHK(launch_ot4_update(R.su.g, d.V, d.Lm[lc], d.Lm[lc ^ 1], d.Lm[lc ^ 1], d.W, uk, uk ? d.VU : nullptr,
+                                         R.G, gscale, s, le));
             } else {
                 HIPCHK(launch_adj_step(R.su.g, d.Lm[lc], d.Lm[lc ^ 1], d.Lm[lc ^ 1], d.W, uk, R.G, gscale, s, le));
             }

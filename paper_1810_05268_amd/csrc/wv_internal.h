@@ -62,14 +62,15 @@ hipError_t launch_fwd_step(const Grid &g, const float *u_in, const float *u_prev
 hipError_t launch_adj_step(const Grid &g, const float *lam_in, const float *lam_next, float *lam_out,
                            const float *w, const float *uk, double *G, double gscale, hipStream_t s,
                            LaunchEvents ev = {});
-// OT4, first pass: v_out = w lap f; with G, also G += gscale * v_out * x (pointwise).
-hipError_t launch_lapw(const Grid &g, const float *f, float *v_out, const float *w, const float *x, double *G,
-                       double gscale, hipStream_t s, LaunchEvents ev = {});
+// OT4, first pass: v_out = w lap f.
+hipError_t launch_lapw(const Grid &g, const float *f, float *v_out, const float *w, hipStream_t s,
+                       LaunchEvents ev = {});
 // OT4, second pass: u_out = u_in + ((1-a)(u_in - u_prev) + v + (w/12) lap v)/(1+a), v = w lap u_in
-// from the first pass; with G, G += gscale * uk * (v + (w/12) lap v).  u_out may equal u_prev.
+// from the first pass; with G, G += gscale * (uk * (v + (w/12) lap v) + v * vu / 12), vu = w lap uk.
+// u_out may equal u_prev.
 hipError_t launch_ot4_update(const Grid &g, const float *v, const float *u_in, const float *u_prev, float *u_out,
-                             const float *w, const float *uk, double *G, double gscale, hipStream_t s,
-                             LaunchEvents ev = {});
+                             const float *w, const float *uk, const float *vu, double *G, double gscale,
+                             hipStream_t s, LaunchEvents ev = {});
 // Source injection of sample q[n] (forward) at the unique source points of u_out.
 hipError_t launch_inject_src(const Grid &g, const Sparse &sp, const float *q, int n, const float *w,
                              float *u_out, hipStream_t s);

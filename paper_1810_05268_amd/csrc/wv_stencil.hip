@@ -105,20 +105,21 @@ __device__ __forceinline__ void ntstore4(float *p, float a, float b, float c, fl
 // MODE selects what is done with the Laplacian L of the marched field `fin`:
 //   kOT2:  the OT2 step above: out = c + ((1-a)(c - prev) + w L)/(1+a), c = fin's
 //          centre; GRAD adds gscale u^k (w L) to G.
-//   kLapW: out = w L (the first pass of an OT4 step); GRAD adds gscale out * xtra
-//          (xtra = w lap u^k, gscale already divided by 12: the OT4 gradient term
-//          (w^2/12)(lap lam)(lap u)).
+//   kLapW: out = w L (the first pass of an OT4 step; no gradient).
 //   kOT4:  the second pass of an OT4 step: fin is v = w lap u^n, the centre
 //          c = u^n comes pointwise from xtra, and
 //          out = c + ((1-a)(c - prev) + v + (w/12) L)/(1+a);
-//          GRAD adds gscale u^k (v + (w/12) L) to G.
+//          GRAD adds both OT4 gradient terms in one update,
+//          gscale [u^k (v + (w/12) L) + v vu / 12], where vu = w lap u^k comes pointwise
+//          from xtra2 (the second is the term of the m inside the OT4 operator).
 template <int K, bool GRAD, bool VEC, int MODE>
 __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *__restrict__ fin,
                                                  const float *prev, float *fout, const float *__restrict__ w,
                                                  const float *__restrict__ uk, const float *__restrict__ xtra,
-                                                 double *__restrict__ G, double gscale, int tiles_x, int tiles_y,
-                                                 int zchunks, int zlen)
+                                                 const float *__restrict__ xtra2, double *__restrict__ G,
+                                                 double gscale, int tiles_x, int tiles_y, int zchunks, int zlen)
 {
+    static_assert(!(GRAD && MODE == kLapW), "the w lap pass carries no gradient term");
     constexpr int TX = 32, TY = 32;
     constexpr int HX = (K + 3) / 4 * 4;          // x halo columns (>= K, multiple of 4)
     constexpr int LX = TX + 2 * HX, LY = TY + 2 * K;
@@ -216,9 +217,9 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
     auto fill = [&](Stage &S, int z) {
         if constexpr (MODE != kLapW) S.p = load4p(prev, z, x0);
         S.w = load4p(w, z, x0);
-        if constexpr (MODE == kOT4 || (MODE == kLapW && GRAD)) S.c = load4p(xtra, z, x0);
+        if constexpr (MODE == kOT4) S.c = load4p(xtra, z, x0);
         if constexpr (GRAD) {
-            if constexpr (MODE != kLapW) S.u = load4p(uk, z, x0);
+            S.u = load4p(uk, z, x0);
             const long long pg = ((long long)min(z, nz - 1) * ny + min(y, ny - 1)) * nx;   // dense
             if constexpr (VEC) {
                 // two 16-byte loads per lane, normally cached: the line a lane pair shares
@@ -262,6 +263,10 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
 #pragma unroll
             for (int i = 0; i < 4; ++i) gold[i] = S.g[i];
         }
+        // OT4 adjoint: w lap u^k of this plane, loaded here rather than staged (a staged
+        // copy would not fit the registers); the Laplacian below covers its latency
+        float4 vu4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        if constexpr (MODE == kOT4 && GRAD) vu4 = load4p(xtra2, z, x0);
         fill(N, z + AHEAD);
         const int cur = (z - z0) & 1;
         // x neighbours: NXV aligned float4 around the lane's four points
@@ -325,6 +330,7 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
         const float win[4] = {S.w.x, S.w.y, S.w.z, S.w.w};
         const float uin[4] = {S.u.x, S.u.y, S.u.z, S.u.w};
         const float cin[4] = {S.c.x, S.c.y, S.c.z, S.c.w};
+        const float c2in[4] = {vu4.x, vu4.y, vu4.z, vu4.w};
         float on[4], wl[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -354,9 +360,13 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
             if constexpr (GRAD) {
                 double gn[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    gn[i] = MODE == kLapW ? gold[i] + gscale * (double)on[i] * (double)cin[i]
-                                          : gold[i] + gscale * (double)uin[i] * (double)wl[i];
+                for (int i = 0; i < 4; ++i) {
+                    if constexpr (MODE == kOT4)   // v vu / 12 rounded once in binary32
+                        gn[i] = gold[i] + gscale * ((double)uin[i] * (double)wl[i] +
+                                                    (double)(q[i][K] * c2in[i] * (1.0f / 12.0f)));
+                    else
+                        gn[i] = gold[i] + gscale * (double)uin[i] * (double)wl[i];
+                }
                 if constexpr (VEC) {
                     *reinterpret_cast<double2 *>(&G[p0g]) = make_double2(gn[0], gn[1]);
                     *reinterpret_cast<double2 *>(&G[p0g + 2]) = make_double2(gn[2], gn[3]);
@@ -430,9 +440,10 @@ template <int K, bool GRAD, int MODE>
 __global__ __launch_bounds__(256) void stencil2d(Grid g, const float *__restrict__ fin, const float *prev,
                                                  float *fout, const float *__restrict__ w,
                                                  const float *__restrict__ uk, const float *__restrict__ xtra,
-                                                 double *__restrict__ G, double gscale, int tiles_x, int zchunks,
-                                                 int zlen)
+                                                 const float *__restrict__ xtra2, double *__restrict__ G,
+                                                 double gscale, int tiles_x, int zchunks, int zlen)
 {
+    static_assert(!(GRAD && MODE == kLapW), "the w lap pass carries no gradient term");
     constexpr int TX = 256;
     __shared__ float row[TX + 2 * K];
     const int nwg = tiles_x * zchunks;
@@ -480,10 +491,7 @@ __global__ __launch_bounds__(256) void stencil2d(Grid g, const float *__restrict
             const long long p = (long long)z * nx + x;
             const float wp = __builtin_nontemporal_load(&w[p]);
             if constexpr (MODE == kLapW) {
-                const float v = wp * lap;
-                __builtin_nontemporal_store(v, &fout[p]);
-                if constexpr (GRAD)
-                    G[p] += gscale * (double)v * (double)__builtin_nontemporal_load(&xtra[p]);
+                __builtin_nontemporal_store(wp * lap, &fout[p]);
             } else {
                 const float ctr = MODE == kOT4 ? __builtin_nontemporal_load(&xtra[p]) : c;
                 const float wl = MODE == kOT4 ? fmaf(wp * (1.0f / 12.0f), lap, c) : wp * lap;
@@ -491,7 +499,11 @@ __global__ __launch_bounds__(256) void stencil2d(Grid g, const float *__restrict
                 const float d = ctr - __builtin_nontemporal_load(&prev[p]);
                 const float dn = (a == 0.0f) ? d + wl : ((1.0f - a) * d + wl) / (1.0f + a);
                 __builtin_nontemporal_store(ctr + dn, &fout[p]);
-                if constexpr (GRAD) G[p] += gscale * (double)__builtin_nontemporal_load(&uk[p]) * (double)wl;
+                if constexpr (GRAD && MODE == kOT4)
+                    G[p] += gscale * ((double)__builtin_nontemporal_load(&uk[p]) * (double)wl +
+                                      (double)c * (double)__builtin_nontemporal_load(&xtra2[p]) * (1.0 / 12.0));
+                else if constexpr (GRAD)
+                    G[p] += gscale * (double)__builtin_nontemporal_load(&uk[p]) * (double)wl;
             }
         }
         __syncthreads();
@@ -710,7 +722,8 @@ void launch_timed(Kern kern, dim3 grid, hipStream_t s, LaunchEvents ev, Args... 
 
 template <int K, bool GRAD, bool VEC, int MODE>
 hipError_t launch3d(const Grid &g, const float *fin, const float *prev, float *fout, const float *w,
-                    const float *uk, const float *xtra, double *G, double gscale, hipStream_t s, LaunchEvents ev)
+                    const float *uk, const float *xtra, const float *xtra2, double *G, double gscale, hipStream_t s,
+                    LaunchEvents ev)
 {
     auto kern = stencil3d<K, GRAD, VEC, MODE>;
     const int tiles_x = (g.nx + 31) / 32, tiles_y = (g.ny + 31) / 32;
@@ -719,41 +732,44 @@ hipError_t launch3d(const Grid &g, const float *fin, const float *prev, float *f
     int zchunks, zlen;
     choose_chunks((long long)tiles_x * tiles_y, g.nz, K, resident_workgroups(kern), zchunks, zlen);
     const int nwg = tiles_x * tiles_y * zchunks;
-    launch_timed(kern, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, xtra, G, gscale, tiles_x, tiles_y, zchunks,
-                 zlen);
+    launch_timed(kern, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, tiles_x, tiles_y,
+                 zchunks, zlen);
     return hipGetLastError();
 }
 
 template <int K, bool GRAD, int MODE>
 hipError_t launch_k(const Grid &g, const float *fin, const float *prev, float *fout, const float *w,
-                    const float *uk, const float *xtra, double *G, double gscale, hipStream_t s, LaunchEvents ev)
+                    const float *uk, const float *xtra, const float *xtra2, double *G, double gscale, hipStream_t s,
+                    LaunchEvents ev)
 {
     if (g.ndim == 3) {
-        if (g.nx % 4 == 0) return launch3d<K, GRAD, true, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
-        return launch3d<K, GRAD, false, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
+        if (g.nx % 4 == 0)
+            return launch3d<K, GRAD, true, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
+        return launch3d<K, GRAD, false, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
     }
     const int tiles_x = (g.nx + 255) / 256;
     int zchunks, zlen;
     choose_chunks(tiles_x, g.nz, K, 512, zchunks, zlen);
     const int nwg = tiles_x * zchunks;
-    launch_timed(stencil2d<K, GRAD, MODE>, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, xtra, G, gscale, tiles_x,
-                 zchunks, zlen);
+    launch_timed(stencil2d<K, GRAD, MODE>, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale,
+                 tiles_x, zchunks, zlen);
     return hipGetLastError();
 }
 
 template <bool GRAD, int MODE>
 hipError_t launch_any(const Grid &g, const float *fin, const float *prev, float *fout, const float *w,
-                      const float *uk, const float *xtra, double *G, double gscale, hipStream_t s, LaunchEvents ev)
+                      const float *uk, const float *xtra, const float *xtra2, double *G, double gscale, hipStream_t s,
+                      LaunchEvents ev)
 {
     switch (g.K) {
-    case 1: return launch_k<1, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
-    case 2: return launch_k<2, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
-    case 3: return launch_k<3, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
-    case 4: return launch_k<4, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
-    case 5: return launch_k<5, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
-    case 6: return launch_k<6, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
-    case 7: return launch_k<7, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
-    case 8: return launch_k<8, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, G, gscale, s, ev);
+    case 1: return launch_k<1, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
+    case 2: return launch_k<2, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
+    case 3: return launch_k<3, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
+    case 4: return launch_k<4, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
+    case 5: return launch_k<5, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
+    case 6: return launch_k<6, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
+    case 7: return launch_k<7, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
+    case 8: return launch_k<8, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
     default: return hipErrorInvalidValue;
     }
 }
@@ -763,30 +779,28 @@ hipError_t launch_any(const Grid &g, const float *fin, const float *prev, float 
 hipError_t launch_fwd_step(const Grid &g, const float *u_in, const float *u_prev, float *u_out, const float *w,
                            hipStream_t s, LaunchEvents ev)
 {
-    return launch_any<false, kOT2>(g, u_in, u_prev, u_out, w, nullptr, nullptr, nullptr, 0.0, s, ev);
+    return launch_any<false, kOT2>(g, u_in, u_prev, u_out, w, nullptr, nullptr, nullptr, nullptr, 0.0, s, ev);
 }
 
 hipError_t launch_adj_step(const Grid &g, const float *lam_in, const float *lam_next, float *lam_out,
                            const float *w, const float *uk, double *G, double gscale, hipStream_t s,
                            LaunchEvents ev)
 {
-    if (G) return launch_any<true, kOT2>(g, lam_in, lam_next, lam_out, w, uk, nullptr, G, gscale, s, ev);
-    return launch_any<false, kOT2>(g, lam_in, lam_next, lam_out, w, nullptr, nullptr, nullptr, 0.0, s, ev);
+    if (G) return launch_any<true, kOT2>(g, lam_in, lam_next, lam_out, w, uk, nullptr, nullptr, G, gscale, s, ev);
+    return launch_any<false, kOT2>(g, lam_in, lam_next, lam_out, w, nullptr, nullptr, nullptr, nullptr, 0.0, s, ev);
 }
 
-hipError_t launch_lapw(const Grid &g, const float *f, float *v_out, const float *w, const float *x, double *G,
-                       double gscale, hipStream_t s, LaunchEvents ev)
+hipError_t launch_lapw(const Grid &g, const float *f, float *v_out, const float *w, hipStream_t s, LaunchEvents ev)
 {
-    if (G) return launch_any<true, kLapW>(g, f, nullptr, v_out, w, nullptr, x, G, gscale, s, ev);
-    return launch_any<false, kLapW>(g, f, nullptr, v_out, w, nullptr, nullptr, nullptr, 0.0, s, ev);
+    return launch_any<false, kLapW>(g, f, nullptr, v_out, w, nullptr, nullptr, nullptr, nullptr, 0.0, s, ev);
 }
 
 hipError_t launch_ot4_update(const Grid &g, const float *v, const float *u_in, const float *u_prev, float *u_out,
-                             const float *w, const float *uk, double *G, double gscale, hipStream_t s,
+                             const float *w, const float *uk, const float *vu, double *G, double gscale, hipStream_t s,
                              LaunchEvents ev)
 {
-    if (G) return launch_any<true, kOT4>(g, v, u_prev, u_out, w, uk, u_in, G, gscale, s, ev);
-    return launch_any<false, kOT4>(g, v, u_prev, u_out, w, nullptr, u_in, nullptr, 0.0, s, ev);
+    if (G) return launch_any<true, kOT4>(g, v, u_prev, u_out, w, uk, u_in, vu, G, gscale, s, ev);
+    return launch_any<false, kOT4>(g, v, u_prev, u_out, w, nullptr, u_in, nullptr, nullptr, 0.0, s, ev);
 }
 
 hipError_t launch_inject_src(const Grid &g, const Sparse &sp, const float *q, int n, const float *w,
