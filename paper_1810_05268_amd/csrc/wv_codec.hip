@@ -722,7 +722,11 @@ __global__ __launch_bounds__(256) void decode_kernel(DecArgs A)
                     const float4 b = *reinterpret_cast<const float4 *>(A.sub + r0 + 4 * bx);
                     o = make_float4(b.x - o.x, b.y - o.y, b.z - o.z, b.w - o.w);
                 }
-                *reinterpret_cast<float4 *>(row + 4 * bx) = o;
+                // streamed out: the next kernel reads it once, so it need not stay in the
+                // caches (and its write-back is paid here, not during that kernel)
+                typedef float f4v __attribute__((ext_vector_type(4)));
+                const f4v t = {o.x, o.y, o.z, o.w};
+                __builtin_nontemporal_store(t, reinterpret_cast<f4v *>(row + 4 * bx));
             } else {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
