@@ -49,6 +49,14 @@ COUNTERS = os.path.join(ROOT, "profiles", "stencil3d_fault_body_3d_counters.txt"
 STENCIL_SRC = os.path.join(ROOT, "paper_1810_05268_amd", "csrc", "wv_stencil.hip")
 
 
+# wv_stats.timing bits: 1 = HIP events around every schedule action (per-phase device
+# times, for the run-time model), 2 = events recorded by every stencil dispatch (the
+# roofline).  The timed steps use launch events only; per-action events add dependent
+# packets between kernels and cost about 4 % of the wall time.
+TIMING_ACTIONS = 1
+TIMING_LAUNCHES = 2
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -83,23 +91,25 @@ def ot4_block(shot, budget, tol, steps):
     gp = torch.empty(G.shape, dtype=torch.float64, device="cuda")
     gc = torch.empty(G.shape, dtype=torch.float64, device="cuda")
 
-    def run(tol_, hint, out, n):
+    def run(tol_, hint, out, n, timing):
         walls, st = [], None
         for _ in range(n):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            _, _, st = G.misfit_gradient(d_obs, budget, tol_, hint, timing=3, out=out)
+            _, _, st = G.misfit_gradient(d_obs, budget, tol_, hint, timing=timing, out=out)
             torch.cuda.synchronize()
             walls.append(time.perf_counter() - t0)
         return walls, st
     log("OT4 plain ...")
-    wp, sp = run(0.0, 0.0, gp, steps)
+    wp, sp = run(0.0, 0.0, gp, steps, TIMING_LAUNCHES)
+    _, sp_ph = run(0.0, 0.0, gp, 1, TIMING_ACTIONS)
     log("OT4 compressed ...")
-    _, s0 = run(tol, 0.0, gc, 1)
+    _, s0 = run(tol, 0.0, gc, 1, 0)
     h = plan_hint(s0, G.P, shot.nt, budget)
-    wc, sc = run(tol, h, gc, steps)
+    wc, sc = run(tol, h, gc, steps, TIMING_LAUNCHES)
+    _, sc_ph = run(tol, h, gc, 1, TIMING_ACTIONS)
     err = float(torch.linalg.vector_norm(gc - gp) / torch.linalg.vector_norm(gp))
-    cp, cc = P.costs_from_stats(sp), P.costs_from_stats(sc)
+    cp, cc = P.costs_from_stats(sp_ph), P.costs_from_stats(sc_ph)
     pp = P.predict(shot.nt, G.P, budget, False, cp["c_f"], cp["c_r"], t_copy=cp["t_store"], slot_bytes=G.slot_bytes)
     pc = P.predict(shot.nt, G.P, budget, True, cc["c_f"], cc["c_r"], t_c=cc["t_store"], t_d=cc["t_d"], ratio=h)
     out = {"dt": dt, "shot_gradient_s": {"plain": statistics.mean(wp), "compressed": statistics.mean(wc)},
@@ -107,7 +117,7 @@ def ot4_block(shot, budget, tol, steps):
            "schedule": {"plain": {k: sp[k] for k in ("slots", "advances", "stores")},
                         "compressed": {k: sc[k] for k in ("slots", "advances", "stores", "decodes", "ratio")}},
            "step_ms": {"forward": sp["ms_fwd_kernel"] / sp["advances"], "adjoint": sp["ms_adj_kernel"] / sp["reverses"]},
-           "model": {"plain": {"predicted_ms": pp["ms_total"], "measured_ms": sum(sp[k] for k in (
+           "model": {"plain": {"predicted_ms": pp["ms_total"], "measured_ms": sum(sp_ph[k] for k in (
                          "ms_forward", "ms_adjoint", "ms_store", "ms_restore"))},
                      "full_storage_ms": pp["ms_full_storage"]}}
     log(f"OT4: plain {out['shot_gradient_s']['plain']:.3f} s, compressed {out['shot_gradient_s']['compressed']:.3f} s "
@@ -354,6 +364,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4, help="codec tolerance of the headline run")
     ap.add_argument("--sweep", default="1e-3,1e-6", help="extra tolerances timed once each ('' = none)")
     ap.add_argument("--budget", type=float, default=16e9, help="checkpoint memory, bytes")
+    ap.add_argument("--budget-sweep", default="", help="other checkpoint budgets (bytes, comma separated) timed "
+                                                       "plain and compressed once each ('' = none)")
     ap.add_argument("--quick", action="store_true", help="small grid for a fast functional run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=200, help="0 = skip the serving stream")
@@ -394,12 +406,12 @@ def main():
     g_plain = torch.empty(G.shape, dtype=torch.float64, device="cuda")
     g_comp = torch.empty(G.shape, dtype=torch.float64, device="cuda")
 
-    def timed(tol, hint, out, n):
+    def timed(tol, hint, out, n, timing=TIMING_LAUNCHES):
         walls, stats, phi = [], [], None
         for _ in range(n):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            phi, _, st = G.misfit_gradient(d_obs, budget, tol, hint, timing=3, out=out)
+            phi, _, st = G.misfit_gradient(d_obs, budget, tol, hint, timing=timing, out=out)
             torch.cuda.synchronize()
             walls.append(time.perf_counter() - t0)
             stats.append(st)
@@ -409,6 +421,7 @@ def main():
     log("plain revolve ...")
     timed(0.0, 0.0, g_plain, args.warmup)
     w_plain, st_plain, phi_plain = timed(0.0, 0.0, g_plain, args.steps)
+    _, st_plain_ph, _ = timed(0.0, 0.0, g_plain, 1, TIMING_ACTIONS)   # per-phase times (untimed call)
     log(f"plain: {statistics.mean(w_plain):.3f} s  M={st_plain[0]['slots']} advances={st_plain[0]['advances']}")
 
     # compressed: the first (warm-up) call plans with the ratio of the final state; later
@@ -418,20 +431,22 @@ def main():
     _, st0, _ = timed(args.tol, 0.0, g_comp, max(1, args.warmup))
     hint = plan_hint(st0[-1], Pn, shot.nt, budget)
     w_comp, st_comp, phi_comp = timed(args.tol, hint, g_comp, args.steps)
+    _, st_comp_ph, _ = timed(args.tol, hint, g_comp, 1, TIMING_ACTIONS)
     err = float(torch.linalg.vector_norm(g_comp - g_plain) / torch.linalg.vector_norm(g_plain))
     log(f"compressed tol {args.tol}: {statistics.mean(w_comp):.3f} s  M={st_comp[0]['slots']} "
         f"ratio={st_comp[0]['ratio']:.1f} advances={st_comp[0]['advances']} grad err vs plain {err:.3e}")
 
     sweep, sweep_stats = [], []
     for tol in [float(t) for t in args.sweep.split(",") if t.strip()]:
-        _, sp0, _ = timed(tol, 0.0, g_comp, 1)
+        _, sp0, _ = timed(tol, 0.0, g_comp, 1, 0)
         h = plan_hint(sp0[-1], Pn, shot.nt, budget)
         ws_, ss_, _ = timed(tol, h, g_comp, 1)
+        _, sph_, _ = timed(tol, h, g_comp, 1, TIMING_ACTIONS)
         e = float(torch.linalg.vector_norm(g_comp - g_plain) / torch.linalg.vector_norm(g_plain))
         sweep.append({"tol": tol, "shot_s": ws_[0], "slots": ss_[0]["slots"], "ratio": ss_[0]["ratio"],
                       "advances": ss_[0]["advances"], "grad_rel_err_vs_plain": e,
                       "speedup_vs_plain": statistics.mean(w_plain) / ws_[0]})
-        sweep_stats.append((tol, h, ss_[0]))
+        sweep_stats.append((tol, h, sph_[0]))
         log(f"sweep tol {tol}: {ws_[0]:.3f} s ratio {ss_[0]['ratio']:.1f} err {e:.3e}")
 
     # per-phase device times over the timed compressed steps (HIP events on the call's stream)
@@ -457,11 +472,11 @@ def main():
                              "traffic": tr["forward"] if tr else None},
             "adjoint_step": {"avg_ms": adj_ms, "GBs": round(adj_gbs, 1), "frac": round(adj_gbs / HBM_PEAK_GBS, 4),
                              "traffic": tr["adjoint"] if tr else None}}
-    st = st_comp[0]
+    st = st_comp_ph[0]
     ms_per_store = st["ms_store"] / st["stores"] if st["stores"] else None
     ms_per_decode = st["ms_restore"] / st["decodes"] if st["decodes"] else None
 
-    model = performance_model(shot.nt, Pn, G.slot_bytes, budget, st_plain[0], st_comp[0], hint, sweep_stats)
+    model = performance_model(shot.nt, Pn, G.slot_bytes, budget, st_plain_ph[0], st_comp_ph[0], hint, sweep_stats)
     # compressibility over time at the headline tolerance (untimed)
     stride = max(1, shot.nt // 10)
     cb = G.compressibility(args.tol, stride)
@@ -469,6 +484,29 @@ def main():
                        "ratio": [4.0 * Pn / b for b in cb]}
     log("compressibility (ratio of u^n): " + ", ".join(f"{n}:{r:.0f}" for n, r in
                                                          zip(compressibility["steps"], compressibility["ratio"])))
+
+    # optional: plain against compressed at other checkpoint budgets (each run once; the
+    # compressed call plans from the profile a first compressed call measured)
+    budget_sweep = []
+    for bb in [int(float(x)) for x in args.budget_sweep.split(",") if x.strip()]:
+        def once(tol, hint, out):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, st_ = G.misfit_gradient(d_obs, bb, tol, hint, out=out)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0, st_
+        wp_, sp_ = once(0.0, 0.0, g_plain)
+        _, s0_ = once(args.tol, 0.0, g_comp)
+        h_ = plan_hint(s0_, Pn, shot.nt, bb)
+        wc_, sc_ = once(args.tol, h_, g_comp)
+        e_ = float(torch.linalg.vector_norm(g_comp - g_plain) / torch.linalg.vector_norm(g_plain))
+        budget_sweep.append({"budget": bb, "plain_s": wp_, "plain_slots": sp_["slots"],
+                             "plain_advances": sp_["advances"], "compressed_s": wc_,
+                             "compressed_slots": sc_["slots"], "compressed_advances": sc_["advances"],
+                             "retries": sc_["retries"], "speedup_vs_plain": wp_ / wc_,
+                             "grad_rel_err_vs_plain": e_})
+        log(f"budget {bb:.3g} B: plain {wp_:.3f} s (M={sp_['slots']}, {sp_['advances']} advances), compressed "
+            f"{wc_:.3f} s (M={sc_['slots']}, {sc_['advances']} advances), {wp_ / wc_:.2f}x, err {e_:.2e}")
 
     ms_step = 1e3 * statistics.mean(w_comp)
     value = Pn * 2 * shot.nt / (ms_step * 1e-3) / 1e9
@@ -490,7 +528,9 @@ def main():
                                                          "ratio", "ratio_planned", "peak_bytes", "retries")},
                      "plain": {k: st_plain[0][k] for k in ("slots", "advances", "stores", "restores")}},
         "phase_ms": {"compressed": {k: st[k] for k in ("ms_forward", "ms_adjoint", "ms_store", "ms_restore")},
-                     "plain": {k: st_plain[0][k] for k in ("ms_forward", "ms_adjoint", "ms_store", "ms_restore")}},
+                     "plain": {k: st_plain_ph[0][k] for k in ("ms_forward", "ms_adjoint", "ms_store", "ms_restore")},
+                     "note": "one extra call each with per-action events (they cost about 4 % of wall time, "
+                             "so the timed steps record only the stencil launches)"},
         "codec": {"ms_per_store": ms_per_store, "ms_per_field_decode": ms_per_decode,
                   "fields_per_store": (st["bytes_stored"] * st["ratio"]) / (4.0 * Pn * st["stores"])
                   if st["stores"] else None},
@@ -500,6 +540,8 @@ def main():
         "compressibility": compressibility,
         "roofline": roof,
     }
+    if budget_sweep:
+        out["budget_sweep"] = budget_sweep
     if not args.no_ot4:
         del g_plain, g_comp
         torch.cuda.synchronize()

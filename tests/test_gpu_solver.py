@@ -79,6 +79,28 @@ def _residual(shot):
     return S, res, dobs, g
 
 
+def test_two_layer_full_size_full_storage_and_revolve_10():
+    """The 2-D two-layer model at its full size (101^2 + 20-cell layer, 500 steps, order 4):
+    gradient with full storage and with uncompressed Revolve on 10 checkpoints (M = 11 with
+    the initial zero state), against the oracle's full-storage gradient.  The two GPU
+    gradients are bit-identical (recomputation is deterministic and the reverse sweep sums
+    in the same order), and the recomputation count is the binomial closed form."""
+    import torch
+    shot = W.two_layer_2d()
+    S, res, _, gref = _residual(shot)
+    G, _ = gpu_side(shot)
+    rt = torch.as_tensor(res.astype(np.float32), device="cuda")
+    full, st_full = G.gradient(rt, G.slot_bytes * shot.nt)
+    M = 11
+    g, st = G.gradient(rt, G.slot_bytes * (M - 1))
+    e = rel_l2(full.cpu().numpy(), gref)
+    print(f"two-layer full size: gradient rel-L2 {e:.2e}, Revolve advances {st['advances']}")
+    assert st_full["advances"] == shot.nt
+    assert st["slots"] == M and st["advances"] == SC.p_closed(shot.nt + 1, M)
+    assert torch.equal(g, full)
+    assert e <= GRAD_TOL
+
+
 @pytest.mark.parametrize("ndim", [2, 3])
 def test_gradient_uncompressed(ndim):
     import torch
