@@ -92,3 +92,37 @@ def test_layered_noise_full_size_forward_and_revolve():
     assert e_d <= WAVEFIELD_TOL
     assert st["advances"] == st_or["advances"] == SC.p_closed(shot.nt + 1, M)
     assert e_g <= GRAD_TOL
+
+
+def test_fault_body_all_3000_steps_properties():
+    """The large shot with all 3000 steps, as the bench runs it, checked by properties that
+    hold at any size (the FP64 oracle cannot run it in seconds): plain Revolve gives the
+    bit-identical gradient with 31 and 121 slots (recomputation is deterministic and the
+    reverse sweep sums in one order) after exactly the binomial number of forward steps; the
+    misfit does not depend on the checkpoint strategy; and the compressed gradient at tol
+    1e-4 (every state stored) stays within 10 tol of the plain one in rel-L2."""
+    import torch
+    shot = W.fault_body_3d()
+    Gt, _ = gpu_side(shot, "true")
+    d_obs = Gt.forward()
+    del Gt
+    torch.cuda.empty_cache()
+    G, _ = gpu_side(shot)
+    g31 = torch.empty(G.shape, dtype=torch.float64, device="cuda")
+    g121 = torch.empty_like(g31)
+    gc = torch.empty_like(g31)
+    phi31, _, st31 = G.misfit_gradient(d_obs, G.slot_bytes * 30, out=g31)
+    phi121, _, st121 = G.misfit_gradient(d_obs, G.slot_bytes * 120, out=g121)
+    G._ws = None
+    torch.cuda.empty_cache()
+    phic, _, stc = G.misfit_gradient(d_obs, int(16e9), 1e-4, out=gc)
+    e = float(torch.linalg.vector_norm(gc - g31) / torch.linalg.vector_norm(g31))
+    print(f"3000 steps: advances {st31['advances']} / {st121['advances']}, compressed slots {stc['slots']} "
+          f"ratio {stc['ratio']:.1f}, rel-L2 to plain {e:.2e}")
+    assert st31["slots"] == 31 and st121["slots"] == 121
+    assert st31["advances"] == SC.p_closed(shot.nt + 1, 31)
+    assert st121["advances"] == SC.p_closed(shot.nt + 1, 121)
+    assert torch.equal(g31, g121)
+    assert phi31 == phi121 == phic
+    assert stc["retries"] == 0 and stc["peak_bytes"] <= 16e9
+    assert e <= 10 * 1e-4
