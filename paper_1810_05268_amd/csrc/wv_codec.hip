@@ -419,6 +419,52 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
     const unsigned excl_bits = s_scan[tid] - nbits;
     const unsigned total_bits = s_scan[255];
     const uint32_t chunk_words = (total_bits + 63u) / 64u;
+    // successors may sum this chunk's size as soon as it is known
+    if (tid == 0 && c > 0)
+        __hip_atomic_store(&A.flags[c], make_flag(kFlagAgg, A.epoch, chunk_words), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+
+    auto emit = [&](auto &sink) {
+        Emitter em{(long long)excl_bits, 0ull};
+        em.put(coded ? 1ull : 0ull, 1, sink);
+        if (coded) em.put((unsigned long long)(emax + 127), 8, sink);
+        {
+            int n = 0;
+#pragma unroll 1
+            for (int k = 31; k >= kmin_w; --k) {
+                if (coded && k >= kmin) {
+                    const unsigned long long mk = (unsigned long long)m_hi[k] << 32 | m_lo[k];
+                    if (n > 0) em.put(mk & low_mask(n), n, sink);
+                    if (n < S) {
+                        unsigned long long r = mk >> n;
+                        while (r != 0ull) {
+                            const int z = __ffsll((long long)r) - 1;
+                            em.put(1ull, 1, sink);
+                            em.put(1ull << z, z + 1, sink);
+                            n += z + 1;
+                            r = (z + 1 < 64) ? (r >> (z + 1)) : 0ull;
+                        }
+                        if (n < S) em.put(0ull, 1, sink);
+                    }
+                }
+            }
+        }
+        em.flush(sink);
+    };
+
+    // A chunk that fits the LDS buffer is assembled there first: its bit positions are
+    // chunk-local, so the emission needs no global offset and runs while the
+    // predecessors finish (the look-back below then rarely waits).
+    const bool in_lds = chunk_words <= (uint32_t)kLdsWords;
+    if (in_lds) {
+        for (uint32_t i = tid; i < chunk_words; i += 256) s_bits[i] = 0ull;
+        __syncthreads();
+        if (valid) {
+            auto sink = [&](long long w, unsigned long long bits) { atomicOr(&s_bits[w], bits); };
+            emit(sink);
+        }
+    }
+    __syncthreads();
 
     // decoupled look-back: one wave reads 256 predecessor status words per round
     // (4 per lane, nearest first) and stops at the nearest inclusive prefix
@@ -426,9 +472,6 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
         const uint32_t ep = A.epoch & 0x3FFFFFFFu;
         unsigned long long excl = 0;
         if (c > 0) {
-            if (tid == 0)
-                __hip_atomic_store(&A.flags[c], make_flag(kFlagAgg, A.epoch, chunk_words), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
             long long top = c - 1;
             unsigned spins = 0;
             while (true) {
@@ -485,43 +528,7 @@ __global__ __launch_bounds__(256) void encode_kernel(EncArgs A)
     if (tid == 0 && !fits) atomicOr(A.err, 4u);
     unsigned long long *data = (unsigned long long *)(hdr + A.prefix_bytes) + excl;
 
-    auto emit = [&](auto &sink) {
-        Emitter em{(long long)excl_bits, 0ull};
-        em.put(coded ? 1ull : 0ull, 1, sink);
-        if (coded) em.put((unsigned long long)(emax + 127), 8, sink);
-        {
-            int n = 0;
-#pragma unroll 1
-            for (int k = 31; k >= kmin_w; --k) {
-                if (coded && k >= kmin) {
-                    const unsigned long long mk = (unsigned long long)m_hi[k] << 32 | m_lo[k];
-                    if (n > 0) em.put(mk & low_mask(n), n, sink);
-                    if (n < S) {
-                        unsigned long long r = mk >> n;
-                        while (r != 0ull) {
-                            const int z = __ffsll((long long)r) - 1;
-                            em.put(1ull, 1, sink);
-                            em.put(1ull << z, z + 1, sink);
-                            n += z + 1;
-                            r = (z + 1 < 64) ? (r >> (z + 1)) : 0ull;
-                        }
-                        if (n < S) em.put(0ull, 1, sink);
-                    }
-                }
-            }
-        }
-        em.flush(sink);
-    };
-
-    if (fits && chunk_words <= (uint32_t)kLdsWords) {
-        // assemble the chunk in LDS, then store it with coalesced writes
-        for (uint32_t i = tid; i < chunk_words; i += 256) s_bits[i] = 0ull;
-        __syncthreads();
-        if (valid) {
-            auto sink = [&](long long w, unsigned long long bits) { atomicOr(&s_bits[w], bits); };
-            emit(sink);
-        }
-        __syncthreads();
+    if (fits && in_lds) {
         for (uint32_t i = tid; i < chunk_words; i += 256) data[i] = s_bits[i];
     } else if (fits) {
         for (uint32_t i = tid; i < chunk_words; i += 256) data[i] = 0ull;
