@@ -238,7 +238,7 @@ DryRun dry_run(const std::vector<int32_t> &acts, int M, bool compressed)
     DryRun r;
     const std::vector<char> need2 = second_level_needed(acts, M);
     std::vector<char> slot2((size_t)M + 2, 0);
-    int hot_slot = -1, hot_k = -1, pend_slot = -1;
+    int hot_slot = -1, hot_k = -1;
     bool hot_db = false, pending = false;
     for (size_t i = 0; i < acts.size() / 3; ++i) {
         const int op = acts[3 * i], a = acts[3 * i + 1], b = acts[3 * i + 2];
@@ -269,7 +269,6 @@ DryRun dry_run(const std::vector<int32_t> &acts, int M, bool compressed)
                     hot_db = false;
                 }
                 pending = slot2[b] != 0;
-                pend_slot = b;
             }
             ++r.restores;
             break;
@@ -280,7 +279,6 @@ DryRun dry_run(const std::vector<int32_t> &acts, int M, bool compressed)
             break;
         }
     }
-    (void)pend_slot;
     return r;
 }
 
@@ -584,9 +582,7 @@ Layout plan_layout(const wv_model *m, const wv_geom *geo, const Setup &su, int o
         L.res = take(data_bytes);
         L.dsim = take(data_bytes);
         L.partials = take(kParts * 8);
-        const int dims[3] = {su.g.nx, su.g.ny, su.g.nz};
         const int cdims[3] = {su.g.nx, su.ndim == 3 ? su.g.ny : su.g.nz, su.ndim == 3 ? su.g.nz : 1};
-        (void)dims;
         const CodecDims cd = codec_dims(su.ndim, cdims, su.g.px);
         L.nchunks_max = cd.nchunks;
         L.flags = take((size_t)cd.nchunks * 8);
