@@ -27,9 +27,10 @@ def test_forward_2d_two_layer_full_size():
 
 
 @pytest.mark.parametrize("order", [2, 4, 8, 12, 16])
-@pytest.mark.parametrize("nxi", [44, 45])
+@pytest.mark.parametrize("nxi", [44, 45, 48])
 def test_forward_3d_orders_ragged(order, nxi):
-    """nxi = 44: padded x extent a multiple of 4 (vector path); 45: scalar path."""
+    """nxi = 44: padded x extent 60, a multiple of 4 (vector path), rows pitched to 64;
+    45: 61, scalar path; 48: 64, rows already a multiple of 32 (no pad columns)."""
     shot = small_3d(n=(nxi, 38, 41), order=order, nt=80)
     S, _ = oracle_side(shot)
     G, _ = gpu_side(shot)
