@@ -156,8 +156,9 @@ size_t wv_workspace_bytes(const wv_model *model, const wv_geom *geom, int op, si
  * uncompressed checkpoints with every row of a 3-D grid padded to a multiple of 32
  * elements (128 bytes), so that rows start on cache lines; the caller's arrays stay
  * dense.  An uncompressed checkpoint slot takes 8 times this many bytes; compressed
- * slots and all ratios refer to the dense 4 P bytes of a field.  Returns 0 on an
- * invalid model.  Host only. */
+ * slots and all ratios refer to the dense 4 P bytes of a field.  A field array must
+ * stay below 2^31 elements (point indices are 32-bit): every call returns WV_EINVAL for
+ * a larger grid.  Returns 0 on an invalid model.  Host only. */
 long long wv_field_elements(const wv_model *model);
 
 /* ------------------------------------------------------------------ solver */

@@ -113,6 +113,28 @@ def test_field_elements_pitch_rows_to_128_bytes_in_3d(n, nbl):
     assert pb.workspace_bytes(B.OP_FORWARD) >= 4 * 4 * pb.field_elements()
 
 
+def test_largest_grid_is_validated_on_the_host():
+    """Field arrays are indexed with 32-bit point indices (the sparse tables): a grid whose
+    pitched field array reaches 2^31 elements is rejected before any device work, and one
+    just below is accepted (only host queries are made here)."""
+    import paper_1810_05268_amd._binding as B
+    h = (10.0, 10.0, 10.0)
+    dt = 0.4 * B.cfl_dt(3, h, 4, 3000.0)
+    src = np.array([[50.0, 50.0, 20.0]])
+
+    def pb(n):
+        return B.Problem(ndim=3, n=n, h=h, nbl=0, space_order=4, nt=10, dt=dt, vmax=3000.0, vel=0x1000, src=src,
+                         wavelet=0x2000, rec=src.copy())
+    ok = pb((1280, 1280, 1300))            # pitched 1280 x 1280 x 1300 = 2.13e9 < 2^31
+    assert ok.field_elements() == 1280 * 1280 * 1300
+    assert ok.workspace_bytes(B.OP_FORWARD) > 4 * 4 * ok.field_elements()
+    big = pb((1290, 1280, 1300))           # rows pitched to 1312: 2.18e9 >= 2^31
+    with pytest.raises(B.WvError):
+        big.field_elements()
+    with pytest.raises(B.WvError):
+        big.workspace_bytes(B.OP_FORWARD)
+
+
 def test_predict_plain_slots_follow_slot_bytes():
     import paper_1810_05268_amd as P
     N, points = 500, 10 ** 6
