@@ -173,7 +173,11 @@ def performance_model(nt, points, slot_bytes, budget, st_plain, st_comp, hint, s
         r["rel_err"] = (r["predicted_ms"] - r["measured_ms"]) / r["measured_ms"]
     full = P.predict(nt, points, budget, False, cp["c_f"], cp["c_r"], t_copy=cp["t_store"],
                      slot_bytes=slot_bytes)["ms_full_storage"]
-    return {"costs_plain": cp, "costs_compressed": cc, "full_storage_ms": full, "runs": rows}
+    # the decision the model exists for: compress at this budget or not (from the timed
+    # compressed call's compressibility profile), against which run measured faster
+    ch = P.choose(nt, points, budget, cp, cc, profile=st_comp["profile"], slot_bytes=slot_bytes)
+    ch["measured_faster"] = "compressed" if phases(st_comp) < phases(st_plain) else "plain"
+    return {"costs_plain": cp, "costs_compressed": cc, "full_storage_ms": full, "runs": rows, "choice": ch}
 
 
 def traffic_per_launch():
@@ -499,12 +503,16 @@ def main():
         _, s0_ = once(args.tol, 0.0, g_comp)
         h_ = plan_hint(s0_, Pn, shot.nt, bb)
         wc_, sc_ = once(args.tol, h_, g_comp)
+        ch_ = P.choose(shot.nt, Pn, bb, P.costs_from_stats(st_plain_ph[0]), P.costs_from_stats(st_comp_ph[0]),
+                       profile=s0_["profile"], slot_bytes=G.slot_bytes)
         e_ = float(torch.linalg.vector_norm(g_comp - g_plain) / torch.linalg.vector_norm(g_plain))
         budget_sweep.append({"budget": bb, "plain_s": wp_, "plain_slots": sp_["slots"],
                              "plain_advances": sp_["advances"], "compressed_s": wc_,
                              "compressed_slots": sc_["slots"], "compressed_advances": sc_["advances"],
                              "retries": sc_["retries"], "speedup_vs_plain": wp_ / wc_,
-                             "grad_rel_err_vs_plain": e_})
+                             "grad_rel_err_vs_plain": e_,
+                             "model_choice": "compressed" if ch_["compressed"] else "plain",
+                             "model_ms": {"plain": ch_["ms_plain"], "compressed": ch_["ms_compressed"]}})
         log(f"budget {bb:.3g} B: plain {wp_:.3f} s (M={sp_['slots']}, {sp_['advances']} advances), compressed "
             f"{wc_:.3f} s (M={sc_['slots']}, {sc_['advances']} advances), {wp_ / wc_:.2f}x, err {e_:.2e}")
 

@@ -371,6 +371,24 @@ typedef struct {
 int wv_predict(int nt, long long points, size_t mem_budget, int compressed, const wv_costs *costs,
                wv_prediction *out);
 
+typedef struct {
+    int compressed;          /* 1 if compressed checkpoints are predicted faster, else 0 */
+    int slots;               /* M of the chosen strategy */
+    double ratio_hint;       /* compressed choice: the planning ratio to pass to the gradient call */
+    double ms_plain;         /* predicted time of plain Revolve */
+    double ms_compressed;    /* predicted time with compressed checkpoints */
+} wv_choice;
+
+/* The decision the run-time model exists for (Sec. "Performance model including
+ * compression"): whether compressing the checkpoints of this gradient pays at this
+ * budget.  Both strategies are priced as wv_predict does, plain with `plain` (its
+ * slot_bytes sizes the slots) and compressed with `compressed`.  With a compressibility
+ * profile (WV_PROFILE sizes, as wv_plan takes; NULL if none) the compressed slot count
+ * is wv_plan's, else the one compressed->ratio gives.  Plain wins ties: it is also
+ * exact.  Host only. */
+int wv_choose(int nt, long long points, size_t mem_budget, const wv_costs *plain, const wv_costs *compressed,
+              const double *profile, int nprofile, wv_choice *out);
+
 const char *wv_strerror(int code);
 
 /* Detail of the last WV_EHIP returned on the calling thread: the failing runtime

@@ -10,11 +10,12 @@ this package only marshals arguments to it:
 * ``build``: compiles the HIP sources in-tree for gfx950.
 """
 from ._binding import (OP_FORWARD, OP_GRADIENT, Problem, WvError, adjoint_src, cfl_dt, forward, gradient,  # noqa
-                       costs_from_stats, lib, misfit_gradient, pad_velocity, plan, predict, schedule,
+                       choose, costs_from_stats, lib, misfit_gradient, pad_velocity, plan, predict, schedule,
                        schedule_forward_steps, velocity_gradient, zfpk_decode, zfpk_encode, zfpk_max_bytes,
                        zfpk_workspace_bytes)
 
-__all__ = ["OP_FORWARD", "OP_GRADIENT", "Problem", "WvError", "adjoint_src", "cfl_dt", "costs_from_stats", "forward",
+__all__ = ["OP_FORWARD", "OP_GRADIENT", "Problem", "WvError", "adjoint_src", "cfl_dt", "choose", "costs_from_stats",
+           "forward",
            "gradient", "lib", "misfit_gradient", "pad_velocity", "plan", "predict", "schedule", "schedule_forward_steps",
            "velocity_gradient",
            "zfpk_decode", "zfpk_encode", "zfpk_max_bytes", "zfpk_workspace_bytes"]

@@ -66,6 +66,14 @@ class WvCosts(C.Structure):
                 ("t_d", C.c_double), ("ratio", C.c_double), ("slot_bytes", C.c_double)]
 
 
+class WvChoice(C.Structure):
+    _fields_ = [("compressed", C.c_int), ("slots", C.c_int), ("ratio_hint", C.c_double), ("ms_plain", C.c_double),
+                ("ms_compressed", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class WvPrediction(C.Structure):
     _fields_ = [("slots", C.c_int), ("advances", C.c_long), ("stores", C.c_long), ("fields", C.c_long),
                 ("decodes", C.c_long), ("ms_forward", C.c_double), ("ms_adjoint", C.c_double),
@@ -84,7 +92,7 @@ class WvResult(C.Structure):
 # every symbol include/wv.h declares
 SYMBOLS = ["wv_cfl_dt", "wv_cfl_dt_to", "wv_workspace_bytes", "wv_field_elements", "wv_forward", "wv_gradient", "wv_misfit_gradient", "wv_adjoint_src",
            "wv_pad_velocity", "wv_velocity_gradient", "wv_zfpk_workspace_bytes", "wv_zfpk_max_bytes",
-           "wv_zfpk_encode", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_predict", "wv_plan", "wv_compressibility", "wv_strerror",
+           "wv_zfpk_encode", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_predict", "wv_choose", "wv_plan", "wv_compressibility", "wv_strerror",
            "wv_last_error", "wv_version", "wv_engine_create", "wv_engine_submit", "wv_engine_wait",
            "wv_engine_pending", "wv_engine_destroy"]
 
@@ -127,6 +135,8 @@ def lib():
         L.wv_schedule_forward_steps.argtypes = [C.c_int, C.c_int]
         L.wv_schedule_forward_steps.restype = C.c_long
         L.wv_predict.argtypes = [C.c_int, C.c_longlong, sz, C.c_int, C.POINTER(WvCosts), C.POINTER(WvPrediction)]
+        L.wv_choose.argtypes = [C.c_int, C.c_longlong, sz, C.POINTER(WvCosts), C.POINTER(WvCosts),
+                                C.POINTER(C.c_double), C.c_int, C.POINTER(WvChoice)]
         L.wv_plan.argtypes = [C.c_int, C.c_longlong, sz, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_int),
                               C.POINTER(C.c_double)]
         L.wv_compressibility.argtypes = [mp, gp, C.c_double, C.c_int, C.POINTER(C.c_size_t), C.c_int,
@@ -227,6 +237,21 @@ def predict(nt: int, points: int, mem_budget: int, compressed: bool, c_f: float,
     out = WvPrediction()
     _check(lib().wv_predict(int(nt), int(points), int(mem_budget), 1 if compressed else 0, C.byref(costs),
                             C.byref(out)), "wv_predict")
+    return out.as_dict()
+
+
+def choose(nt: int, points: int, mem_budget: int, plain: dict, compressed: dict, profile=None,
+           slot_bytes: float = 0.0) -> dict:
+    """Plain or compressed checkpoints for this budget, whichever the run-time model predicts
+    faster (see wv_choose).  plain / compressed: per-unit costs as costs_from_stats returns
+    them; compressed["ratio"] is used when no profile is given."""
+    cp = WvCosts(plain["c_f"], plain["c_r"], plain.get("t_store", 0.0), 0.0, 0.0, 1.0, float(slot_bytes))
+    cc = WvCosts(compressed["c_f"], compressed["c_r"], 0.0, compressed.get("t_store", 0.0), compressed.get("t_d", 0.0),
+                 float(compressed.get("ratio", 0.0)), 0.0)
+    prof = (C.c_double * 17)(*[float(x) for x in profile]) if profile is not None else None
+    out = WvChoice()
+    _check(lib().wv_choose(int(nt), int(points), int(mem_budget), C.byref(cp), C.byref(cc), prof,
+                           17 if profile is not None else 0, C.byref(out)), "wv_choose")
     return out.as_dict()
 
 

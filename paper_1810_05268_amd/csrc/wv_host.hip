@@ -904,6 +904,31 @@ int wv_predict(int nt, long long points, size_t mem_budget, int compressed, cons
     return WV_OK;
 }
 
+int wv_choose(int nt, long long points, size_t mem_budget, const wv_costs *plain, const wv_costs *compressed,
+              const double *profile, int nprofile, wv_choice *out)
+{
+    if (nt < 1 || points < 1 || !plain || !compressed || !out) return WV_EINVAL;
+    if (profile && nprofile != kProfile) return WV_EINVAL;
+    const bool use_profile = profile && profile_valid(profile);
+    if (!use_profile && !(compressed->ratio > 0)) return WV_EINVAL;
+    wv_prediction pp{}, pc{};
+    int rc = wv_predict(nt, points, mem_budget, 0, plain, &pp);
+    if (rc) return rc;
+    wv_costs cc = *compressed;
+    if (use_profile) {
+        const int M = plan_slots_profile(nt, mem_budget, profile);
+        cc.ratio = M > 1 ? ratio_for_slots(nt, mem_budget, (size_t)points * 8, M) : 1.0;
+    }
+    if ((rc = wv_predict(nt, points, mem_budget, 1, &cc, &pc))) return rc;
+    std::memset(out, 0, sizeof(*out));
+    out->ms_plain = pp.ms_total;
+    out->ms_compressed = pc.ms_total;
+    out->compressed = pc.ms_total < pp.ms_total ? 1 : 0;
+    out->slots = out->compressed ? pc.slots : pp.slots;
+    out->ratio_hint = out->compressed ? cc.ratio : 0.0;
+    return WV_OK;
+}
+
 int wv_schedule(int nt, int M, int32_t *actions, size_t cap, size_t *n_actions)
 {
     if (nt < 0 || M < 1 || !n_actions) return WV_EINVAL;

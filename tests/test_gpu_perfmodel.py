@@ -40,3 +40,39 @@ def test_model_predicts_other_budgets(tol):
         assert pr["fields"] == sm["fields"] and pr["decodes"] == sm["decodes"]
         assert abs(pr["ms_total"] - phases) <= 0.15 * phases
         assert abs(pr["ms_total"] - sm["ms_total"]) <= 0.25 * sm["ms_total"]
+
+
+def test_model_chooses_the_faster_strategy():
+    """wv_choose against measurement, with costs from one plain and one compressed call. At a
+    budget of 2 slots plain Revolve recomputes quadratically and compression must win; at a
+    budget that holds every state uncompressed, plain Revolve (copies, no codec) must win; at
+    6 slots the two are within a few percent (this 400-step shot recomputes cheaply), and
+    whichever is chosen must measure within 5 % of the faster."""
+    import torch
+    import paper_1810_05268_amd as P
+    shot = W.layered_noise_3d(n=(120, 112, 104), nt=400, order=8)
+    G, _ = gpu_side(shot)
+    rng = np.random.default_rng(3)
+    res = torch.as_tensor((rng.standard_normal((shot.nt + 1, len(shot.rec))) * 1e-3).astype(np.float32),
+                          device="cuda")
+    tol = 1e-4
+
+    def phases(st):
+        return st["ms_forward"] + st["ms_adjoint"] + st["ms_store"] + st["ms_restore"]
+    G.gradient(res, 20 * G.slot_bytes, timing=1)                                  # warm-up
+    _, sp = G.gradient(res, 20 * G.slot_bytes, timing=1)
+    _, sc = G.gradient(res, 20 * G.slot_bytes, tol=tol, ratio_hint=8.0, timing=1)
+    cp, cc = P.costs_from_stats(sp), P.costs_from_stats(sc)
+    for slots, expect in ((2, 1), (6, None), (shot.nt, 0)):
+        budget = slots * G.slot_bytes
+        ch = P.choose(shot.nt, G.P, budget, cp, cc, profile=sc["profile"], slot_bytes=G.slot_bytes)
+        _, mp = G.gradient(res, budget, timing=1)
+        _, mc = G.gradient(res, budget, tol=tol, ratio_hint=ch["ratio_hint"] if ch["compressed"] else 0.0,
+                           timing=1)
+        t = {0: phases(mp), 1: phases(mc)}
+        print(f"{slots} slots: chose {'compressed' if ch['compressed'] else 'plain'} (predicted plain "
+              f"{ch['ms_plain']:.1f} ms, compressed {ch['ms_compressed']:.1f} ms); measured plain {t[0]:.1f} ms, "
+              f"compressed {t[1]:.1f} ms")
+        if expect is not None:
+            assert ch["compressed"] == expect
+        assert t[ch["compressed"]] <= 1.05 * min(t.values())

@@ -135,6 +135,29 @@ def test_largest_grid_is_validated_on_the_host():
         big.workspace_bytes(B.OP_FORWARD)
 
 
+def test_choose_compression_where_it_pays():
+    """With the large shot's measured per-unit costs (ms), compression is chosen at a tight
+    budget and plain Revolve once every raw state fits (no recomputation and no codec); the
+    choice is the faster of the two predictions, and with a profile the compressed slot count
+    is wv_plan's."""
+    import paper_1810_05268_amd as P
+    N, points, slot = 3000, 64_000_000, 8 * 66_560_000
+    plain = {"c_f": 0.219, "c_r": 0.466, "t_store": 0.093}
+    comp = {"c_f": 0.222, "c_r": 0.468, "t_store": 0.132, "t_d": 0.070, "ratio": 50.0}
+    tight = P.choose(N, points, int(4e9), plain, comp, slot_bytes=slot)
+    assert tight["compressed"] == 1 and tight["ms_compressed"] < tight["ms_plain"]
+    assert tight["slots"] == P.predict(N, points, int(4e9), True, 1, 1, ratio=tight["ratio_hint"])["slots"]
+    roomy = P.choose(N, points, slot * N, plain, comp, slot_bytes=slot)
+    assert roomy["compressed"] == 0 and roomy["slots"] == N and roomy["ratio_hint"] == 0.0
+    assert roomy["ms_plain"] <= roomy["ms_compressed"]
+    prof = [800.0] + [float(2e5 + 3e4 * j) for j in range(1, 17)]
+    M, _ = P.plan(N, points, int(4e9), prof)
+    with_prof = P.choose(N, points, int(4e9), plain, comp, profile=prof, slot_bytes=slot)
+    assert with_prof["compressed"] == 1 and with_prof["slots"] == M
+    with pytest.raises(P.WvError):      # no ratio and no profile
+        P.choose(N, points, int(4e9), plain, {k: v for k, v in comp.items() if k != "ratio"}, slot_bytes=slot)
+
+
 def test_predict_plain_slots_follow_slot_bytes():
     import paper_1810_05268_amd as P
     N, points = 500, 10 ** 6
