@@ -17,7 +17,9 @@
  * Discretisation (the paper gives only the continuous problem):
  *   - grid: n[a] interior points per axis plus nbl absorbing cells on each side;
  *     axis 0 (x) is contiguous, the last axis is depth; arrays are C order
- *     [z][y][x] (3-D) or [z][x] (2-D); P = prod(n[a] + 2 nbl);
+ *     [z][y][x] (3-D) or [z][x] (2-D); P = prod(n[a] + 2 nbl); every array the
+ *     caller passes is dense (the library pads the rows of its own field arrays,
+ *     see wv_field_elements);
  *   - centred space_order-th order second differences (space_order = 2K,
  *     K = 1..8), zero halo outside the padded grid;
  *   - damping a(x) = dt/2 sum_a smax_a (delta_a/nbl)^2,
