@@ -126,3 +126,33 @@ def test_fault_body_all_3000_steps_properties():
     assert phi31 == phi121 == phic
     assert stc["retries"] == 0 and stc["peak_bytes"] <= 16e9
     assert e <= 10 * 1e-4
+
+
+def test_fault_body_ot4_all_3000_steps_properties():
+    """The same properties for the OT4 kernel on the large shot (its own CFL step, 3000
+    steps): plain Revolve bit-identical at 31 and 61 slots with the binomial number of
+    forward steps, the misfit independent of the checkpoint strategy, the compressed
+    gradient (planned from the probed profile, no retry) within 10 tol of the plain one."""
+    import torch
+    shot = W.fault_body_3d()
+    Gt, _ = gpu_side(shot, "true", time_order=4)
+    d_obs = Gt.forward()
+    del Gt
+    torch.cuda.empty_cache()
+    G, _ = gpu_side(shot, time_order=4)
+    ga = torch.empty(G.shape, dtype=torch.float64, device="cuda")
+    gb = torch.empty_like(ga)
+    gc = torch.empty_like(ga)
+    pa, _, sa = G.misfit_gradient(d_obs, G.slot_bytes * 30, out=ga)
+    pb, _, sb = G.misfit_gradient(d_obs, G.slot_bytes * 60, out=gb)
+    G._ws = None
+    torch.cuda.empty_cache()
+    pc, _, sc = G.misfit_gradient(d_obs, int(16e9), 1e-4, out=gc)
+    e = float(torch.linalg.vector_norm(gc - ga) / torch.linalg.vector_norm(ga))
+    print(f"OT4 3000 steps: advances {sa['advances']} / {sb['advances']}, compressed slots {sc['slots']}, "
+          f"rel-L2 to plain {e:.2e}")
+    assert sa["advances"] == SC.p_closed(shot.nt + 1, 31) and sb["advances"] == SC.p_closed(shot.nt + 1, 61)
+    assert torch.equal(ga, gb)
+    assert pa == pb == pc
+    assert sc["retries"] == 0 and sc["peak_bytes"] <= 16e9
+    assert e <= 10 * 1e-4
