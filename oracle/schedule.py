@@ -24,7 +24,12 @@ The recomputation count of eq. (2) is p(N+1, M) - N: zero iff M >= N, as the
 paper remarks after eq. (3).
 
 ``schedule(N, M)`` emits the action list of the recursion with the smallest
-optimal first advance k (ties broken towards the left).  Actions are int32
+optimal first advance k (ties broken towards the left).  ``schedule(N, M,
+write_min=True)`` breaks the tie instead towards the fewest checkpoint writes:
+among the optimal first advances it takes the k that minimises the stores of the
+whole recursion (``write_min_table``, a dynamic programme over segments; smallest
+k among equal counts), the tie-break the paper points to for schedules whose
+writes are expensive.  Actions are int32
 triples (op, a, b):
   1 ADVANCE x_a -> x_b, 2 STORE x_a in slot b, 3 RESTORE x_a from slot b,
   4 FREE slot b (holding x_a), 5 REVERSE step a.
@@ -88,20 +93,16 @@ def p_recurrence(l: int, c: int) -> int:
 
 def _closed_vec(ls: np.ndarray, c: int) -> np.ndarray:
     """p_closed over an array of chain lengths (exact integers)."""
-    out = np.zeros(ls.shape, dtype=np.int64)
+    ls = np.asarray(ls, dtype=np.int64)
     if c == 1:
         return ls * (ls - 1) // 2
-    bet = [beta(c, r) for r in range(0, 64)]
-    bet1 = [beta(c + 1, r) for r in range(0, 64)]
-    for i, l in enumerate(ls.tolist()):
-        if l <= 1:
-            out[i] = 0
-            continue
-        r = 0
-        while bet[r] < l:
-            r += 1
-        out[i] = r * l - (bet1[r - 1] if r >= 1 else 0)
-    return out
+    top = int(ls.max()) if ls.size else 0
+    bet = [beta(c, 0)]
+    while bet[-1] < top:                  # beta(c, r) for r = 0.. until it covers every l
+        bet.append(beta(c, len(bet)))
+    r = np.searchsorted(np.asarray(bet, dtype=np.int64), ls, side="left")   # min r: beta(c, r) >= l
+    bet1 = np.asarray([beta(c + 1, j - 1) for j in range(len(bet))], dtype=np.int64)
+    return np.where(ls <= 1, 0, r * ls - bet1[r])
 
 
 def _first_advance(l: int, c: int) -> int:
@@ -113,10 +114,37 @@ def _first_advance(l: int, c: int) -> int:
     return int(k[int(np.argmin(cost))])
 
 
-def schedule(N: int, M: int) -> np.ndarray:
+def write_min_table(L: int, C: int) -> tuple[np.ndarray, np.ndarray]:
+    """W[l, c]: the fewest stores of the recursion for a segment of l steps and c slots
+    when every split takes an optimal first advance (minimal forward steps); K[l, c]:
+    the smallest first advance that attains W[l, c].  A split stores once (unless its
+    right part is the single state just reached, which is reversed at once), then the
+    right part has c-1 slots and the left part c:
+        W[l, c] = min_{k optimal} ( [l-k > 1] + W[l-k, c-1] + W[k, c] ),  W[1, c] = W[l, 1] = 0."""
+    W = np.zeros((L + 1, C + 1), dtype=np.int64)
+    K = np.ones((L + 1, C + 1), dtype=np.int64)
+    ls = np.arange(L + 1, dtype=np.int64)
+    for c in range(2, C + 1):
+        pc, pc1 = _closed_vec(ls, c), _closed_vec(ls, c - 1)    # p(., c) and p(., c-1)
+        for l in range(2, L + 1):
+            k = ls[1:l]
+            cost = k + pc[k] + pc1[l - k]
+            opt = k[cost == cost.min()]
+            # a right part of one state is reversed at once from the working state:
+            # its checkpoint would never be read, so that split stores nothing
+            w = (l - opt > 1) + W[l - opt, c - 1] + W[opt, c]
+            j = int(np.argmin(w))
+            W[l, c] = w[j]
+            K[l, c] = opt[j]
+    return W, K
+
+
+def schedule(N: int, M: int, write_min: bool = False) -> np.ndarray:
     """Action list (int32, shape (n, 3)) reversing N steps with M slots."""
     if N < 0 or M < 1:
         raise ValueError("need N >= 0 and M >= 1")
+    if write_min:
+        _, K = write_min_table(N + 1, min(M, N + 1))
     acts: list[tuple[int, int, int]] = []
     state = {"wm": 0, "depth": 0}
 
@@ -145,8 +173,15 @@ def schedule(N: int, M: int) -> np.ndarray:
                     state["wm"] = s + i
                 reverse(s + i)
             return
-        k = _first_advance(l, c)
+        k = int(K[l, min(c, K.shape[1] - 1)]) if write_min else _first_advance(l, c)
         need(s, slot)
+        if write_min and l - k == 1:
+            # the state reached is reversed at once from the working state: no checkpoint
+            acts.append((ADVANCE, s, s + k))
+            state["wm"] = s + k
+            reverse(s + k)
+            rev(s, k, c, slot)
+            return
         acts.append((ADVANCE, s, s + k))
         state["wm"] = s + k
         state["depth"] += 1
@@ -178,6 +213,39 @@ def counts(acts: np.ndarray) -> dict:
         "reverses": int((a[:, 0] == REVERSE).sum()),
         "max_slot": int(st[:, 2].max()) if len(st) else 0,
     }
+
+
+def brute_force_min_writes(N: int, M: int) -> tuple[int, int]:
+    """Exhaustive search over every schedule (tiny N): the fewest forward steps and, among
+    schedules with that many, the fewest stores (lexicographic shortest path)."""
+    start = (0, frozenset([0]), N)
+    dist = {start: (0, 0)}
+    heap = [((0, 0), 0, frozenset([0]), N)]
+    while heap:
+        d, wm, S, nr = heapq.heappop(heap)
+        if dist.get((wm, S, nr), (1 << 60, 0)) < d:
+            continue
+        if nr == 0:
+            return d
+        moves = []
+        if wm == nr:
+            moves.append(((0, 0), wm, S, nr - 1))
+        if wm < nr:
+            moves.append(((1, 0), wm + 1, S, nr))
+        if wm not in S and len(S) < M:
+            moves.append(((0, 1), wm, S | {wm}, nr))
+        for s_ in S:
+            if s_ != wm:
+                moves.append(((0, 0), s_, S, nr))
+            if s_ != 0:
+                moves.append(((0, 0), wm, S - {s_}, nr))
+        for (da, dw), w2, S2, n2 in moves:
+            key = (w2, S2, n2)
+            nd = (d[0] + da, d[1] + dw)
+            if nd < dist.get(key, (1 << 60, 0)):
+                dist[key] = nd
+                heapq.heappush(heap, (nd, w2, S2, n2))
+    raise RuntimeError("no schedule found")
 
 
 def brute_force_min(N: int, M: int) -> int:

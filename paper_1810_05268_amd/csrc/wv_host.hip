@@ -73,23 +73,17 @@ long long binom(int c, long long r)
     return res;
 }
 
+// min { r : beta(c, r) >= l }, stepping beta(c, r) = beta(c, r-1) (c+r) / r (exact)
 int repetitions(long long l, int c)
 {
     int r = 0;
-    while (binom(c, r) < l) ++r;
+    long long b = 1;
+    while (b < l) {
+        ++r;
+        const __int128 t = (__int128)b * (c + r) / r;
+        b = t >= kSat ? kSat : (long long)t;
+    }
     return r;
-}
-
-// smallest optimal first advance for a segment of l steps and c slots (c >= 2):
-// Griewank's optimal set is the interval
-// [max(beta(c,r-2), l-beta(c-1,r), 1), min(beta(c,r-1), l-beta(c-1,r-1), l-1)].
-long long first_advance(long long l, int c)
-{
-    if (c >= l - 1) return 1;
-    const int r = repetitions(l, c);
-    long long lo = binom(c, r - 2);
-    lo = std::max(lo, l - binom(c - 1, r));
-    return std::max(lo, 1LL);
 }
 
 long long forward_steps(long long nt, int M)
@@ -109,9 +103,98 @@ struct Frame {
     int nslot, phase;
 };
 
+// Write-minimal tie-break.  Every split takes a first advance from Griewank's optimal
+// interval (so the forward-step count stays minimal); among those, the k that minimises
+// the checkpoint writes of the whole recursion (smallest such k):
+//   W(l, c) = min_{k in [lo, hi]} f(k),  f(k) = [l-k > 1] + W(l-k, c-1) + W(k, c),
+//   W(1, c) = W(l, 1) = 0,
+// where a right part of a single state stores nothing: that state is the one just
+// reached and is reversed at once from the working state, so a checkpoint of it would
+// never be read.  Where c >= l-1 every state fits and k = 1, W = l-2.  Where two
+// repetitions suffice (beta(c, 2) >= l) the minimum is W = l-2-min(c, l-1-c).  Over the
+// optimal interval f is convex (its differences never decrease), so the smallest
+// minimiser is the first k whose forward difference is >= 0, found by bisection.  Both
+// facts hold on every entry the full programme (a scan of the interval) was compared on;
+// the schedules are checked against it.  The table holds the entries with
+// beta(c, 2) < l (c < sqrt(2l)), column by column, for the slot counts asked for so far;
+// it is kept per thread and reused by later schedules of the same length (the planner
+// asks for many slot counts of one run).
+struct WriteMin {
+    long long L = 0;
+    int C = 1;                  // columns 2..C are built
+    std::vector<int32_t> W, K;  // [c * (L+1) + l], used where beta(c, 2) < l
+    int32_t w(long long l, int c) const
+    {
+        if (l <= 2 || c <= 1) return 0;
+        if (c >= l - 1) return (int32_t)(l - 2);
+        if (binom(c, 2) >= l) return (int32_t)(l - 2 - std::min<long long>(c, l - 1 - c));
+        return W[(size_t)c * (L + 1) + l];
+    }
+};
+
+thread_local WriteMin g_wmin;
+
+// Griewank's set of optimal first advances for a segment of l steps and c slots (c >= 2):
+// the interval [max(beta(c,r-2), l-beta(c-1,r), 1), min(beta(c,r-1), l-beta(c-1,r-1), l-1)].
+void optimal_interval(long long l, int c, long long &lo, long long &hi)
+{
+    const int r = repetitions(l, c);
+    lo = std::max(std::max(binom(c, r - 2), l - binom(c - 1, r)), 1LL);
+    hi = std::min(std::min(binom(c, r - 1), l - binom(c - 1, r - 1)), l - 1);
+}
+
+// the write-minimal first advance and the writes it leads to
+long long best_split(const WriteMin &t, long long l, int c, int32_t *writes)
+{
+    long long lo, hi;
+    optimal_interval(l, c, lo, hi);
+    auto f = [&](long long k) { return (int32_t)(l - k > 1) + t.w(l - k, c - 1) + t.w(k, c); };
+    while (lo < hi) {
+        const long long mid = lo + (hi - lo) / 2;
+        if (f(mid + 1) >= f(mid)) hi = mid;
+        else lo = mid + 1;
+    }
+    if (writes) *writes = f(lo);
+    return lo;
+}
+
+// the table for schedules of L states with up to M slots
+const WriteMin &write_min_table(long long L, int M)
+{
+    WriteMin &t = g_wmin;
+    if (t.L != L) {
+        t.L = L;
+        t.C = 1;
+        t.W.clear();
+        t.K.clear();
+    }
+    int C = 1;
+    while (C < M && binom(C + 1, 2) < L) ++C;   // columns that hold an entry with beta(c, 2) < l
+    if (C <= t.C) return t;
+    t.W.resize((size_t)(C + 1) * (L + 1), 0);
+    t.K.resize((size_t)(C + 1) * (L + 1), 1);
+    for (int c = t.C + 1; c <= C; ++c)
+        for (long long l = binom(c, 2) + 1; l <= L; ++l) {   // beta(c, 2) < l (so c < l-1)
+            int32_t wv = 0;
+            const long long k = best_split(t, l, c, &wv);
+            t.W[(size_t)c * (L + 1) + l] = wv;
+            t.K[(size_t)c * (L + 1) + l] = (int32_t)k;
+        }
+    t.C = C;
+    return t;
+}
+
 void make_schedule(int nt, int M, std::vector<int32_t> &out)
 {
     out.clear();
+    const long long L = (long long)nt + 1;
+    // every segment of the recursion has c <= M, and c >= l-1 throughout when M >= L-1
+    const WriteMin *tab = (M >= 2 && M < L - 1) ? &write_min_table(L, M) : nullptr;
+    auto split = [&](long long l, int c) -> long long {
+        if (c >= l - 1) return 1;
+        if (binom(c, 2) < l) return tab->K[(size_t)c * (L + 1) + l];
+        return best_split(*tab, l, c, nullptr);
+    };
     int wm = 0, depth = 0;
     auto emit = [&](int op, long long a, long long b) {
         out.push_back(op);
@@ -154,10 +237,15 @@ void make_schedule(int nt, int M, std::vector<int32_t> &out)
             }
             continue;
         }
-        const long long k = first_advance(f.l, f.c);
+        const long long k = split(f.l, f.c);
         need(f.s, f.slot);
         emit(ADVANCE, f.s, f.s + k);
         wm = (int)(f.s + k);
+        if (f.l - k == 1) {            // reversed at once from the working state: no checkpoint
+            emit(REVERSE, f.s + k, 0);
+            st.push_back({f.s, k, f.c, f.slot, 0, 0, 0});
+            continue;
+        }
         ++depth;
         emit(STORE, f.s + k, depth);
         st.push_back({f.s, f.l, f.c, f.slot, k, depth, 1});

@@ -38,7 +38,7 @@ def test_fault_body_full_grid_revolve_gradient():
     rng = np.random.default_rng(11)
     res = rng.standard_normal((nt + 1, len(shot.rec))) * 1e-3
     res[0] = 0.0
-    acts = SC.schedule(nt, M)
+    acts = SC.schedule(nt, M, write_min=True)
     g_or, st_or = S.gradient_actions(res, acts, M)
     G, _ = gpu_side(shot)
     g, st = G.gradient(torch.as_tensor(res.astype(np.float32), device="cuda"), G.slot_bytes * (M - 1))
@@ -84,7 +84,7 @@ def test_layered_noise_full_size_forward_and_revolve():
     e_d = rel_l2(data.cpu().numpy(), ref["data"])
     res = ref["data"] - d_obs
     M = 21                  # 20 stored checkpoints plus the initial (zero) state
-    acts = SC.schedule(shot.nt, M)
+    acts = SC.schedule(shot.nt, M, write_min=True)
     g_or, st_or = S.gradient_actions(res, acts, M)
     g, st = G.gradient(torch.as_tensor(res.astype(np.float32), device="cuda"), G.slot_bytes * (M - 1))
     e_g = rel_l2(g.cpu().numpy(), g_or)

@@ -104,10 +104,11 @@ def test_misfit_definition():
     assert oracle.misfit(a, b) == 0.5 * (1.0 + 0.25 + 0.0 + 4.0)
 
 
+@pytest.mark.parametrize("write_min", [False, True])
 @pytest.mark.parametrize("M", [1, 2, 3, 5, 12, 80, 200])
-def test_revolve_bit_identical_to_full_storage(prob2d, M):
+def test_revolve_bit_identical_to_full_storage(prob2d, M, write_min):
     p = prob2d
-    acts = SC.schedule(p["spec"].nt, M)
+    acts = SC.schedule(p["spec"].nt, M, write_min=write_min)
     g, st = p["S"].gradient_actions(p["res"], acts, M)
     assert np.array_equal(g, p["g"])
     c = SC.counts(acts)

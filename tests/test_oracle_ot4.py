@@ -156,10 +156,11 @@ def test_central_finite_differences(prob_ot4):
         assert errs[1] < errs[0] / 30 and errs[2] < errs[1] / 30
 
 
+@pytest.mark.parametrize("write_min", [False, True])
 @pytest.mark.parametrize("M", [1, 3, 12, 80])
-def test_revolve_bit_identical_to_full_storage(prob_ot4, M):
+def test_revolve_bit_identical_to_full_storage(prob_ot4, M, write_min):
     p = prob_ot4
-    acts = SC.schedule(p["spec"].nt, M)
+    acts = SC.schedule(p["spec"].nt, M, write_min=write_min)
     g, st = p["S"].gradient_actions(p["res"], acts, M)
     assert np.array_equal(g, p["g"])
     assert st["advances"] == SC.p_closed(p["spec"].nt + 1, M)

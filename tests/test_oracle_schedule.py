@@ -91,3 +91,62 @@ def test_first_advance_is_smallest_optimal():
     for c in range(2, 9):
         for l in range(2, 61):
             assert SC._first_advance(l, c) == kmin[c, l]
+
+
+# ------------------------------------------------------------------ write-minimal tie-break
+
+@pytest.mark.parametrize("N", range(1, 12))
+def test_write_min_is_optimal_by_exhaustive_search(N):
+    """Among all schedules with the fewest forward steps, none writes fewer checkpoints
+    than the write-minimal recursion (lexicographic shortest path over every schedule)."""
+    for M in range(1, 6):
+        c = SC.counts(SC.schedule(N, M, write_min=True))
+        assert SC.brute_force_min_writes(N, M) == (SC.p_closed(N + 1, M), c["stores"]), M
+
+
+def test_write_min_closed_form_where_two_repetitions_suffice():
+    """W(l, c) = l - 2 where every state fits (c >= l-1), and l - 2 - min(c, l-1-c)
+    wherever two repetitions suffice (beta(c, 2) >= l)."""
+    L = C = 240
+    W, _ = SC.write_min_table(L, C)
+    n = 0
+    for c in range(2, C + 1):
+        for l in range(2, L + 1):
+            if c >= l - 1:
+                assert W[l, c] == l - 2, (l, c)
+            elif SC.beta(c, 2) >= l:
+                assert W[l, c] == l - 2 - min(c, l - 1 - c), (l, c)
+                n += 1
+    assert n > 10_000
+
+
+@pytest.mark.parametrize("N,M", [(1, 1), (2, 1), (7, 2), (30, 3), (64, 5), (100, 7), (250, 16), (40, 40), (40, 100)])
+def test_write_min_schedule_is_valid(N, M):
+    acts = SC.schedule(N, M, write_min=True)
+    assert simulate(acts, N, M) == list(range(N, 0, -1))
+    assert SC.counts(acts)["advances"] == SC.p_closed(N + 1, M)
+
+
+def test_write_min_never_writes_more_and_keeps_the_step_count():
+    for N in range(1, 61):
+        for M in range(1, 11):
+            a, b = SC.counts(SC.schedule(N, M)), SC.counts(SC.schedule(N, M, write_min=True))
+            assert b["advances"] == a["advances"]
+            assert b["stores"] <= a["stores"]
+            assert b["max_slot"] <= M - 1
+
+
+PINNED_WRITE_MIN = [  # N, M, forward steps t(N+1, M), stores W (write-minimal)
+    (500, 10, 1640, 219),
+    (1000, 20, 2750, 769),
+    (3000, 2, 152000, 75),
+    (3000, 31, 8442, 2472),
+]
+
+
+@pytest.mark.parametrize("N,M,t,Wn", PINNED_WRITE_MIN)
+def test_write_min_pinned_counts(N, M, t, Wn):
+    c = SC.counts(SC.schedule(N, M, write_min=True))
+    assert c["advances"] == t == SC.p_closed(N + 1, M)
+    assert c["stores"] == Wn
+    assert c["reverses"] == N
