@@ -307,10 +307,18 @@ int wv_engine_destroy(wv_engine *engine);
  * the same schedule the gradient calls execute.  Actions are int32 triples (op, a, b):
  *   1 ADVANCE x_a -> x_b, 2 STORE x_a in slot b, 3 RESTORE x_a from slot b,
  *   4 FREE slot b (holding x_a), 5 REVERSE step a.
- * The first advance of every split is the smallest optimal one (Griewank's
- * binomial interval).  actions: host [cap][3]; *n_actions receives the count;
- * WV_ECAP if cap is too small (the count is still returned). */
-int wv_schedule(int nt, int M, int32_t *actions, size_t cap, size_t *n_actions);
+ * Every split takes a first advance from Griewank's binomial interval of optimal ones,
+ * so the forward steps are the minimum t(nt+1, M) of recurrence (3) either way:
+ *   write_min = 0: the smallest optimal first advance.  Compressed gradient calls run
+ *     this one: their checkpoint streams grow over the run, and these splits hold the
+ *     earliest states, so more slots fit a budget.
+ *   write_min != 0: the first advance that minimises the checkpoint writes of the whole
+ *     reversal (W in the storage overhead W S / B; the smallest such advance among
+ *     equal counts), and no store of a state that is reversed at once from the working
+ *     state.  Uncompressed gradient calls run this one: their slots are of one size.
+ * actions: host [cap][3]; *n_actions receives the count; WV_ECAP if cap is too small
+ * (the count is still returned). */
+int wv_schedule(int nt, int M, int write_min, int32_t *actions, size_t cap, size_t *n_actions);
 
 /* Forward steps of that schedule: t(nt+1, M) = r (nt+1) - C(M+1+r-1, r-1),
  * r = min{r : C(M+r, r) >= nt+1}. */

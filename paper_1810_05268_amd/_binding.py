@@ -131,7 +131,7 @@ def lib():
         L.wv_zfpk_max_bytes.restype = sz
         L.wv_zfpk_encode.argtypes = [vp, C.c_int, ip, C.c_double, vp, sz, C.POINTER(C.c_size_t), vp, sz, vp]
         L.wv_zfpk_decode.argtypes = [vp, C.c_int, ip, vp, vp]
-        L.wv_schedule.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int32), sz, C.POINTER(C.c_size_t)]
+        L.wv_schedule.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int32), sz, C.POINTER(C.c_size_t)]
         L.wv_schedule_forward_steps.argtypes = [C.c_int, C.c_int]
         L.wv_schedule_forward_steps.restype = C.c_long
         L.wv_predict.argtypes = [C.c_int, C.c_longlong, sz, C.c_int, C.POINTER(WvCosts), C.POINTER(WvPrediction)]
@@ -198,11 +198,15 @@ def cfl_dt(ndim: int, h, space_order: int, vmax: float, time_order: int = 2) -> 
     return float(lib().wv_cfl_dt_to(ndim, hh, space_order, vmax, time_order))
 
 
-def schedule(nt: int, M: int) -> np.ndarray:
+def schedule(nt: int, M: int, write_min: bool = True) -> np.ndarray:
+    """wv_schedule: write_min=True is what uncompressed gradient calls run, False what
+    compressed ones run."""
     n = C.c_size_t(0)
-    lib().wv_schedule(nt, M, None, 0, C.byref(n))
+    wm = 1 if write_min else 0
+    lib().wv_schedule(nt, M, wm, None, 0, C.byref(n))
     out = np.zeros((max(n.value, 1), 3), dtype=np.int32)
-    _check(lib().wv_schedule(nt, M, out.ctypes.data_as(C.POINTER(C.c_int32)), n.value, C.byref(n)), "wv_schedule")
+    _check(lib().wv_schedule(nt, M, wm, out.ctypes.data_as(C.POINTER(C.c_int32)), n.value, C.byref(n)),
+           "wv_schedule")
     return out[: n.value]
 
 

@@ -184,14 +184,24 @@ const WriteMin &write_min_table(long long L, int M)
     return t;
 }
 
-void make_schedule(int nt, int M, std::vector<int32_t> &out)
+// The reversal of nt steps with M slots.  write_min: the write-minimal first advance,
+// for slots of one size (exact copies), where every optimal split peaks at the same
+// memory and fewer writes cost nothing.  Otherwise the smallest optimal first advance,
+// for compressed slots: their streams grow over the run (late states compress worst),
+// and the smallest splits hold the earliest states, so more slots fit a budget.
+void make_schedule(int nt, int M, bool write_min, std::vector<int32_t> &out)
 {
     out.clear();
     const long long L = (long long)nt + 1;
     // every segment of the recursion has c <= M, and c >= l-1 throughout when M >= L-1
-    const WriteMin *tab = (M >= 2 && M < L - 1) ? &write_min_table(L, M) : nullptr;
+    const WriteMin *tab = (write_min && M >= 2 && M < L - 1) ? &write_min_table(L, M) : nullptr;
     auto split = [&](long long l, int c) -> long long {
         if (c >= l - 1) return 1;
+        if (!write_min) {
+            long long lo, hi;
+            optimal_interval(l, c, lo, hi);
+            return lo;
+        }
         if (binom(c, 2) < l) return tab->K[(size_t)c * (L + 1) + l];
         return best_split(*tab, l, c, nullptr);
     };
@@ -241,7 +251,7 @@ void make_schedule(int nt, int M, std::vector<int32_t> &out)
         need(f.s, f.slot);
         emit(ADVANCE, f.s, f.s + k);
         wm = (int)(f.s + k);
-        if (f.l - k == 1) {            // reversed at once from the working state: no checkpoint
+        if (write_min && f.l - k == 1) {   // reversed at once from the working state: no checkpoint
             emit(REVERSE, f.s + k, 0);
             st.push_back({f.s, k, f.c, f.slot, 0, 0, 0});
             continue;
@@ -428,7 +438,7 @@ double profile_size(const double *prof, int N, long long k)
 double simulate_peak(int N, int M, const double *prof)
 {
     std::vector<int32_t> acts;
-    make_schedule(N, M, acts);
+    make_schedule(N, M, false, acts);
     const std::vector<char> need2 = second_level_needed(acts, M);
     std::vector<double> held((size_t)M + 2, 0.0);
     double live = 0.0, peak = 0.0;
@@ -975,7 +985,7 @@ int wv_predict(int nt, long long points, size_t mem_budget, int compressed, cons
     const int M = plan_slots(nt, mem_budget, S, compressed != 0, compressed ? costs->ratio : 1.0);
     if (M < 1) return WV_EBUDGET;
     std::vector<int32_t> acts;
-    make_schedule(nt, M, acts);
+    make_schedule(nt, M, compressed == 0, acts);
     const DryRun r = dry_run(acts, M, compressed != 0);
     std::memset(out, 0, sizeof(*out));
     out->slots = M;
@@ -1017,11 +1027,11 @@ int wv_choose(int nt, long long points, size_t mem_budget, const wv_costs *plain
     return WV_OK;
 }
 
-int wv_schedule(int nt, int M, int32_t *actions, size_t cap, size_t *n_actions)
+int wv_schedule(int nt, int M, int write_min, int32_t *actions, size_t cap, size_t *n_actions)
 {
     if (nt < 0 || M < 1 || !n_actions) return WV_EINVAL;
     std::vector<int32_t> a;
-    make_schedule(nt, M, a);
+    make_schedule(nt, M, write_min != 0, a);
     *n_actions = a.size() / 3;
     if (a.size() / 3 > cap) return WV_ECAP;
     if (!a.empty()) std::memcpy(actions, a.data(), a.size() * 4);
@@ -1139,7 +1149,7 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
     if (R.src_adj_mode) {
         for (int k = N; k >= 1; --k) acts.insert(acts.end(), {REVERSE, k, 0});
     } else {
-        make_schedule(N, M, acts);
+        make_schedule(N, M, !(R.tol > 0), acts);
     }
     int rc = WV_OK;
     const bool comp = R.tol > 0;

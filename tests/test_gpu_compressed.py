@@ -35,7 +35,7 @@ def test_compressed_gradient_within_codec_bound(case, tol):
     shot = W.near_anomaly_2d() if case == "2d" else small_3d(nt=100)
     M = 8
     S, res, g0 = _problem(shot)
-    acts = SC.schedule(shot.nt, M, write_min=True)
+    acts = SC.schedule(shot.nt, M)
     g_or, st_or = S.gradient_actions(res, acts, M, tol=tol, increment=True)
     e_or = rel_l2(g_or, g0)
     G, _ = gpu_side(shot)

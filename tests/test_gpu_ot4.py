@@ -83,7 +83,7 @@ def test_revolve_bit_identical_and_compressed():
         assert st["advances"] == SC.p_closed(shot.nt + 1, M)
         assert torch.equal(g, full), M
     M, tol = 8, 1e-5
-    acts = SC.schedule(shot.nt, M, write_min=True)
+    acts = SC.schedule(shot.nt, M)
     g_or, _ = S.gradient_actions(res, acts, M, tol=tol, increment=True)
     e_or = rel_l2(g_or, gref)
     g, st = G.gradient(rt, int(8 * G.P * (M - 1) * 1.05), tol=tol, ratio_hint=1.0)

@@ -38,11 +38,12 @@ def test_header_symbols_exported():
 
 @pytest.mark.parametrize("N,M", [(1, 1), (2, 1), (7, 2), (30, 3), (100, 7), (500, 10), (1000, 20), (3000, 2),
                                  (3000, 31), (1200, 300), (40, 40), (40, 100)])
-def test_schedule_identical_to_oracle(N, M):
-    """The library emits the write-minimal schedule: the oracle's, action for action."""
+@pytest.mark.parametrize("write_min", [True, False])
+def test_schedule_identical_to_oracle(N, M, write_min):
+    """Both split rules of the library: the oracle's schedules, action for action."""
     import paper_1810_05268_amd as P
-    a = P.schedule(N, M)
-    b = SC.schedule(N, M, write_min=True)
+    a = P.schedule(N, M, write_min)
+    b = SC.schedule(N, M, write_min=write_min)
     assert np.array_equal(a, b)
     assert P.schedule_forward_steps(N, M) == SC.p_closed(N + 1, M)
 
@@ -51,7 +52,14 @@ def test_schedule_grid_identical_to_oracle():
     import paper_1810_05268_amd as P
     for N in range(0, 41):
         for M in range(1, 14):
-            assert np.array_equal(P.schedule(N, M), SC.schedule(N, M, write_min=True)), (N, M)
+            for wm in (True, False):
+                assert np.array_equal(P.schedule(N, M, wm), SC.schedule(N, M, write_min=wm)), (N, M, wm)
+
+
+@pytest.mark.parametrize("N,M", [(3000, 312), (3000, 1250)])
+def test_smallest_split_schedule_identical_to_oracle_at_large_slot_counts(N, M):
+    import paper_1810_05268_amd as P
+    assert np.array_equal(P.schedule(N, M, False), SC.schedule(N, M))
 
 
 @pytest.mark.parametrize("N,M", [(3000, 312), (3000, 1250), (3000, 2486)])
@@ -284,7 +292,7 @@ def _peak(N, M, prof):
     (independent of the library: oracle schedule, level scan above, linear sizes)."""
     import math
     from oracle import schedule as SC
-    acts = [tuple(a) for a in SC.schedule(N, M, write_min=True)]
+    acts = [tuple(a) for a in SC.schedule(N, M)]
     need, _ = _second_level_stores(acts)
     ks = [0] + [-(-(j * N) // 16) for j in range(1, 17)]
 
