@@ -28,8 +28,10 @@ optimal first advance k (ties broken towards the left).  ``schedule(N, M,
 write_min=True)`` breaks the tie instead towards the fewest checkpoint writes:
 among the optimal first advances it takes the k that minimises the stores of the
 whole recursion (``write_min_table``, a dynamic programme over segments; smallest
-k among equal counts), the tie-break the paper points to for schedules whose
-writes are expensive.  Actions are int32
+k among equal counts): every write is charged in the storage overhead W S / B of the
+checkpointing performance model, and any k of the interval is optimal in steps.
+A right part of a single state is then not stored: it is the state just reached,
+reversed at once from the working state.  Actions are int32
 triples (op, a, b):
   1 ADVANCE x_a -> x_b, 2 STORE x_a in slot b, 3 RESTORE x_a from slot b,
   4 FREE slot b (holding x_a), 5 REVERSE step a.
