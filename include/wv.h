@@ -173,7 +173,8 @@ int wv_forward(const wv_model *model, const wv_geom *geom, float *data, float *s
                void *ws, size_t ws_bytes, void *stream);
 
 /* Adjoint-state gradient with respect to m for a given data residual r = d_sim - d_obs,
- * reversed with Revolve checkpointing inside mem_budget bytes of checkpoint memory.
+ * reversed with Revolve checkpointing inside mem_budget bytes of checkpoint memory, on
+ * the schedule wv_schedule gives (write_min = 1 when tol == 0, 0 when tol > 0).
  *   residual    device [nt+1][nrec] float (row 0 unused)
  *   mem_budget  bytes available for checkpoints (SI bytes); the slot count is
  *               M = min(nt, 1 + floor(mem_budget / slot)), the 1 being x_0 (the zero

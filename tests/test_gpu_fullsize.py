@@ -45,6 +45,7 @@ def test_fault_body_full_grid_revolve_gradient():
     e = rel_l2(g.cpu().numpy(), g_or)
     print(f"full grid gradient rel-L2 {e:.2e}", st)
     assert st["slots"] == M and st["advances"] == st_or["advances"]
+    assert st["stores"] == st_or["stores"] == SC.counts(acts)["stores"]
     assert e <= GRAD_TOL
 
 
@@ -91,6 +92,7 @@ def test_layered_noise_full_size_forward_and_revolve():
     print(f"168^3: data {e_d:.2e} gradient {e_g:.2e} advances {st['advances']}")
     assert e_d <= WAVEFIELD_TOL
     assert st["advances"] == st_or["advances"] == SC.p_closed(shot.nt + 1, M)
+    assert st["stores"] == st_or["stores"] == SC.counts(acts)["stores"]
     assert e_g <= GRAD_TOL
 
 
