@@ -317,6 +317,9 @@ int wv_engine_destroy(wv_engine *engine);
  *     reversal (W in the storage overhead W S / B; the smallest such advance among
  *     equal counts), and no store of a state that is reversed at once from the working
  *     state.  Uncompressed gradient calls run this one: their slots are of one size.
+ *     Its host table takes 8 (C+1)(nt+2) bytes, C = min(M, largest c with
+ *     C(c+2, 2) < nt+1), kept per thread for later calls of the same nt; where that
+ *     exceeds 2^26 entries (512 MB) the smallest optimal advance is used instead.
  * actions: host [cap][3]; *n_actions receives the count; WV_ECAP if cap is too small
  * (the count is still returned). */
 int wv_schedule(int nt, int M, int write_min, int32_t *actions, size_t cap, size_t *n_actions);

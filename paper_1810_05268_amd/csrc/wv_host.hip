@@ -158,6 +158,24 @@ long long best_split(const WriteMin &t, long long l, int c, int32_t *writes)
     return lo;
 }
 
+// columns the table needs for L states and up to M slots: those with an entry where
+// beta(c, 2) < l
+int write_min_columns(long long L, int M)
+{
+    int C = 1;
+    while (C < M && binom(C + 1, 2) < L) ++C;
+    return C;
+}
+
+// The table holds (C+1)(L+1) entries of each kind; a reversal that would need more is
+// scheduled with the smallest optimal split instead (still minimal in forward steps).
+constexpr long long kWriteMinEntries = 1LL << 26;
+
+bool write_min_fits(long long L, int M)
+{
+    return (long long)(write_min_columns(L, M) + 1) * (L + 1) <= kWriteMinEntries;
+}
+
 // the table for schedules of L states with up to M slots
 const WriteMin &write_min_table(long long L, int M)
 {
@@ -167,9 +185,10 @@ const WriteMin &write_min_table(long long L, int M)
         t.C = 1;
         t.W.clear();
         t.K.clear();
+        t.W.shrink_to_fit();
+        t.K.shrink_to_fit();
     }
-    int C = 1;
-    while (C < M && binom(C + 1, 2) < L) ++C;   // columns that hold an entry with beta(c, 2) < l
+    const int C = write_min_columns(L, M);
     if (C <= t.C) return t;
     t.W.resize((size_t)(C + 1) * (L + 1), 0);
     t.K.resize((size_t)(C + 1) * (L + 1), 1);
@@ -186,13 +205,15 @@ const WriteMin &write_min_table(long long L, int M)
 
 // The reversal of nt steps with M slots.  write_min: the write-minimal first advance,
 // for slots of one size (exact copies), where every optimal split peaks at the same
-// memory and fewer writes cost nothing.  Otherwise the smallest optimal first advance,
-// for compressed slots: their streams grow over the run (late states compress worst),
-// and the smallest splits hold the earliest states, so more slots fit a budget.
+// memory and fewer writes cost nothing (unless its table would exceed kWriteMinEntries).
+// Otherwise the smallest optimal first advance, for compressed slots: their streams grow
+// over the run (late states compress worst), and the smallest splits hold the earliest
+// states, so more slots fit a budget.
 void make_schedule(int nt, int M, bool write_min, std::vector<int32_t> &out)
 {
     out.clear();
     const long long L = (long long)nt + 1;
+    write_min = write_min && write_min_fits(L, M);
     // every segment of the recursion has c <= M, and c >= l-1 throughout when M >= L-1
     const WriteMin *tab = (write_min && M >= 2 && M < L - 1) ? &write_min_table(L, M) : nullptr;
     auto split = [&](long long l, int c) -> long long {

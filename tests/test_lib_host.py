@@ -340,3 +340,13 @@ def test_plan_growing_profile_holds_more_slots_than_the_final_state_ratio():
     assert M > worst["slots"]
     with pytest.raises(P.WvError):
         P.plan(N, points, budget, [0.0] * 17)
+
+
+def test_write_min_table_cap_falls_back_to_the_smallest_split():
+    """A reversal whose write-minimal table would exceed 2^26 entries is scheduled with the
+    smallest optimal split, still minimal in forward steps."""
+    import paper_1810_05268_amd as P
+    N, M = 1_000_000, 200
+    a = P.schedule(N, M)
+    assert np.array_equal(a, P.schedule(N, M, False))
+    assert SC.counts(a)["advances"] == SC.p_closed(N + 1, M)
