@@ -40,3 +40,11 @@ def test_full_trajectory_bytes_sums_rounded_streams():
     import bench
     st = {"profile": [1000.0] * 17}
     assert bench.full_trajectory_bytes(st, 10) == 10 * 1024.0
+
+
+def test_raw_gpts_counts_every_stencil_update_over_kernel_time():
+    import bench
+    stats = [{"advances": 8442, "reverses": 3000, "ms_fwd_kernel": 8442 * 0.2, "ms_adj_kernel": 3000 * 0.4}] * 2
+    # 11442 updates of 1e6 points in 2888.4 ms, twice
+    assert bench.raw_gpts(stats, 1_000_000) == pytest.approx(11442e6 / 2.8884 / 1e9, abs=1e-3)
+    assert bench.raw_gpts([{"advances": 1, "reverses": 1, "ms_fwd_kernel": 0.0, "ms_adj_kernel": 0.0}], 10) is None
