@@ -148,6 +148,25 @@ def full_trajectory_bytes(st, nt):
     return float(np.sum(np.ceil(sizes / 256.0) * 256.0))
 
 
+def copy_ceiling_gbs(nbytes=1 << 30, reps=10):
+    """Bytes read plus bytes written per second by a plain device copy of nbytes (torch's
+    copy kernel), timed with events over reps copies: a measured ceiling for streaming
+    kernels on this chip, beside the published 8 TB/s."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
+
+
 def raw_gpts(stats, points):
     """Stencil point updates per second of stencil kernel time over calls timed with
     per-launch events (Gpt/s)."""
@@ -489,6 +508,9 @@ def main():
     # counted HBM bytes (traffic) over the same launch time: the real rate, against the
     # algorithmic rate of "achieved"
     roof["hbm_gbs"] = roof["adjoint_step" if dom == "adjoint" else "forward_step"]["hbm_gbs"]
+    roof["copy_gbs"] = copy_ceiling_gbs()
+    roof["copy_note"] = ("torch's device copy of 1 GiB, read + write bytes per second: a plain streaming "
+                         "reference measured in this process, not a hand-tuned ceiling")
     st = st_comp_ph[0]
     ms_per_store = st["ms_store"] / st["stores"] if st["stores"] else None
     ms_per_decode = st["ms_restore"] / st["decodes"] if st["decodes"] else None
