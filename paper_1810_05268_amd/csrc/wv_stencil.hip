@@ -687,11 +687,11 @@ int grid_for(long long n, int threads)
     return (int)b;
 }
 
-// z chunking: enough workgroups to keep every CU busy, chunks no shorter than 4K planes.
-void choose_chunks(long long tiles, int nz, int K, int target, int &zchunks, int &zlen)
+// z chunking: about `target` workgroups, chunks no shorter than min_len planes.
+void choose_chunks(long long tiles, int nz, int min_len, int target, int &zchunks, int &zlen)
 {
     long long want = target / tiles;
-    long long maxc = nz / (4 * (K > 0 ? K : 1));
+    long long maxc = nz / (min_len > 0 ? min_len : 1);
     if (maxc < 1) maxc = 1;
     if (want > maxc) want = maxc;
     if (want < 1) want = 1;
@@ -730,7 +730,7 @@ hipError_t launch3d(const Grid &g, const float *fin, const float *prev, float *f
     // one resident round of workgroups: z chunks as long as possible (the 2K-plane
     // warm-up of each chunk re-reads the field), but enough of them to fill the GPU
     int zchunks, zlen;
-    choose_chunks((long long)tiles_x * tiles_y, g.nz, K, resident_workgroups(kern), zchunks, zlen);
+    choose_chunks((long long)tiles_x * tiles_y, g.nz, 4 * K, resident_workgroups(kern), zchunks, zlen);
     const int nwg = tiles_x * tiles_y * zchunks;
     launch_timed(kern, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, tiles_x, tiles_y,
                  zchunks, zlen);
@@ -747,9 +747,12 @@ hipError_t launch_k(const Grid &g, const float *fin, const float *prev, float *f
             return launch3d<K, GRAD, true, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
         return launch3d<K, GRAD, false, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
     }
+    // 2-D grids are small (a few MB): a step is bound by the latency of each workgroup's
+    // plane-by-plane march, not by bandwidth, so chunks are short (down to K planes, whose
+    // 2K-plane warm-up loads are issued together) and the workgroups many
     const int tiles_x = (g.nx + 255) / 256;
     int zchunks, zlen;
-    choose_chunks(tiles_x, g.nz, K, 512, zchunks, zlen);
+    choose_chunks(tiles_x, g.nz, K, 2048, zchunks, zlen);
     const int nwg = tiles_x * zchunks;
     launch_timed(stencil2d<K, GRAD, MODE>, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale,
                  tiles_x, zchunks, zlen);
