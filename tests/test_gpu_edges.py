@@ -98,3 +98,21 @@ def test_workspace_contents_do_not_matter(order, tol):
     for a, b in zip(out[0][:3], out[1][:3]):
         assert torch.equal(a, b)
     assert out[0][3] == out[1][3]
+
+
+@pytest.mark.parametrize("n,order,nbl", [((300, 4), 16, 2), ((70, 203), 4, 20), ((520, 61), 8, 20)])
+def test_2d_strip_and_chunk_edges(n, order, nbl):
+    """2-D grids against the oracle where the z chunking is at its edges: a strip shallower
+    than the stencil reach (a single chunk), many chunks of a few planes with a ragged
+    last one, and more than one 256-wide x strip with a ragged last strip."""
+    shot = W.near_anomaly_2d(n=n, nt=60, order=order, nbl=nbl)
+    S, _ = oracle_side(shot)
+    G, _ = gpu_side(shot)
+    ref = S.forward(want_last=True)
+    data, state = G.forward(want_state=True)
+    assert np.any(ref["data"])
+    assert rel_l2(data.cpu().numpy(), ref["data"]) <= 1e-5
+    assert rel_l2(state[0].cpu().numpy(), ref["last"][0]) <= 1e-5
+    e, st, _ = _gradient_case(shot, 6)
+    assert st["advances"] == SC.p_closed(shot.nt + 1, 6)
+    assert e <= 1e-4
