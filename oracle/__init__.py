@@ -75,6 +75,8 @@ def lib():
         L.or_gradient_full.argtypes = [vp, dp, dp, dp, dp]
         L.or_gradient_full.restype = C.c_int
         L.or_gradient_nform.argtypes = [vp, dp, dp, dp]
+        L.or_gradient_bound.argtypes = [vp, dp, dp]
+        L.or_gradient_bound.restype = C.c_int
         L.or_adjoint_src.argtypes = [vp, dp, dp]
         L.or_adjoint_src.restype = C.c_int
         L.or_gradient_actions.argtypes = [vp, dp, C.POINTER(C.c_int32), C.c_long, C.c_int, C.c_double, C.c_int,
@@ -249,6 +251,16 @@ class Solver:
         g = np.zeros(self.P)
         lib().or_gradient_nform(self._h, _dp(np.ascontiguousarray(traj)), _dp(np.ascontiguousarray(lam)), _dp(g))
         return g.reshape(self.shape)
+
+    def gradient_bound(self, residual):
+        """B with |g(u~) - g(u)| <= e B at every point when every forward state the
+        reverse steps read is within e of the exact one (OT2; or_gradient_bound)."""
+        residual = np.ascontiguousarray(residual, dtype=np.float64)
+        b = np.zeros(self.P)
+        rc = lib().or_gradient_bound(self._h, _dp(residual), _dp(b))
+        if rc:
+            raise RuntimeError(f"or_gradient_bound failed: {rc}")
+        return b.reshape(self.shape)
 
     def adjoint_src(self, residual):
         residual = np.ascontiguousarray(residual, dtype=np.float64)

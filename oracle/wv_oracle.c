@@ -475,6 +475,36 @@ void or_gradient_nform(const or_ctx *c, const double *traj, const double *lam_al
     grad_finish(c, grad);
 }
 
+/* Pointwise sensitivity of the gradient to the forward states it reads.  By the
+ * gradient's definition above the adjoint states do not depend on u, so replacing each
+ * u^k by a state within e of it at every point changes g by at most
+ *   e * (1/dt^2) sum_k |(1+a) lam^{k-1} - 2 lam^k + (1-a) lam^{k+1}|
+ * at each point.  Writes that sum, scaled by 1/dt^2 (without e), to bound.  OT2 only
+ * (OR_EINVAL for OT4, whose extra term reads the Laplacian of u^k).                   */
+int or_gradient_bound(const or_ctx *c, const double *residual, double *bound)
+{
+    if (is_ot4(c)) return OR_EINVAL;
+    long P = c->P;
+    int N = c->m.nt;
+    double *l0 = calloc(P, sizeof(double)), *l1 = calloc(P, sizeof(double));
+    double *l2 = calloc(P, sizeof(double)), *lap = malloc(sizeof(double) * P);
+    if (!l0 || !l1 || !l2 || !lap) { free(l0); free(l1); free(l2); free(lap); return OR_ENOMEM; }
+    double *kp1 = l0, *k0 = l1, *km1 = l2;   /* lam^{k+1}, lam^k, lam^{k-1} */
+    memset(bound, 0, sizeof(double) * P);
+    for (int k = N; k >= 1; k--) {
+        or_adjoint_step(c, residual + (long)k * c->nrec, k0, kp1, km1, lap);
+        for (long p = 0; p < P; p++) {
+            double a = c->damp[p];
+            bound[p] += fabs((1.0 + a) * km1[p] - 2.0 * k0[p] + (1.0 - a) * kp1[p]);
+        }
+        double *t = kp1; kp1 = k0; k0 = km1; km1 = t;
+    }
+    double s = 1.0 / (c->m.dt * c->m.dt);
+    for (long p = 0; p < P; p++) bound[p] *= s;
+    free(l0); free(l1); free(l2); free(lap);
+    return OR_OK;
+}
+
 /* Adjoint source: src_adj[n] = S lam^n for n = 0..N-1 (S = source gather),
  * i.e. the derivative of <d, r> with respect to the wavelet sample q^n.    */
 int or_adjoint_src(const or_ctx *c, const double *residual, double *src_adj)

@@ -76,3 +76,26 @@ def test_compressed_gradient_error_falls_with_tolerance():
     print("errors", errs, "bytes", sizes)
     assert errs[0] > errs[1] > errs[2]
     assert sizes[0] < sizes[1] < sizes[2]
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-5])
+def test_compression_only_gradient_within_pointwise_bound(tol):
+    """Every state stored compressed (M = N, no recomputation).  The adjoint states are the
+    same as in the plain run, and each decoded state is within tol of the stored one, so
+    at every point |g_tol - g_plain| <= tol (1/dt^2) sum_k |(1+a) lam^{k-1} - 2 lam^k +
+    (1-a) lam^{k+1}|; the sum comes from the FP64 oracle, with 5 % for the binary32
+    adjoint."""
+    import torch
+    shot = small_3d(nt=100)
+    S, res, _ = _problem(shot)
+    B = S.gradient_bound(res)
+    G, _ = gpu_side(shot)
+    rt = torch.as_tensor(res.astype(np.float32), device="cuda")
+    g_plain, _ = G.gradient(rt, G.slot_bytes * 9)
+    g, st = G.gradient(rt, G.slot_bytes * shot.nt, tol=tol, ratio_hint=1.0)
+    assert st["slots"] == shot.nt and st["advances"] == shot.nt
+    d = (g - g_plain).abs().cpu().numpy()
+    top = float(np.abs(g_plain.cpu().numpy()).max())
+    print(f"tol {tol:g}: worst share of the bound {float(np.max(d / np.maximum(tol * B, 1e-300))):.3f}")
+    assert np.all(d <= 1.05 * tol * B + 1e-9 * top)
+    assert d.max() > 0.0

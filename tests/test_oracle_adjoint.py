@@ -132,3 +132,27 @@ def test_compressed_gradient_error_trend(prob2d):
     # levels and increment representations agree to within the same order
     g_lv, _ = p["S"].gradient_actions(p["res"], acts, 6, tol=1e-5, increment=False)
     assert np.linalg.norm(g_lv - p["g"]) / gref < 10 * errs[2] + 1e-9
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-5])
+def test_compression_only_gradient_within_pointwise_bound(prob2d, tol):
+    """Every state stored compressed (M = N, no recomputation): the adjoint states do not
+    depend on u, so by the gradient's definition
+        |g_tol - g_0| <= e (1/dt^2) sum_k |(1+a) lam^{k-1} - 2 lam^k + (1-a) lam^{k+1}|
+    at every point, with e the largest change of a stored state: the codec's tol plus the
+    rounding of the state to binary32 before encoding.  A reversal that reads the state of
+    the neighbouring step (a planted mistake) breaks the bound."""
+    p = prob2d
+    N = p["spec"].nt
+    g, st = p["S"].gradient_actions(p["res"], SC.schedule(N, N), N, tol=tol, increment=True)
+    assert st["advances"] == N
+    B = p["S"].gradient_bound(p["res"])
+    e = tol + 2.0 ** -24 * np.abs(p["fw"]["traj"]).max()
+    d = np.abs(g - p["g"])
+    assert np.all(d <= e * B * (1.0 + 1e-9))
+    assert d.max() > 0.0
+    # planted mistake: every reverse step reads u^{k-1} instead of u^k
+    traj = p["fw"]["traj"]
+    shifted = np.concatenate([np.zeros_like(traj[:1]), traj[:-1]])
+    wrong = p["S"].gradient_full(shifted, p["res"])
+    assert np.any(np.abs(wrong - p["g"]) > e * B)
