@@ -256,8 +256,17 @@ size_t wv_zfpk_max_bytes(int ndim, const int *dims);
 int wv_zfpk_encode(const float *field, int ndim, const int *dims, double tol, void *out, size_t cap,
                    size_t *nbytes, void *ws, size_t ws_bytes, void *stream);
 
-/* Decode a stream made by wv_zfpk_encode into field (device, same dims). */
-int wv_zfpk_decode(const void *in, int ndim, const int *dims, float *field, void *stream);
+/* Decode a stream made by wv_zfpk_encode into field (device, same dims).
+ *   in      device, nbytes readable bytes holding the stream (8-byte aligned)
+ *   nbytes  readable bytes at `in` (at least the stream's total size)
+ * Before anything is launched the 64-byte header is copied to the host and checked
+ * against the caller's ndim and dims and against nbytes (magic, version, block and
+ * chunk counts, chunk size, data words, total size); any mismatch, a truncated
+ * stream included, returns WV_EINVAL and launches nothing.  Inside the stream every
+ * word the decoder reads is bounds-checked against nbytes, so corrupt chunk offsets
+ * or block lengths decode to wrong values but never read outside [in, in + nbytes).
+ * Synchronises the stream once (the header copy). */
+int wv_zfpk_decode(const void *in, size_t nbytes, int ndim, const int *dims, float *field, void *stream);
 
 /* ------------------------------------------------------------------ serving engine */
 

@@ -130,7 +130,7 @@ def lib():
         L.wv_zfpk_max_bytes.argtypes = [C.c_int, ip]
         L.wv_zfpk_max_bytes.restype = sz
         L.wv_zfpk_encode.argtypes = [vp, C.c_int, ip, C.c_double, vp, sz, C.POINTER(C.c_size_t), vp, sz, vp]
-        L.wv_zfpk_decode.argtypes = [vp, C.c_int, ip, vp, vp]
+        L.wv_zfpk_decode.argtypes = [vp, sz, C.c_int, ip, vp, vp]
         L.wv_schedule.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int32), sz, C.POINTER(C.c_size_t)]
         L.wv_schedule_forward_steps.argtypes = [C.c_int, C.c_int]
         L.wv_schedule_forward_steps.restype = C.c_long
@@ -376,8 +376,12 @@ def zfpk_encode(field, tol: float, out, ws, stream=None) -> int:
     return int(nb.value)
 
 
-def zfpk_decode(stream_buf, field, stream=None) -> None:
+def zfpk_decode(stream_buf, field, nbytes=None, stream=None) -> None:
+    """Decode the stream in the device buffer stream_buf (nbytes readable bytes, default
+    the whole buffer) into the device float32 field."""
     ndim = field.dim()
     dims = list(reversed(field.shape))
-    _check(lib().wv_zfpk_decode(_ptr(stream_buf), ndim, _dims(ndim, dims), _ptr(field), _stream(stream)),
-           "wv_zfpk_decode")
+    if nbytes is None:
+        nbytes = stream_buf.numel() * stream_buf.element_size()
+    _check(lib().wv_zfpk_decode(_ptr(stream_buf), int(nbytes), ndim, _dims(ndim, dims), _ptr(field),
+                                _stream(stream)), "wv_zfpk_decode")

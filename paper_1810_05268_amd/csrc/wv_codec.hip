@@ -195,7 +195,10 @@ struct BitReader {
     long long widx;
     unsigned long long w0, w1;
     int off;
-    __device__ __forceinline__ unsigned long long load(long long i) const { return i < nw ? data[i] : 0ull; }
+    __device__ __forceinline__ unsigned long long load(long long i) const
+    {
+        return (i >= 0 && i < nw) ? data[i] : 0ull;
+    }
     __device__ __forceinline__ void init(long long pos)
     {
         widx = pos >> 6;
@@ -634,7 +637,10 @@ __global__ __launch_bounds__(256) void decode_kernel(DecArgs A)
     // The chunk's words are contiguous: stage them in LDS with one coalesced pass, so
     // that each lane's sequential bit reads are LDS reads instead of a chain of
     // dependent global loads.  Chunks too long for the buffer read global memory.
-    const long long cbase = (long long)chunk_off[c];
+    // a chunk offset outside the data words (only a corrupt stream has one) is clamped,
+    // so that every word read below stays inside the readable range
+    long long cbase = (long long)chunk_off[c];
+    cbase = cbase < 0 ? 0 : (cbase > nwords ? nwords : cbase);
     const long long cw = ((long long)s_scan[255] + 63) / 64 + 1;   // + the reader's look-ahead word
     const bool staged = cw <= kDecLdsWords;
     if (staged) {

@@ -1587,19 +1587,28 @@ size_t wv_zfpk_max_bytes(int ndim, const int *dims)
     return codec_max_bytes(codec_dims(ndim, dims));
 }
 
-int wv_zfpk_encode(const float *field, int ndim, const int *dims, double tol, void *out, size_t cap,
-                   size_t *nbytes, void *ws, size_t ws_bytes, void *stream)
+}  // extern "C"
+
+namespace {
+
+int check_encode_args(const float *field, int ndim, const int *dims, double tol, const void *out,
+                      const size_t *nbytes)
 {
-    hipStream_t s = (hipStream_t)stream;
     if ((ndim != 2 && ndim != 3) || !dims || !field || !out || !nbytes || !(tol > 0) || !std::isfinite(tol))
         return WV_EINVAL;
     for (int a = 0; a < ndim; ++a)
         if (dims[a] < 1) return WV_EINVAL;
     if (((uintptr_t)out) & 7) return WV_EINVAL;
+    return WV_OK;
+}
+
+// One field through the encoder with its bookkeeping and chunk status words at b
+// (wv_zfpk_workspace_bytes of them, 256-byte aligned); b is cleared here by a fill
+// kernel, so it may hold anything on entry.  Synchronises the stream.
+int encode_one(const float *field, int ndim, const int *dims, double tol, void *out, size_t cap, size_t *nbytes,
+               uint8_t *b, hipStream_t s)
+{
     const CodecDims cd = codec_dims(ndim, dims);
-    (void)hipGetLastError();
-    if (!ws || ws_bytes < wv_zfpk_workspace_bytes(ndim, dims) || (((uintptr_t)ws) & 255)) return WV_ENOMEM;
-    uint8_t *b = (uint8_t *)ws;
     unsigned *err = (unsigned *)b;
     uint64_t *base = (uint64_t *)(b + 128);
     uint64_t *next = (uint64_t *)(b + 136);
@@ -1621,14 +1630,49 @@ int wv_zfpk_encode(const float *field, int ndim, const int *dims, double tol, vo
     return WV_OK;
 }
 
-int wv_zfpk_decode(const void *in, int ndim, const int *dims, float *field, void *stream)
+}  // namespace
+
+extern "C" {
+
+int wv_zfpk_encode(const float *field, int ndim, const int *dims, double tol, void *out, size_t cap,
+                   size_t *nbytes, void *ws, size_t ws_bytes, void *stream)
 {
-    if ((ndim != 2 && ndim != 3) || !dims || !in || !field) return WV_EINVAL;
+    int rc = check_encode_args(field, ndim, dims, tol, out, nbytes);
+    if (rc) return rc;
+    (void)hipGetLastError();
+    if (!ws || ws_bytes < wv_zfpk_workspace_bytes(ndim, dims) || (((uintptr_t)ws) & 255)) return WV_ENOMEM;
+    return encode_one(field, ndim, dims, tol, out, cap, nbytes, (uint8_t *)ws, (hipStream_t)stream);
+}
+
+int wv_zfpk_decode(const void *in, size_t nbytes, int ndim, const int *dims, float *field, void *stream)
+{
+    if ((ndim != 2 && ndim != 3) || !dims || !in || !field || (((uintptr_t)in) & 7)) return WV_EINVAL;
     for (int a = 0; a < ndim; ++a)
         if (dims[a] < 1) return WV_EINVAL;
     const CodecDims cd = codec_dims(ndim, dims);
+    if (nbytes < (size_t)cd.prefix_bytes) return WV_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
     (void)hipGetLastError();
-    HIPCHK(launch_decode(cd, (const uint8_t *)in, nullptr, ~0ull, field, nullptr, (hipStream_t)stream));
+    // the header must describe exactly this field and fit the readable bytes
+    uint8_t h[64];
+    HIPCHK(hipMemcpyAsync(h, in, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    uint32_t h32[12];
+    uint64_t data_words = 0, total = 0;
+    double tol = 0.0;
+    std::memcpy(h32, h, sizeof(h32));
+    std::memcpy(&tol, h + 24, 8);
+    std::memcpy(&data_words, h + 48, 8);
+    std::memcpy(&total, h + 56, 8);
+    const int want[3] = {cd.dims[0], cd.dims[1], cd.dims[2]};
+    bool ok = h32[0] == 0x4B50465Au && h32[1] == 1u && h32[2] == (uint32_t)ndim;
+    for (int a = 0; a < 3; ++a) ok = ok && h32[3 + a] == (uint32_t)want[a];
+    ok = ok && h32[8] == (uint32_t)cd.nblocks && h32[9] == (uint32_t)cd.nchunks &&
+         h32[10] == (uint32_t)kBlocksPerChunk && tol > 0 && std::isfinite(tol);
+    ok = ok && data_words <= (uint64_t)(nbytes - (size_t)cd.prefix_bytes) / 8 &&
+         total == (uint64_t)cd.prefix_bytes + 8 * data_words && total <= (uint64_t)nbytes;
+    if (!ok) return WV_EINVAL;
+    HIPCHK(launch_decode(cd, (const uint8_t *)in, nullptr, (uint64_t)total, field, nullptr, s));
     return WV_OK;
 }
 

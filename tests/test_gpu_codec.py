@@ -67,3 +67,39 @@ def test_many_chunks_wavefield_like():
         got, dec = gpu_roundtrip(f, tol)
         assert got == ref
         assert np.max(np.abs(dec - f)) <= tol
+
+
+def test_decode_rejects_mismatched_or_truncated_streams():
+    """The decoder checks the stream header against the caller's dims and readable
+    bytes on the host and launches nothing on a mismatch; a valid stream decodes
+    exactly when nbytes covers it."""
+    import torch
+    import paper_1810_05268_amd as P
+    from paper_1810_05268_amd._binding import WV_EINVAL, WvError
+    rng = np.random.default_rng(7)
+    field = rng.standard_normal((20, 24, 28)).astype(np.float32)
+    ref = oracle.encode(field, 1e-3)
+    buf = torch.as_tensor(np.frombuffer(ref, dtype=np.uint8).copy(), device="cuda")
+    dec = torch.full(field.shape, 7.0, dtype=torch.float32, device="cuda")
+    P.zfpk_decode(buf, dec, nbytes=len(ref))
+    assert np.array_equal(dec.cpu().numpy().view(np.uint32), oracle.decode(ref).view(np.uint32))
+    cases = []
+    # other dims, other ndim, a stream cut one word short, a stream cut inside its prefix
+    cases.append((torch.empty((20, 24, 29), dtype=torch.float32, device="cuda"), len(ref)))
+    cases.append((torch.empty((20, 24 * 28), dtype=torch.float32, device="cuda"), len(ref)))
+    cases.append((torch.empty(field.shape, dtype=torch.float32, device="cuda"), len(ref) - 8))
+    cases.append((torch.empty(field.shape, dtype=torch.float32, device="cuda"), 100))
+    for out, nb in cases:
+        out.fill_(3.0)
+        with pytest.raises(WvError) as ei:
+            P.zfpk_decode(buf, out, nbytes=nb)
+        assert ei.value.code == WV_EINVAL
+        torch.cuda.synchronize()
+        assert bool(torch.all(out == 3.0))     # nothing was launched
+    # a corrupt magic word
+    bad = buf.clone()
+    bad[0] ^= 1
+    out = torch.full(field.shape, 3.0, dtype=torch.float32, device="cuda")
+    with pytest.raises(WvError):
+        P.zfpk_decode(bad, out, nbytes=len(ref))
+    assert bool(torch.all(out == 3.0))

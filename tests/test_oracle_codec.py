@@ -64,6 +64,25 @@ def test_sequency_order(ndim):
     assert key == sorted(key) and perm[0] == 0
 
 
+def test_sequency_order_all_three_keys_2d():
+    """The whole 2-D order, worked out by hand (v = i + 4 j): total degree i + j first,
+    then i^2 + j^2 ((1,1) before (2,0) and (0,2)), then the slower index j, then i."""
+    expect = [0, 1, 4, 5, 2, 8, 6, 9, 3, 12, 10, 7, 13, 11, 14, 15]
+    assert oracle.sequency_perm(2).tolist() == expect
+
+
+def test_sequency_order_all_three_keys_3d():
+    """The 3-D order at its head and tail, worked out by hand (v = i + 4 j + 16 k).
+    Degree 1: (1,0,0), (0,1,0), (0,0,1).  Degree 2: squares 2 before 4, and within each
+    the slowest index k, then j: (1,1,0), (1,0,1), (0,1,1), (2,0,0), (0,2,0), (0,0,2).
+    Degree 3: (1,1,1) (square 3) first; then the six of square 5 by (k, j):
+    (2,1,0), (1,2,0), (2,0,1), (0,2,1), (1,0,2), (0,1,2); then (3,0,0), (0,3,0), (0,0,3).
+    Degree 8 (all of square 22): (3,3,2), (3,2,3), (2,3,3); then (3,3,3)."""
+    perm = oracle.sequency_perm(3).tolist()
+    assert perm[:20] == [0, 1, 4, 16, 5, 17, 20, 2, 8, 32, 21, 6, 9, 18, 24, 33, 36, 3, 12, 48]
+    assert perm[-4:] == [47, 59, 62, 63]
+
+
 # ---------------------------------------------------------------- error bound on blocks
 
 def family_block(kind, rng, S):
