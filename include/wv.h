@@ -256,6 +256,20 @@ size_t wv_zfpk_max_bytes(int ndim, const int *dims);
 int wv_zfpk_encode(const float *field, int ndim, const int *dims, double tol, void *out, size_t cap,
                    size_t *nbytes, void *ws, size_t ws_bytes, void *stream);
 
+/* wv_zfpk_encode for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same encoder and
+ * the same stream, with no workspace argument.  Its scratch (bookkeeping and chunk
+ * status words) is a fixed 128 KiB array in device memory that each GPU the library
+ * runs on holds until the process ends; the call allocates and frees nothing and
+ * clears the scratch it uses with a fill kernel (no memset).  Limit: fields of at
+ * most 4,177,920 blocks (wv_zfpk_workspace_bytes <= 131072, e.g. 3-D fields up to
+ * 640^3 values); a larger field returns WV_ENOMEM (wv_last_error says why) and
+ * launches nothing.  Every call on one GPU shares that GPU's array, so calls that
+ * overlap on one GPU (concurrent streams or threads) race: run them one at a time.
+ * Arguments, output, errors and synchronisation as wv_zfpk_encode. */
+int wv_zfpk_encode_noalloc(const float *field, int ndim, const int *dims, double tol, void *out, size_t cap,
+                           size_t *nbytes, void *stream);
+
 /* Decode a stream made by wv_zfpk_encode into field (device, same dims).
  *   in      device, nbytes readable bytes holding the stream (8-byte aligned)
  *   nbytes  readable bytes at `in` (at least the stream's total size)

@@ -11,11 +11,11 @@ this package only marshals arguments to it:
 """
 from ._binding import (OP_FORWARD, OP_GRADIENT, Problem, WvError, adjoint_src, cfl_dt, forward, gradient,  # noqa
                        choose, costs_from_stats, lib, misfit_gradient, pad_velocity, plan, predict, schedule,
-                       schedule_forward_steps, velocity_gradient, zfpk_decode, zfpk_encode, zfpk_max_bytes,
-                       zfpk_workspace_bytes)
+                       schedule_forward_steps, velocity_gradient, zfpk_decode, zfpk_encode, zfpk_encode_noalloc,
+                       zfpk_max_bytes, zfpk_workspace_bytes)
 
 __all__ = ["OP_FORWARD", "OP_GRADIENT", "Problem", "WvError", "adjoint_src", "cfl_dt", "choose", "costs_from_stats",
            "forward",
            "gradient", "lib", "misfit_gradient", "pad_velocity", "plan", "predict", "schedule", "schedule_forward_steps",
            "velocity_gradient",
-           "zfpk_decode", "zfpk_encode", "zfpk_max_bytes", "zfpk_workspace_bytes"]
+           "zfpk_decode", "zfpk_encode", "zfpk_encode_noalloc", "zfpk_max_bytes", "zfpk_workspace_bytes"]

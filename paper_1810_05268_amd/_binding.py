@@ -92,7 +92,7 @@ class WvResult(C.Structure):
 # every symbol include/wv.h declares
 SYMBOLS = ["wv_cfl_dt", "wv_cfl_dt_to", "wv_workspace_bytes", "wv_field_elements", "wv_forward", "wv_gradient", "wv_misfit_gradient", "wv_adjoint_src",
            "wv_pad_velocity", "wv_velocity_gradient", "wv_zfpk_workspace_bytes", "wv_zfpk_max_bytes",
-           "wv_zfpk_encode", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_predict", "wv_choose", "wv_plan", "wv_compressibility", "wv_strerror",
+           "wv_zfpk_encode", "wv_zfpk_encode_noalloc", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_predict", "wv_choose", "wv_plan", "wv_compressibility", "wv_strerror",
            "wv_last_error", "wv_version", "wv_engine_create", "wv_engine_submit", "wv_engine_wait",
            "wv_engine_pending", "wv_engine_destroy"]
 
@@ -130,6 +130,7 @@ def lib():
         L.wv_zfpk_max_bytes.argtypes = [C.c_int, ip]
         L.wv_zfpk_max_bytes.restype = sz
         L.wv_zfpk_encode.argtypes = [vp, C.c_int, ip, C.c_double, vp, sz, C.POINTER(C.c_size_t), vp, sz, vp]
+        L.wv_zfpk_encode_noalloc.argtypes = [vp, C.c_int, ip, C.c_double, vp, sz, C.POINTER(C.c_size_t), vp]
         L.wv_zfpk_decode.argtypes = [vp, sz, C.c_int, ip, vp, vp]
         L.wv_schedule.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int32), sz, C.POINTER(C.c_size_t)]
         L.wv_schedule_forward_steps.argtypes = [C.c_int, C.c_int]
@@ -373,6 +374,17 @@ def zfpk_encode(field, tol: float, out, ws, stream=None) -> int:
     _check(lib().wv_zfpk_encode(_ptr(field), ndim, _dims(ndim, dims), float(tol), _ptr(out),
                                 out.numel() * out.element_size(), C.byref(nb), _ptr(ws),
                                 ws.numel() * ws.element_size(), _stream(stream)), "wv_zfpk_encode")
+    return int(nb.value)
+
+
+def zfpk_encode_noalloc(field, tol: float, out, stream=None) -> int:
+    """As zfpk_encode, with the library's fixed device scratch instead of a workspace."""
+    ndim = field.dim()
+    dims = list(reversed(field.shape))
+    nb = C.c_size_t(0)
+    _check(lib().wv_zfpk_encode_noalloc(_ptr(field), ndim, _dims(ndim, dims), float(tol), _ptr(out),
+                                        out.numel() * out.element_size(), C.byref(nb), _stream(stream)),
+           "wv_zfpk_encode_noalloc")
     return int(nb.value)
 
 

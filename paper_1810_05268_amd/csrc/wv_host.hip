@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "wv_internal.h"
@@ -1630,9 +1631,55 @@ int encode_one(const float *field, int ndim, const int *dims, double tol, void *
     return WV_OK;
 }
 
+// Scratch of wv_zfpk_encode_noalloc: the encoder's bookkeeping words and chunk status
+// words in one file-scope device array.  Every GPU the library runs on holds its own
+// copy until the process ends.  In host code the array's name is only a stand-in, so
+// host code never passes it: the device address comes from hipGetSymbolAddress, taken
+// once per device with that device current, and kept in g_scratch_dev.
+constexpr size_t kNoAllocScratchBytes = 128 * 1024;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+int noalloc_scratch(uint8_t **out)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return WV_EINVAL;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return WV_EHIP;
+        g_scratch_dev[dev] = p;
+    }
+    *out = (uint8_t *)g_scratch_dev[dev];
+    return WV_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int wv_zfpk_encode_noalloc(const float *field, int ndim, const int *dims, double tol, void *out, size_t cap,
+                           size_t *nbytes, void *stream)
+{
+    int rc = check_encode_args(field, ndim, dims, tol, out, nbytes);
+    if (rc) return rc;
+    (void)hipGetLastError();
+    if (wv_zfpk_workspace_bytes(ndim, dims) > kNoAllocScratchBytes) {
+        std::snprintf(g_detail, sizeof(g_detail),
+                      "wv_zfpk_encode_noalloc: %zu bytes of scratch needed, %zu available (at most %zu blocks)",
+                      wv_zfpk_workspace_bytes(ndim, dims), kNoAllocScratchBytes,
+                      (kNoAllocScratchBytes - kCodecBk) / 8 * (size_t)kBlocksPerChunk);
+        return WV_ENOMEM;
+    }
+    uint8_t *b = nullptr;
+    if ((rc = noalloc_scratch(&b))) return rc;
+    return encode_one(field, ndim, dims, tol, out, cap, nbytes, b, (hipStream_t)stream);
+}
 
 int wv_zfpk_encode(const float *field, int ndim, const int *dims, double tol, void *out, size_t cap,
                    size_t *nbytes, void *ws, size_t ws_bytes, void *stream)
