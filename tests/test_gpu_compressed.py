@@ -4,9 +4,9 @@ Both sides run the same Revolve schedule (same N and M) with every stored state
 (u^k, d^k = u^k - u^{k-1}) passed through the codec at the same absolute tolerance.
 Their quantisation decisions are taken on slightly different inputs (binary32
 vs binary64 wavefields), so the two compressed gradients are not bitwise equal;
-the bound is the oracle's own compression error at that tolerance (the measured
-constant C of ||g_tol - g_0|| <= C tol), doubled, plus the uncompressed binary32
-tolerance."""
+what is compared is the codec's share of each: the change compression makes to the
+gradient on the GPU against the change it makes in the FP64 oracle on the same
+schedule, with an allowance of twice the binary32 floor of the plain run."""
 import numpy as np
 import pytest
 
@@ -28,36 +28,81 @@ def _problem(shot):
     return S, res, g0
 
 
+def check_codec_parity(tag, g_tol, g_plain, g_or_tol, g0):
+    """The codec's share of a compressed GPU gradient against the oracle's.
+
+    e_or    = ||g_or,tol - g0|| / ||g0||: what compression changes in the FP64 oracle
+              on the same schedule (the quantity under test);
+    d_gpu   = ||g_gpu,tol - g_gpu,plain|| / ||g0||: what it changes on the GPU;
+    e_plain = ||g_gpu,plain - g0|| / ||g0||: the binary32 floor of the plain run.
+    The GPU's change must be the oracle's within a factor of 3 either way, with an
+    additive allowance of twice the binary32 floor (the two sides quantise binary32 and
+    binary64 wavefields, so a few coefficients round differently); and the GPU's
+    compressed gradient must sit closer to the oracle's compressed gradient than the
+    codec's own change plus that floor, i.e. both sides dropped the same bits."""
+    e_or = rel_l2(g_or_tol, g0)
+    d_gpu = rel_l2(g_tol, g_plain) * float(np.linalg.norm(g_plain) / np.linalg.norm(g0))
+    e_plain = rel_l2(g_plain, g0)
+    e_pair = rel_l2(g_tol, g_or_tol)
+    print(f"{tag}: oracle codec change {e_or:.3e}  GPU codec change {d_gpu:.3e}  (ratio {d_gpu / e_or:.3f})"
+          f"  GPU plain floor {e_plain:.3e}  GPU vs oracle compressed {e_pair:.3e}")
+    assert e_plain <= GRAD_TOL
+    assert d_gpu <= 3.0 * e_or + 2.0 * e_plain
+    assert d_gpu >= e_or / 3.0 - 2.0 * e_plain
+    assert e_pair <= 0.5 * e_or + 2.0 * e_plain
+    return e_or, d_gpu, e_plain, e_pair
+
+
 @pytest.mark.parametrize("case", ["2d", "3d"])
-@pytest.mark.parametrize("tol", [1e-4, 1e-6])
+@pytest.mark.parametrize("tol", [1e-3, 1e-4, 1e-6])
 def test_compressed_gradient_within_codec_bound(case, tol):
+    """Compressed checkpoints with recomputation (M = 8 slots): the codec's effect on the
+    gradient matches the oracle's compressed reversal on the same schedule."""
     import torch
     shot = W.near_anomaly_2d() if case == "2d" else small_3d(nt=100)
     M = 8
     S, res, g0 = _problem(shot)
     acts = SC.schedule(shot.nt, M)
     g_or, st_or = S.gradient_actions(res, acts, M, tol=tol, increment=True)
-    e_or = rel_l2(g_or, g0)
     G, _ = gpu_side(shot)
     rt = torch.as_tensor(res.astype(np.float32), device="cuda")
     # ratio hint 1 and a budget of M-1 raw states plus 5 % (room for the per-stream
     # prefix the planner adds to a compressed slot): the schedule has exactly M slots
     budget = int(8 * G.P * (M - 1) * 1.05)
     g, st = G.gradient(rt, budget, tol=tol, ratio_hint=1.0)
-    e_gpu = rel_l2(g.cpu().numpy(), g0)
     g_plain, _ = G.gradient(rt, G.slot_bytes * (M - 1))
-    e_plain = rel_l2(g_plain.cpu().numpy(), g0)
-    print(f"{case} tol {tol:g}: oracle compressed {e_or:.3e}  GPU compressed {e_gpu:.3e}  GPU plain {e_plain:.3e}"
-          f"  ratio {st['ratio']:.1f}")
     assert st["slots"] == M
     assert st["advances"] == st_or["advances"] == SC.p_closed(shot.nt + 1, M)
     assert st["stores"] == st_or["stores"]
     assert st["reverses"] == shot.nt
     assert st["ratio"] > 1.0
-    assert e_plain <= GRAD_TOL
-    assert e_gpu <= 2.0 * e_or + GRAD_TOL
-    # against the GPU's own uncompressed gradient on the same schedule
-    assert rel_l2(g.cpu().numpy(), g_plain.cpu().numpy()) <= 2.0 * e_or + GRAD_TOL
+    check_codec_parity(f"{case} tol {tol:g} ratio {st['ratio']:.1f}", g.cpu().numpy(), g_plain.cpu().numpy(),
+                       g_or, g0)
+
+
+def test_arena_overflow_replans_and_equals_a_direct_plan():
+    """A ratio hint far too optimistic makes every slot count the planner tries overflow
+    the arena: the call re-plans with half the ratio (the last time at the uncompressed
+    size) and reports the repeats; its gradient equals, bit for bit, a call planned at the
+    final ratio from the start."""
+    import torch
+    shot = small_3d(nt=100)
+    S, res, g0 = _problem(shot)
+    G, _ = gpu_side(shot)
+    rt = torch.as_tensor(res.astype(np.float32), device="cuda")
+    # a third of one raw state: a hint of 1e6 plans every state (M = N), whose streams
+    # (about 0.9 MB here) cannot fit; half of that hint plans the same; the last re-plan
+    # takes the uncompressed size, M = 1 (recomputation from x_0 alone)
+    budget = int(8 * G.P * 0.3)
+    g1, st1 = G.gradient(rt, budget, tol=1e-4, ratio_hint=1e6)
+    print("forced overflow:", {k: st1[k] for k in ("retries", "slots", "ratio_planned", "peak_bytes")})
+    assert st1["retries"] >= 1
+    assert st1["peak_bytes"] <= budget
+    g2, st2 = G.gradient(rt, budget, tol=1e-4, ratio_hint=st1["ratio_planned"])
+    assert st2["retries"] == 0 and st2["slots"] == st1["slots"]
+    assert st2["advances"] == st1["advances"] and st2["stores"] == st1["stores"]
+    assert torch.equal(g1, g2)
+    assert rel_l2(g1.cpu().numpy(), g0) <= 1e-3
 
 
 def test_compressed_gradient_error_falls_with_tolerance():

@@ -72,17 +72,23 @@ def test_fault_body_full_field_codec_byte_identical():
 
 
 def test_layered_noise_full_size_forward_and_revolve():
-    """168^3 padded points, order 8, 1000 steps: data against the oracle; the
-    20-slot Revolve gradient (t = 2750) against the oracle's on the same schedule."""
+    """168^3 padded points, order 8, 1000 steps: data and the final wavefield pair
+    (u^N, u^(N-1)) against the oracle; the 20-slot Revolve gradient (t = 2750) against
+    the oracle's on the same schedule."""
     import torch
     shot = W.layered_noise_3d()
     S, _ = oracle_side(shot)
     St, _ = oracle_side(shot, "true")
-    ref = S.forward()
+    ref = S.forward(want_last=True)
     d_obs = St.forward()["data"]
     G, _ = gpu_side(shot)
-    data = G.forward()
+    data, state = G.forward(want_state=True)
     e_d = rel_l2(data.cpu().numpy(), ref["data"])
+    e_u = rel_l2(state[0].cpu().numpy(), ref["last"][0])
+    e_p = rel_l2(state[1].cpu().numpy(), ref["last"][1])
+    print(f"168^3 final state: u^N {e_u:.2e} u^(N-1) {e_p:.2e}")
+    assert e_u <= WAVEFIELD_TOL and e_p <= WAVEFIELD_TOL
+    del state
     res = ref["data"] - d_obs
     M = 21                  # 20 stored checkpoints plus the initial (zero) state
     acts = SC.schedule(shot.nt, M, write_min=True)
@@ -158,3 +164,84 @@ def test_fault_body_ot4_all_3000_steps_properties():
     assert pa == pb == pc
     assert sc["retries"] == 0 and sc["peak_bytes"] <= 16e9
     assert e <= 10 * 1e-4
+
+
+@pytest.mark.parametrize("cls,nt,M", [(0, 300, 8), (1, 60, 6), (2, 20, 5)], ids=["2d_512", "3d_160", "3d_256"])
+def test_serving_class_sizes_bounded_steps(cls, nt, M):
+    """Each request class of the serving stream at its own grid size and space order
+    (2-D 512^2 order 8; 3-D 160^3 order 8; 3-D 256^3 order 12; 10 m, 20-cell layer, a
+    layered random velocity as the stream draws it), for a bounded number of steps the
+    oracle finishes in seconds: data and the final wavefield pair against the oracle; an
+    uncompressed Revolve gradient with M slots for a seeded residual against the oracle's
+    on the same schedule; and the tol 1e-4 compressed gradient on the same slot count
+    against the oracle's compressed reversal (check_codec_parity)."""
+    import torch
+    from tests.test_gpu_compressed import check_codec_parity
+    _, nd, n, order, _ = W.SERVING_CLASSES[cls]
+    rng = np.random.default_rng(50 + cls)
+    shot = W.random_layers(n, (10.0,) * nd, 20, order, nt, rng, float(rng.uniform(10.0, 20.0)))
+    S, _ = oracle_side(shot)
+    ref = S.forward(want_last=True)
+    # a seeded residual (over so few steps the wave has not reached the anomaly that
+    # makes the observed data differ, so d_sim - d_obs would be zero)
+    res = np.random.default_rng(60 + cls).standard_normal(ref["data"].shape) * 1e-3
+    res[0] = 0.0
+    G, _ = gpu_side(shot)
+    data, state = G.forward(want_state=True)
+    e_d = rel_l2(data.cpu().numpy(), ref["data"])
+    e_u = rel_l2(state[0].cpu().numpy(), ref["last"][0])
+    e_p = rel_l2(state[1].cpu().numpy(), ref["last"][1])
+    del state, ref
+    acts = SC.schedule(nt, M, write_min=True)
+    g_or, st_or = S.gradient_actions(res, acts, M)
+    rt = torch.as_tensor(res.astype(np.float32), device="cuda")
+    g, st = G.gradient(rt, G.slot_bytes * (M - 1))
+    e_g = rel_l2(g.cpu().numpy(), g_or)
+    print(f"class {cls} {n} order {order} {nt} steps: data {e_d:.2e} u^N {e_u:.2e} u^(N-1) {e_p:.2e} "
+          f"gradient {e_g:.2e}")
+    assert e_d <= WAVEFIELD_TOL and e_u <= WAVEFIELD_TOL and e_p <= WAVEFIELD_TOL
+    assert st["slots"] == M and st["advances"] == st_or["advances"] == SC.p_closed(nt + 1, M)
+    assert e_g <= GRAD_TOL
+    acts = SC.schedule(nt, M)
+    g_ot, _ = S.gradient_actions(res, acts, M, tol=1e-4, increment=True)
+    gc, stc = G.gradient(rt, int(8 * G.P * (M - 1) * 1.05), tol=1e-4, ratio_hint=1.0)
+    assert stc["slots"] == M
+    check_codec_parity(f"class {cls} tol 1e-4", gc.cpu().numpy(), g.cpu().numpy(), g_ot, g_or)
+
+
+def test_fault_body_3000_steps_long_run_drift():
+    """The large shot's forward problem over all 3000 steps on the full 400^3 grid, in the
+    launch configuration the benchmark times, against the FP64 oracle's run of the same
+    problem stored by tests/golden/make_fault_body_3000.py: the binary32 leapfrog's
+    rounding accumulates over the steps, so this is where the wavefield tolerance (1e-5
+    rel-L2) is tightest.  Compared: u^3000 and u^2999 on the stored subgrid (every 10th
+    point per axis), the 2-norms of the full fields and of all data, and 36 receiver
+    traces over all 3001 samples."""
+    import os
+    gold = os.path.join(os.path.dirname(__file__), "golden", "fault_body_3000.npz")
+    if not os.path.exists(gold):
+        pytest.skip("golden file missing: run tests/golden/make_fault_body_3000.py")
+    ref = np.load(gold)
+    shot = W.fault_body_3d()
+    G, dt = gpu_side(shot)
+    assert dt == float(ref["dt"])
+    data, state = G.forward(want_state=True)
+    sub = int(ref["sub"])
+    u = state[0][::sub, ::sub, ::sub].double().cpu().numpy()
+    up = state[1][::sub, ::sub, ::sub].double().cpu().numpy()
+    nu = float(state[0].double().norm())
+    nup = float(state[1].double().norm())
+    nd = float(data.double().norm())
+    import torch
+    dsub = data[:, torch.as_tensor(ref["rec_idx"], device=data.device)].double().cpu().numpy()
+    del state, data
+    e_u = rel_l2(u, ref["u_sub"])
+    e_up = rel_l2(up, ref["up_sub"])
+    e_d = rel_l2(dsub, ref["data_sub"])
+    r_u = abs(nu / float(ref["u_norm"]) - 1.0)
+    r_up = abs(nup / float(ref["up_norm"]) - 1.0)
+    r_d = abs(nd / float(ref["data_norm"]) - 1.0)
+    print(f"3000 steps: u^N sub {e_u:.2e} u^(N-1) sub {e_up:.2e} traces {e_d:.2e}; norms {r_u:.1e} {r_up:.1e} "
+          f"{r_d:.1e}")
+    assert max(e_u, e_up, e_d) <= WAVEFIELD_TOL
+    assert max(r_u, r_up, r_d) <= WAVEFIELD_TOL

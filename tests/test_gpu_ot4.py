@@ -6,6 +6,7 @@ import pytest
 
 import workloads as W
 from oracle import schedule as SC
+from tests.test_gpu_compressed import check_codec_parity
 from tests.helpers import gpu_side, has_gpu, oracle_side, rel_l2, small_3d
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not has_gpu(), reason="needs a GPU")]
@@ -82,11 +83,11 @@ def test_revolve_bit_identical_and_compressed():
         g, st = G.gradient(rt, G.slot_bytes * (M - 1))
         assert st["advances"] == SC.p_closed(shot.nt + 1, M)
         assert torch.equal(g, full), M
-    M, tol = 8, 1e-5
-    acts = SC.schedule(shot.nt, M)
-    g_or, _ = S.gradient_actions(res, acts, M, tol=tol, increment=True)
-    e_or = rel_l2(g_or, gref)
-    g, st = G.gradient(rt, int(8 * G.P * (M - 1) * 1.05), tol=tol, ratio_hint=1.0)
-    e = rel_l2(g.cpu().numpy(), gref)
-    print(f"OT4 compressed: oracle {e_or:.2e} GPU {e:.2e}")
-    assert st["slots"] == M and e <= 2.0 * e_or + GRAD_TOL
+    M = 8
+    g_plain, _ = G.gradient(rt, G.slot_bytes * (M - 1))
+    for tol in (1e-3, 1e-5):
+        acts = SC.schedule(shot.nt, M)
+        g_or, _ = S.gradient_actions(res, acts, M, tol=tol, increment=True)
+        g, st = G.gradient(rt, int(8 * G.P * (M - 1) * 1.05), tol=tol, ratio_hint=1.0)
+        assert st["slots"] == M
+        check_codec_parity(f"OT4 tol {tol:g}", g.cpu().numpy(), g_plain.cpu().numpy(), g_or, gref)
