@@ -46,7 +46,17 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FWD_BYTES_PER_POINT = 16.0     # read u^n, u^{n-1}, w; write u^{n+1}
 ADJ_BYTES_PER_POINT = 36.0     # read lam^k, lam^{k+1}, w, u^k; write lam^{k-1}; read + write the FP64 gradient
 COUNTERS = os.path.join(ROOT, "profiles", "stencil3d_fault_body_3d_counters.txt")
-STENCIL_SRC = os.path.join(ROOT, "paper_1810_05268_amd", "csrc", "wv_stencil.hip")
+STENCIL_SRC = [os.path.join(ROOT, "paper_1810_05268_amd", "csrc", f) for f in ("wv_stencil.hip", "wv_stencil_dev.h")]
+
+
+def stencil_source_sha256() -> str:
+    """sha256 of the stencil kernels' sources (the kernel file, then its device header)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in STENCIL_SRC:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 # wv_stats.timing bits: 1 = HIP events around every schedule action (per-phase device
@@ -148,23 +158,18 @@ def full_trajectory_bytes(st, nt):
     return float(np.sum(np.ceil(sizes / 256.0) * 256.0))
 
 
-def copy_ceiling_gbs(nbytes=1 << 30, reps=10):
-    """Bytes read plus bytes written per second by a plain device copy of nbytes (torch's
-    copy kernel), timed with events over reps copies: a measured ceiling for streaming
-    kernels on this chip, beside the published 8 TB/s."""
+def stream_ceilings(stream_bytes=256 * 1000 * 1000, reps=10):
+    """Measured HBM ceilings in this process (wv_stream_ceiling): nontemporal streams of
+    3 reads + 1 write (the forward stencil's mix) and 4 reads + 1 write, 256 MB each (the
+    large grid's field size), GB/s of bytes read plus written; the best of reps."""
     import torch
-    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    b.copy_(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    del a, b
-    return round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
+    import paper_1810_05268_amd as P
+    ws = torch.empty(5 * stream_bytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    out = {f"{r}r1w_gbs": round(P.stream_ceiling(r, stream_bytes, ws[off:], reps), 1) for r in (3, 4)}
+    del ws
+    torch.cuda.empty_cache()
+    return out
 
 
 def raw_gpts(stats, points):
@@ -212,7 +217,6 @@ def traffic_per_launch():
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each
     scaled by what the counter reads for a plain copy of known size), or None when
     the stencil source has changed since the counters were taken."""
-    import hashlib
     if not os.path.exists(COUNTERS):
         return None
     kv = {}
@@ -220,9 +224,7 @@ def traffic_per_launch():
         if ":" in line and not line.lstrip().startswith(("#", "|", "`")):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    with open(STENCIL_SRC, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if kv.get("stencil_source_sha256") != sha:
+    if kv.get("stencil_source_sha256") != stencil_source_sha256():
         return None
     ff, wf = float(kv["fetch_scale"]), float(kv["write_scale"])
     out = {}
@@ -265,11 +267,18 @@ def kernels_mode():
 PROFILED_PER_CLASS = 3
 
 
-def serving_leg(nreq, rate, pool_bytes, max_active, tol, cap):
-    """The serving stream: seeded Poisson arrivals of mixed shots through the engine.
-    Untimed calls measure the compressibility profiles of each class's first requests;
-    every request of the class then gets a checkpoint budget of 1.5 x the compressed full
-    trajectory of their elementwise maximum (capped) and the plan for it as the hint."""
+SERVING_VMAX = 3700.0   # m/s: bound of every serving model (layers up to 3.5 km/s plus the 0.2 km/s anomaly)
+
+
+def serving_leg(nreq, rate, pool_bytes, max_active, tol, cap, max_batch, saturation):
+    """The serving stream: seeded Poisson arrivals of mixed shots through the engine, 2-D
+    shots batched (one persistent launch per batch).  Untimed calls measure the
+    compressibility profiles of each class's first requests; every request of the class
+    then gets a checkpoint budget of 1.5 x the compressed full trajectory of their
+    elementwise maximum (capped) and the plan for it as the hint.  All shots take their
+    time step from one velocity bound, so a class shares dt and can share a batch.
+    Then the saturation runs: the first half of the stream replayed at multiples of the
+    rate, until the engine's throughput stops growing (queueing dominates)."""
     import numpy as np
     import torch
 
@@ -281,9 +290,10 @@ def serving_leg(nreq, rate, pool_bytes, max_active, tol, cap):
     items, hints, budgets, profs, cls = [], {}, {}, {}, []
     for i, r in enumerate(reqs):
         s = r.shot
-        dt = s.cfl_frac * P.cfl_dt(s.ndim, s.h, s.order, s.vmax)
+        dt = s.cfl_frac * P.cfl_dt(s.ndim, s.h, s.order, SERVING_VMAX)
         q = W.ricker(s.f0, dt, s.nt).astype(np.float32)
-        G = DeviceShot(s.ndim, s.n, s.h, s.nbl, s.order, s.nt, dt, s.vmax, s.padded("true"), q, s.src, s.rec)
+        G = DeviceShot(s.ndim, s.n, s.h, s.nbl, s.order, s.nt, dt, SERVING_VMAX, s.padded("true"), q, s.src,
+                       s.rec)
         d_obs = G.forward()
         G.set_velocity(s.padded("vel"))
         c = s.extra["class"]
@@ -308,10 +318,12 @@ def serving_leg(nreq, rate, pool_bytes, max_active, tol, cap):
         it[3], it[5] = budgets[c], hints[c]
     items = [tuple(it) for it in items]
     torch.cuda.synchronize()
-    eng = Engine(pool_bytes=pool_bytes, max_active=max_active)
+    eng = Engine(pool_bytes=pool_bytes, max_active=max_active, max_batch=max_batch)
     log(f"serving: replaying {nreq} requests at {rate}/s ...")
     res, wall = replay(eng, items, time_scale=1.0)
     eng.close()
+    del eng
+    torch.cuda.empty_cache()
     bad = [r["status"] for r in res if r["status"] != 0]
     for r, (arr, G, _, b, _, h) in zip(res, items):
         if r["status"] != 0 or r["stats"]["retries"]:
@@ -326,7 +338,30 @@ def serving_leg(nreq, rate, pool_bytes, max_active, tol, cap):
     for c in sorted(set(cls)):
         lc = sorted(r["latency_ms"] for r, k in zip(res, cls) if k == c)
         per_class[str(c)] = {"n": len(lc), "p50_ms": pct(lc, 0.5), "p99_ms": pct(lc, 0.99)}
+    two_d = [r for r, k in zip(res, cls) if k == 0]
+    batches = len({(r["t_start_ms"], r["t_end_ms"]) for r in two_d})
+    # saturation: the first half of the stream at higher arrival rates
+    sat = []
+    half = items[: max(1, nreq // 2)]
+    for mult in saturation:
+        eng = Engine(pool_bytes=pool_bytes, max_active=max_active, max_batch=max_batch)
+        rs, w = replay(eng, half, time_scale=1.0 / mult)
+        eng.close()
+        del eng
+        torch.cuda.empty_cache()
+        ls = sorted(r["latency_ms"] for r in rs)
+        sat.append({"offered_per_s": rate * mult, "req_per_s": len(half) / w, "p50_ms": pct(ls, 0.5),
+                    "p99_ms": pct(ls, 0.99), "failed": sum(1 for r in rs if r["status"] != 0),
+                    "queue_p50_ms": pct(sorted(r["queue_ms"] for r in rs), 0.5)})
+        log(f"saturation x{mult}: offered {rate * mult:.0f}/s -> {len(half) / w:.2f} req/s, p50 "
+            f"{sat[-1]['p50_ms']:.0f} ms, p99 {sat[-1]['p99_ms']:.0f} ms")
+        if len(sat) >= 2 and sat[-1]["req_per_s"] < 1.1 * sat[-2]["req_per_s"]:
+            break   # throughput no longer grows with the load: the engine is saturated
     return {"requests": nreq, "rate_per_s": rate, "failed": len(bad), "wall_s": wall,
+            "max_batch": max_batch, "two_d_requests": len(two_d), "two_d_batches": batches,
+            "saturation": sat, "capacity_req_per_s": max([x["req_per_s"] for x in sat] + [nreq / wall]),
+            "capacity_note": "the largest throughput over the saturation runs (the stream's first half replayed "
+                             "at multiples of the rate), where queueing dominates the latency",
             "retried": sum(1 for r in res if r["stats"]["retries"]),
             "p50_ms": pct(lat, 0.5), "p99_ms": pct(lat, 0.99), "req_per_s": nreq / wall,
             "gpts": pts / wall / 1e9, "per_class": per_class, "pool_bytes": pool_bytes, "max_active": max_active,
@@ -386,6 +421,76 @@ def cpu_baseline(shot, counts, tol):
             "s_per_field_encode": t_enc, "s_per_field_decode": t_dec}
 
 
+def oracle_errors(dt, threads):
+    """Error of the GPU path against the FP64 oracle on the large shot's full 400^3 grid,
+    on samples the oracle finishes in seconds (it cannot run the shot itself in minutes):
+    a 20-step forward run (data and the final wavefield), an 8-step checkpointed gradient
+    with 3 slots for a seeded residual (recomputation on), and the whole 3000-step
+    forward run against the oracle's stored run of it (tests/golden/fault_body_3000.npz,
+    written by tests/golden/make_fault_body_3000.py) when that file is present."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import workloads as W
+    from oracle import schedule as SC
+    from paper_1810_05268_amd.shot import DeviceShot
+
+    def rel(a, b):
+        a = np.asarray(a, dtype=np.float64)
+        b = np.asarray(b, dtype=np.float64)
+        return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+    out = {}
+    for nt in (20, 8):
+        sh = W.fault_body_3d(nt=nt)
+        dto = sh.cfl_frac * oracle.cfl_dt(3, sh.h, sh.order, sh.vmax)
+        spec = oracle.ModelSpec(3, sh.n, sh.h, sh.nbl, sh.order, nt, dto, sh.vmax)
+        q = W.ricker(sh.f0, dto, nt)
+        S = oracle.Solver(spec, sh.padded("vel").astype(np.float64), sh.src, q, sh.rec, nthreads=threads)
+        G = DeviceShot(3, sh.n, sh.h, sh.nbl, sh.order, nt, dt, sh.vmax, sh.padded("vel"), q.astype(np.float32),
+                       sh.src, sh.rec)
+        if nt == 20:
+            ref = S.forward(want_last=True)
+            data, state = G.forward(want_state=True)
+            out["forward_20_steps"] = {"data": rel(data.cpu().numpy(), ref["data"]),
+                                       "u_N": rel(state[0].cpu().numpy(), ref["last"][0]),
+                                       "u_N_1": rel(state[1].cpu().numpy(), ref["last"][1])}
+            del ref, data, state
+        else:
+            M = 3
+            res = np.random.default_rng(11).standard_normal((nt + 1, len(sh.rec))) * 1e-3
+            res[0] = 0.0
+            acts = SC.schedule(nt, M, write_min=True)
+            g_or, st_or = S.gradient_actions(res, acts, M)
+            g, st = G.gradient(torch.as_tensor(res.astype(np.float32), device="cuda"), G.slot_bytes * (M - 1))
+            out["gradient_8_steps_3_slots"] = {"gradient": rel(g.cpu().numpy(), g_or),
+                                               "advances": [st["advances"], st_or["advances"]]}
+            del g
+        del S, G
+        torch.cuda.empty_cache()
+    gold = os.path.join(ROOT, "tests", "golden", "fault_body_3000.npz")
+    if os.path.exists(gold):
+        ref = np.load(gold)
+        sh = W.fault_body_3d()
+        q = W.ricker(sh.f0, dt, sh.nt).astype(np.float32)
+        G = DeviceShot(3, sh.n, sh.h, sh.nbl, sh.order, sh.nt, dt, sh.vmax, sh.padded("vel"), q, sh.src, sh.rec)
+        data, state = G.forward(want_state=True)
+        k = int(ref["sub"])
+        out["forward_3000_steps"] = {
+            "u_N_subgrid": rel(state[0][::k, ::k, ::k].cpu().numpy(), ref["u_sub"]),
+            "u_N_1_subgrid": rel(state[1][::k, ::k, ::k].cpu().numpy(), ref["up_sub"]),
+            "u_N_norm": abs(float(state[0].double().norm()) / float(ref["u_norm"]) - 1.0),
+            "data_norm": abs(float(data.double().norm()) / float(ref["data_norm"]) - 1.0),
+            "traces": rel(data[:, torch.as_tensor(ref["rec_idx"], device=data.device)].cpu().numpy(),
+                          ref["data_sub"])}
+        del G, data, state
+        torch.cuda.empty_cache()
+    out["note"] = ("relative L2 errors of the binary32 GPU path against the binary64 oracle on the full grid; "
+                   "the compressed gradient's codec share is compared with the oracle's in the parity tests")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -395,14 +500,18 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4, help="codec tolerance of the headline run")
     ap.add_argument("--sweep", default="1e-3,1e-6", help="extra tolerances timed once each ('' = none)")
     ap.add_argument("--budget", type=float, default=16e9, help="checkpoint memory, bytes")
-    ap.add_argument("--budget-sweep", default="", help="other checkpoint budgets (bytes, comma separated) timed "
-                                                       "plain and compressed once each ('' = none)")
+    ap.add_argument("--budget-sweep", default="2e9,4e9,64e9", help="other checkpoint budgets (bytes, comma "
+                                                                   "separated) timed plain and compressed once "
+                                                                   "each ('' = none)")
     ap.add_argument("--quick", action="store_true", help="small grid for a fast functional run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=200, help="0 = skip the serving stream")
     ap.add_argument("--serving-rate", type=float, default=2.0)
     ap.add_argument("--serving-pool", type=float, default=200e9)
     ap.add_argument("--serving-active", type=int, default=8)
+    ap.add_argument("--serving-batch", type=int, default=16, help="2-D requests per batched launch (0 = no batching)")
+    ap.add_argument("--serving-saturation", default="2,4,8,16", help="rate multiples of the saturation runs "
+                                                                      "('' = none)")
     ap.add_argument("--kernels", action="store_true", help="short kernel workload for counter passes only")
     ap.add_argument("--no-ot4", action="store_true", help="skip the OT4 comparison")
     args = ap.parse_args()
@@ -459,7 +568,7 @@ def main():
     # calls plan with what it measured, as an optimisation loop would carry it from one
     # iteration to the next
     log("compressed ...")
-    _, st0, _ = timed(args.tol, 0.0, g_comp, max(1, args.warmup))
+    w_cold, st0, _ = timed(args.tol, 0.0, g_comp, max(1, args.warmup))
     hint = plan_hint(st0[-1], Pn, shot.nt, budget)
     w_comp, st_comp, phi_comp = timed(args.tol, hint, g_comp, args.steps)
     _, st_comp_ph, _ = timed(args.tol, hint, g_comp, 1, TIMING_ACTIONS)
@@ -508,9 +617,9 @@ def main():
     # counted HBM bytes (traffic) over the same launch time: the real rate, against the
     # algorithmic rate of "achieved"
     roof["hbm_gbs"] = roof["adjoint_step" if dom == "adjoint" else "forward_step"]["hbm_gbs"]
-    roof["copy_gbs"] = copy_ceiling_gbs()
-    roof["copy_note"] = ("torch's device copy of 1 GiB, read + write bytes per second: a plain streaming "
-                         "reference measured in this process, not a hand-tuned ceiling")
+    roof["ceiling"] = stream_ceilings()
+    roof["ceiling_note"] = ("hand-written nontemporal streams (wv_stream_ceiling), 256 MB per array, bytes read "
+                            "plus written per second: the measured ceiling for the stencils' access mix")
     st = st_comp_ph[0]
     ms_per_store = st["ms_store"] / st["stores"] if st["stores"] else None
     ms_per_decode = st["ms_restore"] / st["decodes"] if st["decodes"] else None
@@ -562,7 +671,11 @@ def main():
         "config": {"workload": (f"{shot.name} {shot.n[0]}x{shot.n[1]}x{shot.n[2]} + {shot.nbl} layer, "
                                 f"order {shot.order}, {shot.nt} steps, budget {budget:.3g} B, tol {args.tol:g}"),
                    "points": Pn, "nt": shot.nt, "mem_budget": budget, "tol": args.tol},
-        "shot_gradient_s": {"compressed": round(ms_step / 1e3, 4), "plain": round(statistics.mean(w_plain), 4)},
+        "shot_gradient_s": {"compressed": round(ms_step / 1e3, 4), "plain": round(statistics.mean(w_plain), 4),
+                            "compressed_cold": round(w_cold[0], 4),
+                            "cold_note": "first compressed call, no ratio hint: its compressibility probe (a "
+                                         "forward run with 16 encodes) is included; the timed calls plan from "
+                                         "the profile it measured"},
         "speedup_vs_plain": round(statistics.mean(w_plain) * 1e3 / ms_step, 4),
         "grad_rel_err_vs_plain": err,
         "plain_gpts": round(Pn * 2 * shot.nt / statistics.mean(w_plain) / 1e9, 3),
@@ -600,7 +713,8 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         out["serving"] = serving_leg(args.serving_requests, args.serving_rate, int(args.serving_pool),
-                                     args.serving_active, 1e-4, int(16e9))
+                                     args.serving_active, 1e-4, int(16e9), args.serving_batch,
+                                     [float(x) for x in args.serving_saturation.split(",") if x.strip()])
         out["latency_ms"] = {"p50": out["serving"]["p50_ms"], "p99": out["serving"]["p99_ms"],
                              "of": "serving stream, from arrival to completion"}
         log(f"serving: p50 {out['serving']['p50_ms']:.1f} ms p99 {out['serving']['p99_ms']:.1f} ms "
@@ -609,6 +723,9 @@ def main():
         log("cpu baseline (oracle sample) ...")
         out["cpu_baseline"] = cpu_baseline(shot, {"advances": st["advances"], "reverses": st["reverses"],
                                                   "stores": st["stores"], "restores": st["decodes"]}, args.tol)
+        if not args.quick:
+            log("errors against the FP64 oracle (bounded samples of the large shot) ...")
+            out["err_vs_fp64_oracle"] = oracle_errors(dt, out["cpu_baseline"]["cores"])
     print(json.dumps(out), flush=True)
 
 

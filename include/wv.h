@@ -282,17 +282,55 @@ int wv_zfpk_encode_noalloc(const float *field, int ndim, const int *dims, double
  * Synchronises the stream once (the header copy). */
 int wv_zfpk_decode(const void *in, size_t nbytes, int ndim, const int *dims, float *field, void *stream);
 
+/* ------------------------------------------------------------------ batched 2-D shots */
+
+/* Misfit and gradient of nshots 2-D shots at once, advanced by one persistent kernel.
+ * Shots are independent (the paper computes one gradient per shot and sums them, Sec.
+ * "Example adjoint problem: Seismic inversion"), and a small 2-D shot cannot fill the GPU
+ * one step per launch.  The shots of a batch share the grid (n, h, nbl), space order,
+ * nt, dt, vmax and receiver count (time_order 2); velocity, wavelet, source and receiver
+ * positions and observed data are their own.  They run the checkpoint schedule of
+ * wv_misfit_gradient with the same slot count M (each shot has mem_budget bytes of
+ * checkpoint memory; compressed, M is the smallest any shot's compressibility probe
+ * plans, unless ratio_hint > 0 plans it), and one kernel launch executes the whole
+ * reversal: the host turns the schedule into a program of phases (stencil steps, source
+ * and residual injections, checkpoint encodes and decodes, the misfit), and every phase
+ * runs for all shots, with a device-wide barrier between phases (a cooperative launch,
+ * every workgroup resident).  Each shot's arithmetic is the solo call's, in the same
+ * order, so its misfit, gradient and d_sim are bit-identical to wv_misfit_gradient's for
+ * that shot alone, whatever else is in the batch.
+ *   models, geoms       host [nshots]
+ *   d_obs               host [nshots] of device [nt+1][nrec] float
+ *   misfits             host [nshots], receives phi of each shot
+ *   grad_m              host [nshots] of device [P] double, overwritten
+ *   d_sim               host [nshots] of device [nt+1][nrec] float, or NULL (entries nullable)
+ *   stats               host [nshots] or NULL (retries: repeats of the whole batch)
+ *   ws                  wv_batch_workspace_bytes(...) bytes, 256-byte aligned
+ * Errors as wv_misfit_gradient, plus WV_EINVAL for shots that do not share the above and
+ * WV_EHIP if the device-wide barrier timed out.  Synchronises the stream. */
+size_t wv_batch_workspace_bytes(int nshots, const wv_model *models, const wv_geom *geoms, size_t mem_budget);
+int wv_batch_misfit_gradient(int nshots, const wv_model *models, const wv_geom *geoms, const float *const *d_obs,
+                             size_t mem_budget, double tol, double ratio_hint, double *misfits,
+                             double *const *grad_m, float *const *d_sim, wv_stats *stats, void *ws, size_t ws_bytes,
+                             void *stream);
+
 /* ------------------------------------------------------------------ serving engine */
 
 /* Continuous batching of shot-gradient requests (shots are independent; the paper
  * computes one gradient per shot and sums them, Sec. "Example adjoint problem").
  * The engine owns max_active worker threads, each with its own HIP stream (default
- * priority) on the device current at creation.  A queued request is admitted, first
- * come first served, as soon as a worker is free and a contiguous slice of the pool
- * holds its workspace (wv_workspace_bytes with WV_OP_GRADIENT and its mem_budget,
- * i.e. its working fields plus its checkpoint arena); its kernels then run beside
- * those of the other admitted requests.  A request's result does not depend on what
- * else is in flight. */
+ * priority) on the device current at creation.  Admission is first fit in arrival
+ * order: a free worker takes the oldest queued request whose workspace
+ * (wv_workspace_bytes with WV_OP_GRADIENT and its mem_budget, i.e. its working fields
+ * plus its checkpoint arena) fits a contiguous free slice of the pool; a request passed
+ * over 8 times by later ones is not passed again (nothing behind it is admitted until
+ * it is).  Its kernels then run beside those of the other admitted requests.  With
+ * batching on (wv_engine_set_batching), 2-D requests are served by one more worker
+ * that runs the oldest queued 2-D request together with every later one that can share
+ * its call (same grid, order, nt, dt, vmax, receiver count, tolerance, budget and ratio
+ * hint), up to max_batch of them, as one wv_batch_misfit_gradient; requests arriving
+ * while a batch runs join the next.  A request's result does not depend on what else is
+ * in flight: batched or not, it is bit-identical to wv_misfit_gradient alone. */
 typedef struct wv_engine wv_engine;
 
 typedef struct {
@@ -307,6 +345,10 @@ typedef struct {
 /* pool: device memory, 256-byte aligned, caller-owned, must outlive the engine.
  * max_active: 1..64 requests in flight. */
 int wv_engine_create(void *pool, size_t pool_bytes, int max_active, wv_engine **engine);
+
+/* Turn the batch lane on (max_batch 2..256: 2-D requests run in batches of up to that
+ * many) or leave it off (0 or 1).  Only before the first request.  WV_EINVAL otherwise. */
+int wv_engine_set_batching(wv_engine *engine, int max_batch);
 
 /* Queue a misfit + gradient request (as wv_misfit_gradient).  model->vel, wavelet,
  * d_obs, grad_m and d_sim (nullable) must stay valid until wv_engine_wait returns
@@ -425,6 +467,13 @@ typedef struct {
  * exact.  Host only. */
 int wv_choose(int nt, long long points, size_t mem_budget, const wv_costs *plain, const wv_costs *compressed,
               const double *profile, int nprofile, wv_choice *out);
+
+/* Measurement hook: the HBM ceiling of this device for a streaming kernel that reads
+ * `reads` (1..4) arrays and writes one, each stream_bytes long, with nontemporal
+ * accesses, four 16-byte loads per lane in flight, over ws (at least (reads + 1)
+ * stream_bytes, 256-byte aligned; overwritten).  *gbs receives the best of reps timed
+ * launches, in GB/s (bytes read plus written).  Synchronises the stream. */
+int wv_stream_ceiling(int reads, size_t stream_bytes, void *ws, size_t ws_bytes, int reps, double *gbs, void *stream);
 
 const char *wv_strerror(int code);
 

@@ -92,8 +92,8 @@ class WvResult(C.Structure):
 # every symbol include/wv.h declares
 SYMBOLS = ["wv_cfl_dt", "wv_cfl_dt_to", "wv_workspace_bytes", "wv_field_elements", "wv_forward", "wv_gradient", "wv_misfit_gradient", "wv_adjoint_src",
            "wv_pad_velocity", "wv_velocity_gradient", "wv_zfpk_workspace_bytes", "wv_zfpk_max_bytes",
-           "wv_zfpk_encode", "wv_zfpk_encode_noalloc", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_predict", "wv_choose", "wv_plan", "wv_compressibility", "wv_strerror",
-           "wv_last_error", "wv_version", "wv_engine_create", "wv_engine_submit", "wv_engine_wait",
+           "wv_zfpk_encode", "wv_zfpk_encode_noalloc", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_predict", "wv_choose", "wv_plan", "wv_compressibility", "wv_stream_ceiling", "wv_strerror",
+           "wv_last_error", "wv_version", "wv_batch_workspace_bytes", "wv_batch_misfit_gradient", "wv_engine_create", "wv_engine_set_batching", "wv_engine_submit", "wv_engine_wait",
            "wv_engine_pending", "wv_engine_destroy"]
 
 _lib = None
@@ -142,11 +142,18 @@ def lib():
                               C.POINTER(C.c_double)]
         L.wv_compressibility.argtypes = [mp, gp, C.c_double, C.c_int, C.POINTER(C.c_size_t), C.c_int,
                                          C.POINTER(C.c_int), vp, sz, vp]
+        L.wv_batch_workspace_bytes.argtypes = [C.c_int, mp, gp, sz]
+        L.wv_batch_workspace_bytes.restype = sz
+        L.wv_batch_misfit_gradient.argtypes = [C.c_int, mp, gp, C.POINTER(C.c_void_p), sz, C.c_double, C.c_double,
+                                               C.POINTER(C.c_double), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                               stp, vp, sz, vp]
+        L.wv_stream_ceiling.argtypes = [C.c_int, sz, vp, sz, C.c_int, C.POINTER(C.c_double), vp]
         L.wv_strerror.argtypes = [C.c_int]
         L.wv_strerror.restype = C.c_char_p
         L.wv_version.restype = C.c_char_p
         L.wv_last_error.restype = C.c_char_p
         L.wv_engine_create.argtypes = [vp, sz, C.c_int, C.POINTER(C.c_void_p)]
+        L.wv_engine_set_batching.argtypes = [vp, C.c_int]
         L.wv_engine_submit.argtypes = [vp, mp, gp, vp, sz, C.c_double, C.c_double, vp, vp]
         L.wv_engine_wait.argtypes = [vp, C.c_int, C.c_double, C.POINTER(WvResult)]
         L.wv_engine_pending.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
@@ -349,6 +356,46 @@ def misfit_gradient(pb: Problem, d_obs, mem_budget: int, tol: float, grad, ws, r
                                     float(ratio_hint), C.byref(phi), _ptr(grad), _ptr(d_sim), C.byref(st), _ptr(ws),
                                     ws.numel() * ws.element_size(), _stream(stream)), "wv_misfit_gradient")
     return float(phi.value), st.as_dict()
+
+
+def stream_ceiling(reads: int, stream_bytes: int, ws, reps: int = 10, stream=None) -> float:
+    """GB/s of a nontemporal stream of `reads` input arrays and one output (wv_stream_ceiling)."""
+    out = C.c_double(0.0)
+    _check(lib().wv_stream_ceiling(int(reads), int(stream_bytes), _ptr(ws), ws.numel() * ws.element_size(), int(reps),
+                                   C.byref(out), _stream(stream)), "wv_stream_ceiling")
+    return float(out.value)
+
+
+def _batch_structs(pbs):
+    models = (WvModel * len(pbs))(*[pb.model for pb in pbs])
+    geoms = (WvGeom * len(pbs))(*[pb.geom for pb in pbs])
+    return models, geoms
+
+
+def batch_workspace_bytes(pbs, mem_budget: int) -> int:
+    models, geoms = _batch_structs(pbs)
+    b = int(lib().wv_batch_workspace_bytes(len(pbs), models, geoms, int(mem_budget)))
+    if b == 0:
+        raise WvError(WV_EINVAL, "wv_batch_workspace_bytes")
+    return b
+
+
+def batch_misfit_gradient(pbs, d_obs, mem_budget: int, tol: float, grads, ws, ratio_hint: float = 0.0,
+                          d_sims=None, stream=None) -> tuple[list, list]:
+    """wv_batch_misfit_gradient over the shots pbs (Problem each); d_obs, grads, d_sims:
+    lists of device tensors, one per shot.  Returns (misfits, stats dicts)."""
+    n = len(pbs)
+    models, geoms = _batch_structs(pbs)
+    vp_arr = C.c_void_p * n
+    dobs = vp_arr(*[_ptr(t) for t in d_obs])
+    gs = vp_arr(*[_ptr(t) for t in grads])
+    ds = vp_arr(*[_ptr(t) for t in d_sims]) if d_sims is not None else None
+    phis = (C.c_double * n)()
+    sts = (WvStats * n)()
+    _check(lib().wv_batch_misfit_gradient(n, models, geoms, dobs, int(mem_budget), float(tol), float(ratio_hint),
+                                          phis, gs, ds, sts, _ptr(ws), ws.numel() * ws.element_size(),
+                                          _stream(stream)), "wv_batch_misfit_gradient")
+    return [float(phis[i]) for i in range(n)], [sts[i].as_dict() for i in range(n)]
 
 
 def adjoint_src(pb: Problem, residual, src_adj, ws, stream=None) -> None:

@@ -2,15 +2,28 @@
 //
 // Shots are independent (the paper's gradients are computed per shot and summed,
 // Sec. "Example adjoint problem: Seismic inversion"), so the engine runs several of
-// them at once: each admitted request gets a slice of a caller-provided device
-// pool (its workspace, including its checkpoint arena) and one of max_active
-// worker threads, each with its own HIP stream, so the kernels of different shots
-// overlap on the device.  Admission is first come, first served: the head of the
-// queue starts as soon as a worker is free and a contiguous slice of the pool that
-// holds its workspace is free; a finished request returns its slice and the next
-// one is admitted at once.  Every request is computed exactly as it would be alone
-// (same kernels, same launch shapes, no shared accumulators), so its result does
-// not depend on what else is in flight.
+// them at once.  Each admitted request gets a slice of a caller-provided device pool
+// (its workspace, including its checkpoint arena) and one of max_active worker
+// threads, each with its own HIP stream, so the kernels of different shots overlap on
+// the device.
+//
+// Admission is first fit in arrival order: a free worker takes the oldest queued
+// request whose workspace fits a contiguous free slice of the pool, so a large request
+// that must wait for memory does not hold back smaller ones behind it.  To keep it from
+// waiting for ever, once it has been passed over kMaxSkips times nothing behind it is
+// admitted until it is.
+//
+// With batching on (wv_engine_set_batching), 2-D requests go to a batch lane instead:
+// one more worker takes every queued 2-D request that shares the oldest one's grid,
+// order, steps, time step, receiver count, tolerance and budget (up to max_batch of
+// them) and runs them as one batched call (wv_batch_misfit_gradient: one persistent
+// kernel advances all of them), while the 3-D requests keep their own workers.  Requests
+// that arrive while a batch runs join the next one.
+//
+// Every request is computed exactly as it would be alone (same kernels and reduction
+// orders; a batched shot's arithmetic is the solo call's), so its result does not
+// depend on what else is in flight.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -26,6 +39,8 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+constexpr int kMaxSkips = 8;
+
 struct Request {
     int id = 0;
     wv_model model{};
@@ -37,10 +52,22 @@ struct Request {
     double *grad = nullptr;
     float *d_sim = nullptr;
     size_t ws_bytes = 0, ws_off = 0;
+    bool batchable = false;   // a 2-D OT2 request
+    int skipped = 0;          // times a later request was admitted before it
     bool done = false;
     wv_result res{};
     Clock::time_point t_submit, t_start, t_end;
 };
+
+// requests that can share one batched call
+bool same_batch(const Request &a, const Request &b)
+{
+    const wv_model &x = a.model, &y = b.model;
+    return x.n[0] == y.n[0] && x.n[1] == y.n[1] && x.h[0] == y.h[0] && x.h[1] == y.h[1] && x.nbl == y.nbl &&
+           x.space_order == y.space_order && x.nt == y.nt && x.dt == y.dt && x.vmax == y.vmax &&
+           a.geom.nrec == b.geom.nrec && a.tol == b.tol && a.mem_budget == b.mem_budget &&
+           a.ratio_hint == b.ratio_hint;
+}
 
 // first-fit allocator over [0, size) with coalescing, 256-byte granularity
 struct Pool {
@@ -93,8 +120,46 @@ struct wv_engine {
     std::vector<hipStream_t> streams;
     int next_id = 0;
     int active = 0;
+    int max_batch = 0;        // > 1: 2-D requests run in batches of up to this many
+    bool batch_started = false;
+    std::thread batch_worker;
+    hipStream_t batch_stream = nullptr;
     bool stop = false;
     Clock::time_point t0;
+
+    double ms(Clock::time_point t) const { return std::chrono::duration<double, std::milli>(t - t0).count(); }
+
+    // Under mu: the request a solo worker admits now (taking its pool slice), or null.
+    Request *admit_solo()
+    {
+        for (auto it = queue.begin(); it != queue.end(); ++it) {
+            Request *r = *it;
+            if (max_batch > 1 && r->batchable) continue;   // the batch lane's
+            size_t off;
+            if (pool.take(r->ws_bytes, &off)) {
+                r->ws_off = off;
+                // every solo request before it that did not fit is passed over once more
+                for (auto jt = queue.begin(); jt != it; ++jt)
+                    if (!(max_batch > 1 && (*jt)->batchable)) (*jt)->skipped++;
+                queue.erase(it);
+                return r;
+            }
+            if (r->skipped >= kMaxSkips) return nullptr;   // it is next: nothing passes it
+        }
+        return nullptr;
+    }
+
+    void finish(Request *r, int rc, double phi, const wv_stats &st, Clock::time_point t_end)
+    {
+        r->t_end = t_end;
+        r->res.status = rc;
+        r->res.misfit = phi;
+        r->res.stats = st;
+        r->res.t_submit_ms = ms(r->t_submit);
+        r->res.t_start_ms = ms(r->t_start);
+        r->res.t_end_ms = ms(r->t_end);
+        r->done = true;
+    }
 
     void run(int w)
     {
@@ -105,20 +170,14 @@ struct wv_engine {
                 std::unique_lock<std::mutex> lk(mu);
                 cv_work.wait(lk, [&] {
                     if (stop && queue.empty()) return true;
-                    if (queue.empty()) return false;
-                    size_t off;
-                    if (!pool.take(queue.front()->ws_bytes, &off)) return false;
-                    queue.front()->ws_off = off;
-                    return true;
+                    return (r = admit_solo()) != nullptr || (stop && !has_solo());
                 });
-                if (queue.empty()) return;   // stopping
-                r = queue.front();
-                queue.pop_front();
+                if (!r) return;   // stopping
                 ++active;
                 r->t_start = Clock::now();
             }
             // the next request may fit as well
-            cv_work.notify_one();
+            cv_work.notify_all();
             r->geom.src_xyz = r->src.data();
             r->geom.rec_xyz = r->rec.data();
             wv_stats st{};
@@ -128,19 +187,116 @@ struct wv_engine {
                                               streams[w]);
             {
                 std::lock_guard<std::mutex> lk(mu);
-                r->t_end = Clock::now();
-                r->res.status = rc;
-                r->res.misfit = phi;
-                r->res.stats = st;
-                auto ms = [&](Clock::time_point t) {
-                    return std::chrono::duration<double, std::milli>(t - t0).count();
-                };
-                r->res.t_submit_ms = ms(r->t_submit);
-                r->res.t_start_ms = ms(r->t_start);
-                r->res.t_end_ms = ms(r->t_end);
-                r->done = true;
+                finish(r, rc, phi, st, Clock::now());
                 pool.give(r->ws_off, r->ws_bytes);
                 --active;
+            }
+            cv_done.notify_all();
+            cv_work.notify_all();
+        }
+    }
+
+    bool has_solo() const
+    {
+        for (const Request *r : queue)
+            if (!(max_batch > 1 && r->batchable)) return true;
+        return false;
+    }
+    bool has_batchable() const
+    {
+        for (const Request *r : queue)
+            if (r->batchable) return true;
+        return false;
+    }
+
+    // The batch lane: the oldest queued 2-D request and every later one that can share
+    // its call, as many as fit max_batch and the pool.
+    void run_batch()
+    {
+        (void)hipSetDevice(device);
+        for (;;) {
+            std::vector<Request *> batch;
+            size_t off = 0, bytes = 0;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_work.wait(lk, [&] {
+                    if (stop && !has_batchable()) return true;
+                    Request *head = nullptr;
+                    for (Request *r : queue)
+                        if (r->batchable) {
+                            head = r;
+                            break;
+                        }
+                    if (!head) return false;
+                    std::vector<Request *> cand;
+                    for (Request *r : queue)
+                        if (r->batchable && same_batch(*head, *r) && (int)cand.size() < max_batch) cand.push_back(r);
+                    // the largest prefix of the candidates whose batch workspace fits the pool
+                    while (!cand.empty()) {
+                        std::vector<wv_model> ms;
+                        std::vector<wv_geom> gs;
+                        for (Request *r : cand) {
+                            ms.push_back(r->model);
+                            gs.push_back(r->geom);
+                            gs.back().src_xyz = r->src.data();
+                            gs.back().rec_xyz = r->rec.data();
+                        }
+                        const size_t need = wv_batch_workspace_bytes((int)cand.size(), ms.data(), gs.data(),
+                                                                     head->mem_budget);
+                        const size_t need_al = (need + 255) / 256 * 256;
+                        if (need == 0) {
+                            // not a valid batch (cannot happen for requests that passed submit):
+                            // fail the head alone
+                            cand.resize(1);
+                            bytes = 0;
+                            break;
+                        }
+                        if (pool.take(need_al, &off)) {
+                            bytes = need_al;
+                            break;
+                        }
+                        cand.pop_back();
+                    }
+                    if (cand.empty()) return false;
+                    batch = cand;
+                    return true;
+                });
+                if (batch.empty()) return;   // stopping
+                for (Request *r : batch) {
+                    queue.erase(std::find(queue.begin(), queue.end(), r));
+                    r->t_start = Clock::now();
+                }
+                active += (int)batch.size();
+            }
+            const int n = (int)batch.size();
+            std::vector<wv_model> ms((size_t)n);
+            std::vector<wv_geom> gs((size_t)n);
+            std::vector<const float *> dobs((size_t)n);
+            std::vector<double *> grads((size_t)n);
+            std::vector<float *> dsims((size_t)n);
+            std::vector<double> phis((size_t)n, 0.0);
+            std::vector<wv_stats> sts((size_t)n);
+            for (int i = 0; i < n; ++i) {
+                Request *r = batch[i];
+                r->geom.src_xyz = r->src.data();
+                r->geom.rec_xyz = r->rec.data();
+                ms[i] = r->model;
+                gs[i] = r->geom;
+                dobs[i] = r->d_obs;
+                grads[i] = r->grad;
+                dsims[i] = r->d_sim;
+            }
+            const int rc = bytes ? wv_batch_misfit_gradient(n, ms.data(), gs.data(), dobs.data(),
+                                                            batch[0]->mem_budget, batch[0]->tol, batch[0]->ratio_hint,
+                                                            phis.data(), grads.data(), dsims.data(), sts.data(),
+                                                            pool_base + off, bytes, batch_stream)
+                                 : WV_EINVAL;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                const Clock::time_point t_end = Clock::now();
+                for (int i = 0; i < n; ++i) finish(batch[i], rc, phis[i], sts[i], t_end);
+                if (bytes) pool.give(off, bytes);
+                active -= n;
             }
             cv_done.notify_all();
             cv_work.notify_all();
@@ -177,6 +333,20 @@ int wv_engine_create(void *pool, size_t pool_bytes, int max_active, wv_engine **
     return WV_OK;
 }
 
+int wv_engine_set_batching(wv_engine *e, int max_batch)
+{
+    if (!e || max_batch < 0 || max_batch > 256) return WV_EINVAL;
+    std::lock_guard<std::mutex> lk(e->mu);
+    if (e->batch_started || !e->queue.empty() || e->active) return WV_EINVAL;   // before the first request only
+    e->max_batch = max_batch;
+    if (max_batch > 1) {
+        if (hipStreamCreateWithFlags(&e->batch_stream, hipStreamNonBlocking) != hipSuccess) return WV_EHIP;
+        e->batch_started = true;
+        e->batch_worker = std::thread([e] { e->run_batch(); });
+    }
+    return WV_OK;
+}
+
 int wv_engine_submit(wv_engine *e, const wv_model *model, const wv_geom *geom, const float *d_obs,
                      size_t mem_budget, double tol, double ratio_hint, double *grad_m, float *d_sim)
 {
@@ -184,12 +354,13 @@ int wv_engine_submit(wv_engine *e, const wv_model *model, const wv_geom *geom, c
     const size_t ws = wv_workspace_bytes(model, geom, WV_OP_GRADIENT, mem_budget);
     if (ws == 0) return WV_EINVAL;
     const size_t need = (ws + 255) / 256 * 256;
-    if (need > e->pool_bytes) return WV_EBUDGET;   // could never be admitted
     Request *r = new Request();
     r->model = *model;
     r->geom = *geom;
     r->src.assign(geom->src_xyz, geom->src_xyz + (size_t)geom->nsrc * model->ndim);
     r->rec.assign(geom->rec_xyz, geom->rec_xyz + (size_t)geom->nrec * model->ndim);
+    r->geom.src_xyz = r->src.data();
+    r->geom.rec_xyz = r->rec.data();
     r->d_obs = d_obs;
     r->mem_budget = mem_budget;
     r->tol = tol;
@@ -197,6 +368,22 @@ int wv_engine_submit(wv_engine *e, const wv_model *model, const wv_geom *geom, c
     r->grad = grad_m;
     r->d_sim = d_sim;
     r->ws_bytes = need;
+    r->batchable = model->ndim == 2 && (model->time_order == 0 || model->time_order == 2);
+    if (r->batchable && e->max_batch > 1) {
+        // a batch of one must fit the pool
+        const size_t nb = wv_batch_workspace_bytes(1, &r->model, &r->geom, mem_budget);
+        if (nb == 0) {
+            delete r;
+            return WV_EINVAL;
+        }
+        if ((nb + 255) / 256 * 256 > e->pool_bytes) {
+            delete r;
+            return WV_EBUDGET;
+        }
+    } else if (need > e->pool_bytes) {
+        delete r;
+        return WV_EBUDGET;   // could never be admitted
+    }
     {
         std::lock_guard<std::mutex> lk(e->mu);
         if (e->stop) {
@@ -208,7 +395,7 @@ int wv_engine_submit(wv_engine *e, const wv_model *model, const wv_geom *geom, c
         e->reqs[r->id] = r;
         e->queue.push_back(r);
     }
-    e->cv_work.notify_one();
+    e->cv_work.notify_all();
     return r->id;
 }
 
@@ -247,7 +434,9 @@ int wv_engine_destroy(wv_engine *e)
     }
     e->cv_work.notify_all();
     for (std::thread &t : e->workers) t.join();
+    if (e->batch_worker.joinable()) e->batch_worker.join();
     for (hipStream_t s : e->streams) (void)hipStreamDestroy(s);
+    if (e->batch_stream) (void)hipStreamDestroy(e->batch_stream);
     for (auto &kv : e->reqs) delete kv.second;
     delete e;
     return WV_OK;

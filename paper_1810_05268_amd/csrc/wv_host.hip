@@ -9,6 +9,7 @@
 // tolerance the copies pass through the codec (eq. (6)) and the slot count grows
 // by the compression ratio.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1486,6 +1487,371 @@ int wv_misfit_gradient(const wv_model *m, const wv_geom *geo, const float *d_obs
     if (!d_obs || !misfit) return WV_EINVAL;
     return gradient_common(m, geo, nullptr, d_obs, mem_budget, tol, ratio_hint, misfit, grad_m, d_sim, stats, ws,
                            ws_bytes, stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batched 2-D shots
+namespace {
+
+constexpr size_t kBatchHdr = 4096;   // barrier words of the persistent launch
+
+// program steps for the schedule acts, with the solo executor's bookkeeping (which
+// buffer holds each level, when the second level is decoded, which data rows the first
+// sweep gathers); every shot of the batch runs the same steps
+struct BatchPlan {
+    std::vector<BatchOp> ops;
+    bool valid = true;
+    long advances = 0, stores = 0, restores = 0, reverses = 0, decodes = 0, fields = 0;
+    int max_depth = 0;
+};
+
+BatchPlan build_batch_program(const std::vector<int32_t> &acts, int M, bool comp)
+{
+    BatchPlan B;
+    auto op = [&](int kind, int n, int a, int b, int c, int d, int e) {
+        B.ops.push_back(BatchOp{kind, n, a, b, c, d, e});
+    };
+    const std::vector<char> need2 = second_level_needed(acts, M);
+    std::vector<char> slot2((size_t)M + 2, 0);
+    int u = kBufZ, up = kBufZ;            // buffers of u^n and u^{n-1} (kBufNone: not decoded yet)
+    int hot_slot = -1, hot_k = -1, pend_slot = -1;
+    bool up_pending = false, hot_db = false, residual_ready = false;
+    int gathered = 0, lc = 0;
+    for (size_t i = 0; i < acts.size() / 3; ++i) {
+        const int a = acts[3 * i + 1], b = acts[3 * i + 2];
+        switch (acts[3 * i]) {
+        case ADVANCE:
+            if (up == kBufNone) {   // advancing from a restore: decode the second level now
+                if (!up_pending) {      // cannot happen: the scan above marks these checkpoints
+                    B.ops.clear();
+                    B.valid = false;
+                    return B;
+                }
+                if (!hot_db) {
+                    op(kOpDec, -1, kBufDB, kBufUB, 0, 2 * pend_slot + 1, 0);
+                    hot_db = true;
+                    B.decodes++;
+                }
+                up = kBufDB;
+                up_pending = false;
+            }
+            op(kOpFwd, a, u, up, 0, b, std::max(a, gathered));
+            gathered = std::max(gathered, b);
+            for (int n = a; n < b; ++n) {   // the buffers the steps leave behind
+                const int out = u == kBufU0 ? kBufU1 : kBufU0;
+                up = u;
+                u = out;
+            }
+            B.advances += b - a;
+            break;
+        case STORE:
+            slot2[b] = need2[i];
+            if (need2[i] && up == kBufNone) {   // cannot happen either
+                B.ops.clear();
+                B.valid = false;
+                return B;
+            }
+            if (comp) {
+                op(kOpEncCount, a, u, need2[i] ? up : kBufNone, 0, 2 * b, 0);
+                op(kOpEncEmit, a, u, need2[i] ? up : kBufNone, 0, 2 * b, 0);
+                if (hot_slot == b) hot_slot = -1;
+            } else {
+                op(kOpCopy, -1, u, kBufSlot + 2 * b, 0, 0, 0);
+                if (need2[i]) op(kOpCopy, -1, up, kBufSlot + 2 * b + 1, 0, 0, 0);
+            }
+            B.stores++;
+            B.fields += need2[i] ? 2 : 1;
+            B.max_depth = std::max(B.max_depth, b);
+            break;
+        case RESTORE:
+            up_pending = false;
+            if (b == 0) {
+                u = up = kBufZ;
+            } else if (comp) {
+                if (hot_slot != b || hot_k != a) {
+                    op(kOpDec, -1, kBufUB, kBufNone, 0, 2 * b, 0);
+                    hot_slot = b;
+                    hot_k = a;
+                    hot_db = false;
+                    B.decodes++;
+                }
+                u = kBufUB;
+                up = kBufNone;
+                up_pending = slot2[b] != 0;
+                pend_slot = b;
+            } else {
+                u = kBufSlot + 2 * b;
+                up = slot2[b] ? kBufSlot + 2 * b + 1 : kBufNone;
+            }
+            B.restores++;
+            break;
+        case REVERSE:
+            if (!residual_ready) {
+                op(kOpResid, -1, u, 0, 0, 0, 0);
+                op(kOpMisfit, -1, 0, 0, 0, 0, 0);
+                residual_ready = true;
+            }
+            // lam^{k-1} overwrites lam^{k+1}
+            op(kOpAdj, a, lc ? kBufL1 : kBufL0, lc ? kBufL0 : kBufL1, u, 0, 0);
+            lc ^= 1;
+            B.reverses++;
+            break;
+        default:
+            break;
+        }
+    }
+    return B;
+}
+
+struct BatchShape {
+    size_t hdr, desc, ops, shot0, shot_bytes, chunk_off;
+    int max_ops;
+    size_t total;
+};
+
+int batch_setup(int nshots, const wv_model *ms, const wv_geom *gs, size_t budget, std::vector<Setup> &su,
+                std::vector<Layout> &L, BatchShape &B)
+{
+    if (nshots < 1 || nshots > 4096 || !ms || !gs) return WV_EINVAL;
+    const wv_model &m0 = ms[0];
+    if (m0.ndim != 2 || (m0.time_order != 0 && m0.time_order != 2)) return WV_EINVAL;
+    su.assign((size_t)nshots, Setup{});
+    L.assign((size_t)nshots, Layout{});
+    for (int i = 0; i < nshots; ++i) {
+        const wv_model &m = ms[i];
+        const bool same = m.ndim == 2 && m.n[0] == m0.n[0] && m.n[1] == m0.n[1] && m.h[0] == m0.h[0] &&
+                          m.h[1] == m0.h[1] && m.nbl == m0.nbl && m.space_order == m0.space_order &&
+                          m.nt == m0.nt && m.dt == m0.dt && m.vmax == m0.vmax &&
+                          (m.time_order == 0 || m.time_order == 2) && gs[i].nrec == gs[0].nrec;
+        if (!same) return WV_EINVAL;
+        int rc = prepare(&m, &gs[i], su[i]);
+        if (rc) return rc;
+        L[i] = plan_layout(&m, &gs[i], su[i], WV_OP_GRADIENT, budget);
+    }
+    const CodecDims cd = codec_dims(2, std::array<int, 3>{su[0].g.nx, su[0].g.nz, 1}.data(), su[0].g.px);
+    B.max_ops = 10 * m0.nt + 64;
+    B.hdr = 0;
+    B.desc = kBatchHdr;
+    B.ops = align_up(B.desc + (size_t)nshots * sizeof(BatchShot), 256);
+    B.shot0 = align_up(B.ops + (size_t)B.max_ops * sizeof(BatchOp), 256);
+    size_t lay = 0;
+    for (int i = 0; i < nshots; ++i) lay = std::max(lay, L[i].total);
+    B.chunk_off = align_up(lay, 256);
+    B.shot_bytes = align_up(B.chunk_off + (size_t)2 * cd.nchunks * 4, 256);
+    B.total = B.shot0 + (size_t)nshots * B.shot_bytes;
+    return WV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t wv_batch_workspace_bytes(int nshots, const wv_model *models, const wv_geom *geoms, size_t mem_budget)
+{
+    std::vector<Setup> su;
+    std::vector<Layout> L;
+    BatchShape B{};
+    if (batch_setup(nshots, models, geoms, mem_budget, su, L, B)) return 0;
+    return B.total;
+}
+
+int wv_batch_misfit_gradient(int nshots, const wv_model *models, const wv_geom *geoms, const float *const *d_obs,
+                             size_t mem_budget, double tol, double ratio_hint, double *misfits,
+                             double *const *grad_m, float *const *d_sim, wv_stats *stats, void *ws, size_t ws_bytes,
+                             void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<Setup> su;
+    std::vector<Layout> L;
+    BatchShape B{};
+    int rc = batch_setup(nshots, models, geoms, mem_budget, su, L, B);
+    if (rc) return rc;
+    if (!d_obs || !misfits || !grad_m || !(tol >= 0) || !std::isfinite(tol)) return WV_EINVAL;
+    for (int i = 0; i < nshots; ++i)
+        if (!d_obs[i] || !grad_m[i]) return WV_EINVAL;
+    if (!ws || ws_bytes < B.total) return WV_ENOMEM;
+    if (((uintptr_t)ws) & 255) return WV_EINVAL;
+    uint8_t *base = (uint8_t *)ws;
+    const wv_model &m0 = models[0];
+    const int N = m0.nt;
+    const Grid &g = su[0].g;
+    const int cdims[3] = {g.nx, g.nz, 1};
+    const CodecDims cd = codec_dims(2, cdims, g.px);
+    const int nwg = batch2d_resident_workgroups(g.K);
+    if (nwg < 1) return hip_fail(hipErrorInvalidValue, "batch2d_resident_workgroups", __LINE__);
+    // per-shot set-up, as a solo call: tables, w, velocity check, zeroed work arrays
+    std::vector<Dev> dv((size_t)nshots);
+    std::vector<BatchShot> shots((size_t)nshots);
+    for (int i = 0; i < nshots; ++i) {
+        uint8_t *sb = base + B.shot0 + (size_t)i * B.shot_bytes;
+        if ((rc = bind(dv[i], sb, B.shot_bytes, L[i], WV_OP_GRADIENT))) return rc;
+        if ((rc = start(dv[i], &models[i], su[i], s))) return rc;
+        Dev &d = dv[i];
+        BatchShot &S = shots[i];
+        S.U[0] = d.U[0];
+        S.U[1] = d.U[1];
+        S.UB = d.UB;
+        S.DB = d.DB;
+        S.Lm[0] = d.Lm[0];
+        S.Lm[1] = d.Lm[1];
+        S.Z = d.Z;
+        S.W = d.W;
+        S.wavelet = geoms[i].wavelet;
+        S.dobs = d_obs[i];
+        S.dsim = (d_sim && d_sim[i]) ? d_sim[i] : d.dsim;
+        S.res = d.res;
+        S.G = grad_m[i];
+        S.partials = d.partials;
+        S.misfit = d.misfit;
+        S.arena = d.arena;
+        S.arena_bytes = d.L.arena_bytes;
+        S.offs = d.offs;
+        S.sizes = d.sizes;
+        S.chunk_words = (uint32_t *)(sb + B.chunk_off);
+        S.err = d.err;
+        S.stats = d.stats;
+        S.src = d.src;
+        S.rec = d.rec;
+    }
+    const size_t Sd = (size_t)su[0].P * 8;   // the dense pair that ratios refer to
+    const size_t Sp = (size_t)su[0].Pf * 8;  // one uncompressed slot
+    double F = 1.0;
+    if (tol > 0) {
+        if (ratio_hint > 0) {
+            F = ratio_hint;
+        } else {
+            // each shot's compressibility probe; the batch takes the smallest slot count
+            int Mmin = N;
+            double Fmin = 0.0;
+            for (int i = 0; i < nshots; ++i) {
+                GradRun R{&models[i], &geoms[i], su[i], dv[i], s, tol, true, false};
+                R.cd = cd;
+                R.S = Sp;
+                R.Sd = Sd;
+                double Fi = 1.0, prof[kProfile];
+                if ((rc = probe_ratio(R, &Fi, prof))) return rc;
+                int Mi = plan_slots(N, mem_budget, Sd, true, Fi);
+                if (profile_valid(prof)) Mi = plan_slots_profile(N, mem_budget, prof);
+                if (i == 0 || Mi < Mmin) {
+                    Mmin = Mi;
+                    Fmin = Fi;
+                }
+            }
+            F = Mmin > 1 ? ratio_for_slots(N, mem_budget, Sd, Mmin) : std::max(1.0, Fmin);
+        }
+    }
+    const double gscale = gradient_scale(&m0);
+    BatchArgs A{};
+    A.g = g;
+    A.cd = cd;
+    A.shots = reinterpret_cast<const BatchShot *>(base + B.desc);
+    A.nshots = nshots;
+    A.ops = reinterpret_cast<const BatchOp *>(base + B.ops);
+    A.gscale = gscale;
+    A.tol = tol;
+    {
+        int te;
+        std::frexp(tol > 0 ? tol : 1.0, &te);
+        A.minexp = te - 1;
+    }
+    A.nrec = geoms[0].nrec;
+    A.nt = N;
+    A.zlen = 16;
+    A.slot_elems = (long long)su[0].Pf * 2;
+    A.bar = reinterpret_cast<unsigned *>(base + B.hdr);
+    A.nwg = nwg;
+    for (int i = 0; i < nshots; ++i) {
+        A.src_pts = std::max(A.src_pts, shots[i].src.npts);
+        A.rec_pts = std::max(A.rec_pts, shots[i].rec.npts);
+    }
+    HIPCHK(hipMemcpyAsync(base + B.desc, shots.data(), shots.size() * sizeof(BatchShot), hipMemcpyHostToDevice, s));
+    for (int attempt = 0;; ++attempt) {
+        const int M = plan_slots(N, mem_budget, tol > 0 ? Sd : Sp, tol > 0, F);
+        if (M < 1) return WV_EBUDGET;
+        std::vector<int32_t> acts;
+        make_schedule(N, M, !(tol > 0), acts);
+        const BatchPlan plan = build_batch_program(acts, M, tol > 0);
+        // cannot happen: the program is bounded by the action count, and the executor's
+        // bookkeeping always has the levels a step reads
+        if (!plan.valid || (int)plan.ops.size() > B.max_ops) return WV_EINVAL;
+        A.nops = (int)plan.ops.size();
+        for (int i = 0; i < nshots; ++i) {
+            Dev &d = dv[i];
+            HIPCHK(launch_fill_f32(d.Lm[0], su[i].Pf, 0.0f, s));
+            HIPCHK(launch_fill_f32(d.Lm[1], su[i].Pf, 0.0f, s));
+            HIPCHK(launch_fill_f64(grad_m[i], su[i].P, 0.0, s));
+            HIPCHK(launch_fill_u64(d.offs, d.L.offs_n, 0, s));
+            HIPCHK(launch_fill_u64(d.sizes, N + 1, 0, s));
+            HIPCHK(launch_fill_f32(shots[i].dsim, geoms[i].nrec, 0.0f, s));
+        }
+        HIPCHK(launch_fill_u64(reinterpret_cast<uint64_t *>(base + B.hdr), kBatchHdr / 8, 0, s));
+        HIPCHK(hipMemcpyAsync(base + B.ops, plan.ops.data(), plan.ops.size() * sizeof(BatchOp),
+                              hipMemcpyHostToDevice, s));
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, s));
+        HIPCHK(launch_batch2d(A, g.K, s));
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipStreamSynchronize(s));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        bool overflow = false, timeout = false, unstable = false;
+        for (int i = 0; i < nshots; ++i) {
+            Dev &d = dv[i];
+            unsigned e = 0;
+            unsigned long long st[2] = {0, 0};
+            double mis = 0.0;
+            HIPCHK(hipMemcpy(&e, d.err, 4, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(st, d.stats, 16, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(&mis, d.misfit, 8, hipMemcpyDeviceToHost));
+            misfits[i] = mis;
+            overflow |= (e & 4u) != 0;
+            timeout |= (e & 16u) != 0;
+            unstable |= (e & (2u | 8u)) != 0;
+            if (stats) {
+                wv_stats &o = stats[i];
+                const int timing = o.timing;
+                std::memset(&o, 0, sizeof(o));
+                o.timing = timing;
+                o.advances = plan.advances;
+                o.stores = plan.stores;
+                o.fields = plan.fields;
+                o.restores = plan.restores;
+                o.decodes = plan.decodes;
+                o.reverses = plan.reverses;
+                o.slots = M;
+                const double raw = (double)plan.fields * (double)(Sd / 2);
+                const bool comp = tol > 0;
+                o.bytes_stored = comp ? (double)st[0] : raw;
+                o.peak_bytes = comp ? (double)st[1] : (double)plan.max_depth * (double)Sp;
+                o.ratio = o.bytes_stored > 0 ? raw / o.bytes_stored : 1.0;
+                o.ratio_planned = F;
+                o.misfit = mis;
+                o.ms_total = ms;
+                o.retries = attempt;
+                if (comp) {
+                    std::vector<uint64_t> sz((size_t)N + 1, 0);
+                    HIPCHK(hipMemcpy(sz.data(), d.sizes, sz.size() * 8, hipMemcpyDeviceToHost));
+                    GradRun R{&models[i], &geoms[i], su[i], dv[i], s, tol, true, false};
+                    R.cd = cd;
+                    profile_from_sizes(sz, N, R.empty_field_bytes(), o.profile);
+                }
+            }
+        }
+        if (timeout) return hip_fail(hipErrorLaunchFailure, "batch2d device-wide barrier timed out", __LINE__);
+        if (overflow && tol > 0 && F > 1.0 && attempt < kArenaRetries) {
+            F = attempt + 1 == kArenaRetries ? 1.0 : std::max(1.0, F / 2);
+            for (int i = 0; i < nshots; ++i) HIPCHK(launch_fill_u64(at<uint64_t>(dv[i].base, dv[i].L.bk), kBk / 8, 0, s));
+            continue;
+        }
+        if (overflow) return WV_EARENA;
+        if (unstable) return WV_EUNSTABLE;
+        return WV_OK;
+    }
 }
 
 int wv_adjoint_src(const wv_model *m, const wv_geom *geo, const float *residual, float *src_adj, void *ws,

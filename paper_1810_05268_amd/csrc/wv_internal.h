@@ -126,4 +126,73 @@ hipError_t launch_encode(const CodecDims &cd, const float *field, const float *s
 hipError_t launch_decode(const CodecDims &cd, const uint8_t *in, const uint64_t *base, uint64_t cap, float *field,
                          const float *sub, hipStream_t s);
 
+// ---------------------------------------------------------------- batched 2-D solver (wv_batch.hip)
+// Several 2-D shots of one grid, order, step count and schedule advanced together by
+// one persistent kernel that runs a program of phases, all shots per phase, with a
+// device-wide barrier between phases.  Each shot keeps the buffers of a solo call
+// (field arrays dense in 2-D).
+struct BatchShot {
+    float *U[2], *UB, *DB, *Lm[2], *Z, *W;
+    const float *wavelet;     // [nt]
+    const float *dobs;        // [nt+1][nrec]
+    float *dsim, *res;        // [nt+1][nrec]
+    double *G;                // gradient (caller's, dense [P])
+    double *partials;         // residual partial sums [kParts]
+    double *misfit;           // phi (device)
+    uint8_t *arena;           // checkpoint memory of this shot
+    uint64_t arena_bytes;
+    uint64_t *offs;           // stream offsets (as the solo executor's)
+    uint64_t *sizes;          // stream bytes of u^k per stored k
+    uint32_t *chunk_words;    // [2][nchunks]: words per chunk of the two fields of a store
+    unsigned *err;            // bit 1: velocity, 2: non-finite input to the codec, 4: arena overflow,
+                              // 8: non-finite wavefield, 16: barrier timeout
+    unsigned long long *stats;  // [0] stream bytes stored, [1] peak arena offset
+    Sparse src, rec;
+};
+
+// Buffers of a program step, by id: the shot's own arrays, or level l of checkpoint
+// slot b (uncompressed) as kBufSlot + 2 b + l.
+enum BatchBuf { kBufZ = 0, kBufU0, kBufU1, kBufUB, kBufDB, kBufL0, kBufL1, kBufNone = 15, kBufSlot = 16 };
+// Program steps.  Every shot executes each one; a device-wide barrier follows each.
+//   kOpFwd:      forward steps n .. d-1 from u^n in a and u^{n-1} in b, each a stencil phase and
+//                a phase that injects the source sample and (for steps s >= e) gathers data row
+//                s+1; the output of each step is the work buffer (kBufU0 / kBufU1) that does not
+//                hold its input, as in the solo executor
+//   kOpAdj:      adjoint step k = n, a = lam^k, b = lam^{k+1} (the output, in place), c = u^k: a
+//                stencil phase with the gradient term, then the residual injection of row k
+//   kOpEncCount: bit counts of the chunks of a store: a = u^k, b = u^{k-1} (kBufNone: one field)
+//   kOpEncEmit:  the store's streams at offs[d] (and offs[d+1] for the second field), next offset at
+//                offs[d+2] (one field) or offs[d+1], offs[d+2]; n = k (stream size recorded), -1 none
+//   kOpDec:      decode the stream at offs[d] into a (b != kBufNone: a = b - decoded)
+//   kOpCopy:     copy field a into b
+//   kOpResid:    residual r = d_sim - d_obs, partial sums of r^2, finiteness of field a
+//   kOpMisfit:   phi = 1/2 sum of the partials
+enum BatchOpKind { kOpNop = 0, kOpFwd, kOpAdj, kOpEncCount, kOpEncEmit, kOpDec, kOpCopy, kOpResid, kOpMisfit };
+struct BatchOp {
+    int32_t kind, n, a, b, c, d, e;
+};
+
+struct BatchArgs {
+    Grid g;
+    CodecDims cd;
+    const BatchShot *shots;
+    int nshots;
+    const BatchOp *ops;
+    int nops;
+    double gscale;
+    double tol;
+    int minexp;
+    int nrec;                 // receivers per shot (every shot of a batch has as many)
+    int src_pts, rec_pts;     // largest scatter-table size over the shots (sources, receivers)
+    int nt;
+    int zlen;                 // rows per stencil work item
+    long long slot_elems;     // elements of one uncompressed checkpoint slot (two fields)
+    unsigned *bar;            // device-wide barrier: [0] arrivals, [64] generation (zero at launch)
+    int nwg;                  // workgroups of the launch (all resident)
+};
+// Workgroups the persistent kernel can keep resident for space order 2K (0 on error).
+int batch2d_resident_workgroups(int K);
+// Cooperative launch of the persistent kernel with A.nwg workgroups.
+hipError_t launch_batch2d(const BatchArgs &A, int K, hipStream_t s);
+
 }  // namespace wv

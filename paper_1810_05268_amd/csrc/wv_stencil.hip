@@ -37,38 +37,12 @@
 // measured 10-15 % slower.  The binary64 gradient belongs to the caller and is dense.
 #include <hip/hip_ext.h>
 
-#include "wv_internal.h"
+#include "wv_stencil_dev.h"
 
 namespace wv {
 
 namespace {
 
-constexpr int kNumXcd = 8;
-
-__device__ __forceinline__ int xcd_remap(int bid, int nwg)
-{
-    // hardware dispatches workgroup i to XCD i % 8; give XCD j a contiguous range
-    int xcd = bid % kNumXcd, loc = bid / kNumXcd;
-    int q = nwg / kNumXcd, r = nwg % kNumXcd;
-    return xcd * q + (xcd < r ? xcd : r) + loc;
-}
-
-__device__ __forceinline__ int layer_depth(int i, int lo, int hi)
-{
-    int a = lo - i, b = i - hi;
-    return a > 0 ? a : (b > 0 ? b : 0);
-}
-
-__device__ __forceinline__ float damping(const Grid &g, int x, int y, int z)
-{
-    int dx = layer_depth(x, g.ix0[0], g.ix1[0]);
-    int dy = layer_depth(y, g.ix0[1], g.ix1[1]);
-    int dz = layer_depth(z, g.ix0[2], g.ix1[2]);
-    return g.dampx * (float)(dx * dx) + g.dampy * (float)(dy * dy) + g.dampz * (float)(dz * dz);
-}
-
-// what a stencil launch does with the Laplacian (see stencil3d)
-constexpr int kOT2 = 0, kLapW = 1, kOT4 = 2;
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
@@ -444,72 +418,12 @@ __global__ __launch_bounds__(256) void stencil2d(Grid g, const float *__restrict
                                                  double gscale, int tiles_x, int zchunks, int zlen)
 {
     static_assert(!(GRAD && MODE == kLapW), "the w lap pass carries no gradient term");
-    constexpr int TX = 256;
-    __shared__ float row[TX + 2 * K];
+    __shared__ float row[256 + 2 * K];
     const int nwg = tiles_x * zchunks;
     const int lid = xcd_remap(blockIdx.x, nwg);
     const int tix = lid % tiles_x, zc = lid / tiles_x;
     const int z0 = zc * zlen, z1 = min(z0 + zlen, g.nz);
-    const int nx = g.nx, nz = g.nz;
-    const int tid = threadIdx.x;
-    const int x = tix * TX + tid;
-    const bool in = x < nx;
-    const float *col = fin + (in ? x : 0);
-    float q[2 * K + 1];
-#pragma unroll
-    for (int j = 0; j < 2 * K; ++j) {
-        const int z = z0 - K + j;
-        q[j] = (in && z >= 0 && z < nz) ? col[(long long)z * nx] : 0.0f;
-    }
-    for (int z = z0; z < z1; ++z) {
-        const int zf = z + K;
-        q[2 * K] = (in && zf < nz) ? col[(long long)zf * nx] : 0.0f;
-        row[tid + K] = q[K];
-        const float *plane = fin + (long long)z * nx;
-        if (tid < K) {
-            const int gl = tix * TX - K + tid;
-            row[tid] = (gl >= 0 && gl < nx) ? plane[gl] : 0.0f;
-            const int gr = tix * TX + TX + tid;
-            row[TX + K + tid] = (gr < nx) ? plane[gr] : 0.0f;
-        }
-        __syncthreads();
-        if (in) {
-            const float c = q[K];
-            float sx = g.cx[1] * ((row[tid + K + 1] - c) + (row[tid + K - 1] - c));
-            float sz = g.cz[1] * ((q[K + 1] - c) + (q[K - 1] - c));
-            if constexpr (K > 1) {
-                float fx = 0.0f, fz = 0.0f;
-#pragma unroll
-                for (int k = 2; k <= K; ++k) {
-                    fx = fmaf(g.cx[k], row[tid + K + k] + row[tid + K - k], fx);
-                    fz = fmaf(g.cz[k], q[K + k] + q[K - k], fz);
-                }
-                sx += fmaf(-g.cf2[0], c, fx);
-                sz += fmaf(-g.cf2[2], c, fz);
-            }
-            const float lap = sx + sz;
-            const long long p = (long long)z * nx + x;
-            const float wp = __builtin_nontemporal_load(&w[p]);
-            if constexpr (MODE == kLapW) {
-                __builtin_nontemporal_store(wp * lap, &fout[p]);
-            } else {
-                const float ctr = MODE == kOT4 ? __builtin_nontemporal_load(&xtra[p]) : c;
-                const float wl = MODE == kOT4 ? fmaf(wp * (1.0f / 12.0f), lap, c) : wp * lap;
-                const float a = damping(g, x, 0, z);
-                const float d = ctr - __builtin_nontemporal_load(&prev[p]);
-                const float dn = (a == 0.0f) ? d + wl : ((1.0f - a) * d + wl) / (1.0f + a);
-                __builtin_nontemporal_store(ctr + dn, &fout[p]);
-                if constexpr (GRAD && MODE == kOT4)
-                    G[p] += gscale * ((double)__builtin_nontemporal_load(&uk[p]) * (double)wl +
-                                      (double)c * (double)__builtin_nontemporal_load(&xtra2[p]) * (1.0 / 12.0));
-                else if constexpr (GRAD)
-                    G[p] += gscale * (double)__builtin_nontemporal_load(&uk[p]) * (double)wl;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 2 * K; ++j) q[j] = q[j + 1];
-    }
+    march2d<K, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, tix, z0, z1, row);
 }
 
 // Adds w s / (1+a) at the source (or receiver) points of the level just written.
@@ -521,26 +435,18 @@ __global__ void inject_kernel(Grid g, Sparse sp, const float *__restrict__ vals,
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= sp.npts) return;
     const int p = sp.s_pts[i];
-    float s = 0.0f;
-    for (int e = sp.s_start[i]; e < sp.s_start[i + 1]; ++e) s = fmaf(sp.s_wt[e], vals[sp.s_col[e]], s);
     const long long sxy = (long long)g.px * g.ny;   // p indexes the pitched field arrays
     const int z = (int)(p / sxy);
     const int rem = (int)(p - z * sxy);
     const int y = rem / g.px, x = rem - (rem / g.px) * g.px;
-    const float a = damping(g, x, y, z);
-    const float wi = w[p] * s;
-    const float inj = (a == 0.0f) ? wi : wi / (1.0f + a);
-    fout[p] += inj;
-    if constexpr (GRAD) G[((long long)z * g.ny + y) * g.nx + x] += gscale * (double)uk[p] * (double)wi;
+    inject_point<GRAD>(g, sp, i, p, x, y, z, vals, w, fout, uk, G, ((long long)z * g.ny + y) * g.nx + x, gscale);
 }
 
 __global__ void gather_kernel(Sparse sp, const float *__restrict__ f, float *__restrict__ out)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= sp.n) return;
-    float s = 0.0f;
-    for (int c = 0; c < sp.nc; ++c) s = fmaf(sp.g_wt[r * sp.nc + c], f[sp.g_idx[r * sp.nc + c]], s);
-    out[r] = s;
+    out[r] = gather_point(sp, r, f);
 }
 
 __global__ void gather_sum_kernel(Sparse sp, const float *__restrict__ f, float *__restrict__ out)

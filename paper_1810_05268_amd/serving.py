@@ -1,11 +1,12 @@
 """Continuous-batching shot-gradient server on one GPU (binding of the C engine).
 
-The engine (``wv_engine_*`` in include/wv.h) admits queued requests first come,
-first served whenever a worker stream and a contiguous slice of the device pool
+The engine (``wv_engine_*`` in include/wv.h) admits queued requests first fit in
+arrival order whenever a worker stream and a contiguous slice of the device pool
 (workspace plus checkpoint arena) are free, and runs the admitted shots
-concurrently on their own HIP streams.  This module owns the pool tensor, keeps
-each request's device buffers alive until it completes, and replays timed request
-streams.  No solver arithmetic happens here.
+concurrently on their own HIP streams; with batching on, 2-D requests that share a
+grid and schedule run together in one persistent launch.  This module owns the pool
+tensor, keeps each request's device buffers alive until it completes, and replays
+timed request streams.  No solver arithmetic happens here.
 """
 from __future__ import annotations
 
@@ -18,7 +19,7 @@ from . import _binding as B
 
 
 class Engine:
-    def __init__(self, pool_bytes: int, max_active: int = 4, device: str = "cuda"):
+    def __init__(self, pool_bytes: int, max_active: int = 4, device: str = "cuda", max_batch: int = 0):
         self.device = torch.device(device)
         self._pool = torch.empty(int(pool_bytes) + 256, dtype=torch.uint8, device=self.device)
         off = (-self._pool.data_ptr()) % 256
@@ -26,6 +27,8 @@ class Engine:
         torch.cuda.synchronize(self.device)
         B._check(B.lib().wv_engine_create(self._pool.data_ptr() + off, int(pool_bytes), int(max_active),
                                           C.byref(self._h)), "wv_engine_create")
+        if max_batch > 1:
+            B._check(B.lib().wv_engine_set_batching(self._h, int(max_batch)), "wv_engine_set_batching")
         self._live = {}
 
     def submit(self, shot, d_obs, mem_budget: int, tol: float = 0.0, ratio_hint: float = 0.0,
