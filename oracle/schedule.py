@@ -203,6 +203,54 @@ def schedule(N: int, M: int, write_min: bool = False) -> np.ndarray:
     return np.asarray(acts, dtype=np.int32).reshape(-1, 3)
 
 
+def peak_bytes(acts: np.ndarray, size) -> float:
+    """Largest total of the checkpoints held at once when stored state x_k takes size[k]
+    bytes (one level per checkpoint; slot 0 holds x_0 and takes nothing)."""
+    held = {}
+    live = peak = 0.0
+    for op, a, b in np.asarray(acts).tolist():
+        if op == STORE:
+            held[b] = float(size[a])
+            live += held[b]
+            peak = max(peak, live)
+        elif op == FREE:
+            live -= held.pop(b)
+    return peak
+
+
+def min_peak(N: int, M: int, size) -> float:
+    """The smallest peak_bytes over every schedule whose splits are all optimal in forward
+    steps (the minimum of recurrence (3)), by exhaustive dynamic programming over the split
+    choices: reversing the segment [a, a + l) with c slots (x_a held below it) and first
+    advance k stores x_{a+k} for the whole reversal of the right part [a + k, a + l) (c - 1
+    slots) and then frees it before the left part [a, a + k) (c slots), so
+        f(a, l, c) = min_{k optimal} max(size[a + k] + f(a + k, l - k, c - 1), f(a, k, c)),
+    f(a, 1, c) = f(a, l, 1) = 0.  Exponential memory in nothing, but O(N^2 M) states:
+    small N only."""
+    from functools import lru_cache
+
+    size = [float(x) for x in size]
+
+    @lru_cache(maxsize=None)
+    def opt(l: int, c: int) -> tuple[int, ...]:
+        k = np.arange(1, l, dtype=np.int64)
+        cost = k + _closed_vec(k, c) + _closed_vec(l - k, c - 1)
+        return tuple(int(x) for x in k[cost == cost.min()])
+
+    @lru_cache(maxsize=None)
+    def f(a: int, l: int, c: int) -> float:
+        if l <= 1 or c <= 1:
+            return 0.0
+        return min(max(size[a + k] + f(a + k, l - k, c - 1), f(a, k, c)) for k in opt(l, c))
+
+    old = sys.getrecursionlimit()
+    sys.setrecursionlimit(max(old, 50 * (N + M) + 1000))
+    try:
+        return f(0, N + 1, M)
+    finally:
+        sys.setrecursionlimit(old)
+
+
 def counts(acts: np.ndarray) -> dict:
     """advances (forward steps), stores, restores, reverses, peak slot depth."""
     a = np.asarray(acts)

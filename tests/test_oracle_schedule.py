@@ -150,3 +150,27 @@ def test_write_min_pinned_counts(N, M, t, Wn):
     assert c["advances"] == t == SC.p_closed(N + 1, M)
     assert c["stores"] == Wn
     assert c["reverses"] == N
+
+
+def test_smallest_split_minimises_the_peak_of_growing_streams():
+    """Compressed checkpoints grow over a run (the wavefield spreads), and the schedule
+    compressed gradient calls run takes the smallest optimal first advance at every split.
+    For any nondecreasing stream sizes that schedule's peak arena equals the smallest peak
+    over every step-optimal schedule, found by exhaustive dynamic programming over the
+    split choices: no other choice of optimal splits lets more slots fit a budget."""
+    rng = np.random.default_rng(21)
+    for N, M in [(30, 3), (40, 5), (60, 4), (80, 8), (120, 6), (90, 12)]:
+        for _ in range(3):
+            size = np.cumsum(rng.uniform(0.0, 1.0, N + 1)) + rng.uniform(0.1, 2.0)
+            acts = SC.schedule(N, M)
+            assert SC.counts(acts)["advances"] == SC.p_closed(N + 1, M)
+            assert SC.peak_bytes(acts, size) == pytest.approx(SC.min_peak(N, M, size), rel=1e-12)
+
+
+def test_split_choice_matters_for_shrinking_streams():
+    """The rule is not vacuous: with stream sizes that fall over the run, some other
+    choice of optimal splits holds a smaller peak than the smallest splits do."""
+    N, M = 60, 4
+    size = np.linspace(10.0, 1.0, N + 1)
+    acts = SC.schedule(N, M)
+    assert SC.min_peak(N, M, size) < SC.peak_bytes(acts, size) - 1e-9
