@@ -475,6 +475,20 @@ int wv_choose(int nt, long long points, size_t mem_budget, const wv_costs *plain
  * launches, in GB/s (bytes read plus written).  Synchronises the stream. */
 int wv_stream_ceiling(int reads, size_t stream_bytes, void *ws, size_t ws_bytes, int reps, double *gbs, void *stream);
 
+/* wv_misfit_gradient with the choice of wv_choose made per call: the run-time model,
+ * fed with the per-unit costs of earlier calls (plain and compressed, as wv_choose takes
+ * them) and, when given, the compressibility profile of an earlier compressed call of
+ * this shot and tolerance, predicts plain Revolve and compressed checkpoints at this
+ * budget; the call then runs the faster, compressed at tol with the planning ratio of
+ * the choice (so M is the choice's slot count), or plain (tol ignored).  *choice
+ * (nullable) receives the decision and both predictions.  Errors as wv_choose and
+ * wv_misfit_gradient; tol must be > 0 (the tolerance stays the caller's: it is an
+ * accuracy choice, not a speed one). */
+int wv_misfit_gradient_auto(const wv_model *model, const wv_geom *geom, const float *d_obs, size_t mem_budget,
+                            double tol, const wv_costs *plain, const wv_costs *compressed, const double *profile,
+                            int nprofile, double *misfit, double *grad_m, float *d_sim, wv_stats *stats,
+                            wv_choice *choice, void *ws, size_t ws_bytes, void *stream);
+
 const char *wv_strerror(int code);
 
 /* Detail of the last WV_EHIP returned on the calling thread: the failing runtime

@@ -92,7 +92,7 @@ class WvResult(C.Structure):
 # every symbol include/wv.h declares
 SYMBOLS = ["wv_cfl_dt", "wv_cfl_dt_to", "wv_workspace_bytes", "wv_field_elements", "wv_forward", "wv_gradient", "wv_misfit_gradient", "wv_adjoint_src",
            "wv_pad_velocity", "wv_velocity_gradient", "wv_zfpk_workspace_bytes", "wv_zfpk_max_bytes",
-           "wv_zfpk_encode", "wv_zfpk_encode_noalloc", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_predict", "wv_choose", "wv_plan", "wv_compressibility", "wv_stream_ceiling", "wv_strerror",
+           "wv_zfpk_encode", "wv_zfpk_encode_noalloc", "wv_zfpk_decode", "wv_schedule", "wv_schedule_forward_steps", "wv_predict", "wv_choose", "wv_plan", "wv_compressibility", "wv_stream_ceiling", "wv_misfit_gradient_auto", "wv_strerror",
            "wv_last_error", "wv_version", "wv_batch_workspace_bytes", "wv_batch_misfit_gradient", "wv_engine_create", "wv_engine_set_batching", "wv_engine_submit", "wv_engine_wait",
            "wv_engine_pending", "wv_engine_destroy"]
 
@@ -147,6 +147,9 @@ def lib():
         L.wv_batch_misfit_gradient.argtypes = [C.c_int, mp, gp, C.POINTER(C.c_void_p), sz, C.c_double, C.c_double,
                                                C.POINTER(C.c_double), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                                stp, vp, sz, vp]
+        L.wv_misfit_gradient_auto.argtypes = [mp, gp, vp, sz, C.c_double, C.POINTER(WvCosts), C.POINTER(WvCosts),
+                                              C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double), vp, vp, stp,
+                                              C.POINTER(WvChoice), vp, sz, vp]
         L.wv_stream_ceiling.argtypes = [C.c_int, sz, vp, sz, C.c_int, C.POINTER(C.c_double), vp]
         L.wv_strerror.argtypes = [C.c_int]
         L.wv_strerror.restype = C.c_char_p
@@ -396,6 +399,23 @@ def batch_misfit_gradient(pbs, d_obs, mem_budget: int, tol: float, grads, ws, ra
                                           phis, gs, ds, sts, _ptr(ws), ws.numel() * ws.element_size(),
                                           _stream(stream)), "wv_batch_misfit_gradient")
     return [float(phis[i]) for i in range(n)], [sts[i].as_dict() for i in range(n)]
+
+
+def misfit_gradient_auto(pb: Problem, d_obs, mem_budget: int, tol: float, plain: dict, compressed: dict, grad, ws,
+                         profile=None, slot_bytes: float = 0.0, d_sim=None, stream=None) -> tuple[float, dict, dict]:
+    """wv_misfit_gradient_auto: the model's choice of plain or compressed checkpoints made
+    per call from earlier calls' costs (as costs_from_stats returns them).  Returns
+    (misfit, stats, choice)."""
+    cp = WvCosts(plain["c_f"], plain["c_r"], plain.get("t_store", 0.0), 0.0, 0.0, 1.0, float(slot_bytes))
+    cc = WvCosts(compressed["c_f"], compressed["c_r"], 0.0, compressed.get("t_store", 0.0), compressed.get("t_d", 0.0),
+                 float(compressed.get("ratio", 0.0)), 0.0)
+    prof = (C.c_double * 17)(*[float(x) for x in profile]) if profile is not None else None
+    st, ch, phi = WvStats(), WvChoice(), C.c_double(0.0)
+    _check(lib().wv_misfit_gradient_auto(C.byref(pb.model), C.byref(pb.geom), _ptr(d_obs), int(mem_budget),
+                                         float(tol), C.byref(cp), C.byref(cc), prof, 17 if profile is not None else 0,
+                                         C.byref(phi), _ptr(grad), _ptr(d_sim), C.byref(st), C.byref(ch), _ptr(ws),
+                                         ws.numel() * ws.element_size(), _stream(stream)), "wv_misfit_gradient_auto")
+    return float(phi.value), st.as_dict(), ch.as_dict()
 
 
 def adjoint_src(pb: Problem, residual, src_adj, ws, stream=None) -> None:

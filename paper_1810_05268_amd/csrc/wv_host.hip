@@ -1854,6 +1854,22 @@ int wv_batch_misfit_gradient(int nshots, const wv_model *models, const wv_geom *
     }
 }
 
+int wv_misfit_gradient_auto(const wv_model *m, const wv_geom *geo, const float *d_obs, size_t mem_budget, double tol,
+                            const wv_costs *plain, const wv_costs *compressed, const double *profile, int nprofile,
+                            double *misfit, double *grad_m, float *d_sim, wv_stats *stats, wv_choice *choice,
+                            void *ws, size_t ws_bytes, void *stream)
+{
+    if (!m || !(tol > 0) || !std::isfinite(tol)) return WV_EINVAL;
+    const long long points = (long long)(m->n[0] + 2 * m->nbl) * (m->n[1] + 2 * m->nbl) *
+                             (m->ndim == 3 ? (long long)(m->n[2] + 2 * m->nbl) : 1LL);
+    wv_choice ch{};
+    int rc = wv_choose(m->nt, points, mem_budget, plain, compressed, profile, nprofile, &ch);
+    if (rc) return rc;
+    if (choice) *choice = ch;
+    return wv_misfit_gradient(m, geo, d_obs, mem_budget, ch.compressed ? tol : 0.0, ch.compressed ? ch.ratio_hint : 0.0,
+                              misfit, grad_m, d_sim, stats, ws, ws_bytes, stream);
+}
+
 int wv_adjoint_src(const wv_model *m, const wv_geom *geo, const float *residual, float *src_adj, void *ws,
                    size_t ws_bytes, void *stream)
 {

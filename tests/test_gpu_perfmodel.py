@@ -76,3 +76,36 @@ def test_model_chooses_the_faster_strategy():
         if expect is not None:
             assert ch["compressed"] == expect
         assert t[ch["compressed"]] <= 1.05 * min(t.values())
+
+
+def test_misfit_gradient_auto_takes_the_models_choice():
+    """wv_misfit_gradient_auto makes wv_choose's decision per call, from the costs and the
+    profile of earlier calls: at 2 slots it compresses (plain Revolve would recompute
+    quadratically), with every state in memory it runs plain Revolve, and each result is
+    bit-identical to the explicit call it chose."""
+    import torch
+    import paper_1810_05268_amd as P
+    from paper_1810_05268_amd.shot import DeviceShot
+    shot = W.layered_noise_3d(n=(120, 112, 104), nt=400, order=8)
+    G, dt = gpu_side(shot)
+    q = W.ricker(shot.f0, dt, shot.nt).astype(np.float32)
+    Gt = DeviceShot(3, shot.n, shot.h, shot.nbl, shot.order, shot.nt, dt, shot.vmax, shot.padded("true"), q,
+                    shot.src, shot.rec)
+    d_obs = Gt.forward()
+    del Gt
+    tol = 1e-4
+    G.misfit_gradient(d_obs, 20 * G.slot_bytes, timing=1)                          # warm-up
+    _, _, sp = G.misfit_gradient(d_obs, 20 * G.slot_bytes, timing=1)
+    _, _, sc = G.misfit_gradient(d_obs, 20 * G.slot_bytes, tol, ratio_hint=8.0, timing=1)
+    cp, cc = P.costs_from_stats(sp), P.costs_from_stats(sc)
+    for slots, expect in ((2, 1), (shot.nt, 0)):
+        budget = slots * G.slot_bytes
+        g = torch.empty(G.shape, dtype=torch.float64, device="cuda")
+        phi, st, ch = P.misfit_gradient_auto(G.pb, d_obs, budget, tol, cp, cc, g, G.workspace(1, budget),
+                                             profile=sc["profile"], slot_bytes=G.slot_bytes)
+        print(f"{slots} slots: {'compressed' if ch['compressed'] else 'plain'}, M {st['slots']}, "
+              f"predicted plain {ch['ms_plain']:.1f} ms, compressed {ch['ms_compressed']:.1f} ms")
+        assert ch["compressed"] == expect and st["slots"] == ch["slots"]
+        phi2, g2, st2 = G.misfit_gradient(d_obs, budget, tol if expect else 0.0,
+                                          ratio_hint=ch["ratio_hint"] if expect else 0.0)
+        assert phi2 == phi and torch.equal(g2, g) and st2["slots"] == st["slots"]
