@@ -39,25 +39,41 @@ __device__ __forceinline__ float *batch_buf(const BatchShot &S, int id, long lon
     }
 }
 
-// Device-wide barrier of the persistent launch (all workgroups resident).  Arrivals are
-// counted in bar[0]; the last arrival resets it and advances the generation bar[64];
-// the others wait for that with a bounded spin (past the bound: err bit 16, and the
-// kernel runs on to its end).  The agent-scope fences make every write of the phase
-// visible to every workgroup of the next.
+// Device-wide barrier of the persistent launch (all workgroups resident).  Two levels:
+// workgroup b arrives at the counter of its group b % 8 (the XCD it runs on under
+// round-robin dispatch), the last arrival of a group at the top counter, and the last of
+// those resets it and advances the generation; everyone else waits for the generation
+// to move, with a bounded spin (past the bound: err bit 16, and the kernel runs on to its
+// end).  Counters, top and generation sit 1 KB apart so that arrivals of different
+// groups and the polling do not meet on one line.  Memory order: a release fence before
+// each arrival, acquire + release fences around the group's and the top's last arrival,
+// relaxed polling (an acquire poll would invalidate the L2 on every spin) and one acquire
+// fence after the wait, so every write of the phase is visible to every workgroup of the
+// next.
 __device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned nwg, unsigned *err)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned *count = bar, *gen = bar + 64;
+        const unsigned ng = nwg < 8u ? nwg : 8u;
+        const unsigned grp = blockIdx.x & 7u;
+        const unsigned in_grp = (nwg - grp + 7u) / 8u;
+        unsigned *sub = bar + 256u * grp, *top = bar + 2048, *gen = bar + 3072;
         const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nwg - 1) {
-            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        bool waiting = true;
+        if (__hip_atomic_fetch_add(sub, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == in_grp - 1u) {
+            __hip_atomic_store(sub, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            if (__hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ng - 1u) {
+                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                waiting = false;
+            }
+        }
+        if (waiting) {
             unsigned spins = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
                 if (++spins > (1u << 24)) {
                     atomicOr(err, 16u);
                     break;
@@ -65,7 +81,7 @@ __device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned nwg, unsign
                 __builtin_amdgcn_s_sleep(2);
             }
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
@@ -133,55 +149,58 @@ __device__ __forceinline__ void for_items(const BatchArgs &A, int per, Body body
     }
 }
 
-// stencil phase of one forward (GRAD false) or adjoint (GRAD true) step
+// One forward (GRAD false) or adjoint (GRAD true) step of every shot, injections fused.
+// Items [0, st_items) of a shot march one z-chunk of one 256-column tile, then add the
+// injections whose grid point lies in that chunk and tile: the source's sample n into
+// `out` (forward), or the residual's row n into `out` with its gradient term (adjoint).
+// Every point has one owner, and its value is the stencil's and then the injection's, as
+// in the solo solver.  Item st_items of a shot gathers the receivers of `gin` into data
+// row `grow` (if grow >= 0): the deferred gather of the previous step's output, which
+// nothing writes during this step.
 template <int K, bool GRAD>
-__device__ __forceinline__ void phase_stencil(const BatchCtx &C, int fin, int prev, int out, int uk, float *s_row)
+__device__ __forceinline__ void phase_step(const BatchCtx &C, int fin, int prev, int out, int uk, int n, int gin,
+                                           int grow, float *s_row)
 {
     const BatchArgs &A = C.A;
-    for_items(A, C.st_items, [&](const BatchShot &S, int j) {
+    const int tid = threadIdx.x, nx = C.g.nx;
+    for_items(A, C.st_items + 1, [&](const BatchShot &S, int j) {
+        if (j == C.st_items) {
+            if (grow >= 0) {
+                const float *f = batch_buf(S, gin, A.slot_elems, C.P);
+                for (int r = tid; r < A.nrec; r += 256) S.dsim[(long long)grow * A.nrec + r] = gather_point(S.rec, r, f);
+            }
+            return;
+        }
         const int tix = j % C.tiles_x, zc = j / C.tiles_x;
         const int z0 = zc * A.zlen, z1 = min(z0 + A.zlen, C.g.nz);
-        march2d<K, GRAD, kOT2>(C.g, batch_buf(S, fin, A.slot_elems, C.P), batch_buf(S, prev, A.slot_elems, C.P),
-                               batch_buf(S, out, A.slot_elems, C.P), S.W,
-                               GRAD ? batch_buf(S, uk, A.slot_elems, C.P) : nullptr, nullptr, nullptr,
-                               GRAD ? S.G : nullptr, GRAD ? A.gscale : 0.0, tix, z0, z1, s_row);
-    });
-}
-
-// One workgroup per shot: the source injection of sample n into `out`, then (row >= 0)
-// the receiver gather of data row `row` from it; the barrier between them makes the
-// injected values visible to the gather.
-__device__ __forceinline__ void phase_inject_src(const BatchCtx &C, int n, int out, int row)
-{
-    const BatchArgs &A = C.A;
-    const int tid = threadIdx.x;
-    for_items(A, 1, [&](const BatchShot &S, int) {
         float *f = batch_buf(S, out, A.slot_elems, C.P);
-        for (int i = tid; i < S.src.npts; i += 256) {
-            const int p = S.src.s_pts[i];
-            const int z = p / C.g.nx, x = p - (p / C.g.nx) * C.g.nx;
-            inject_point<false>(C.g, S.src, i, p, x, 0, z, S.wavelet + n, S.W, f, nullptr, nullptr, p, 0.0);
+        const float *u = GRAD ? batch_buf(S, uk, A.slot_elems, C.P) : nullptr;
+        march2d<K, GRAD, kOT2>(C.g, batch_buf(S, fin, A.slot_elems, C.P), batch_buf(S, prev, A.slot_elems, C.P), f,
+                               S.W, u, nullptr, nullptr, GRAD ? S.G : nullptr, GRAD ? A.gscale : 0.0, tix, z0, z1,
+                               s_row);
+        __syncthreads();
+        const Sparse &sp = GRAD ? S.rec : S.src;
+        const int x0 = tix * 256, x1 = min(x0 + 256, nx);
+        for (int i = tid; i < sp.npts; i += 256) {
+            const int p = sp.s_pts[i];
+            const int z = p / nx, x = p - z * nx;
+            if (z < z0 || z >= z1 || x < x0 || x >= x1) continue;
+            if constexpr (GRAD)
+                inject_point<true>(C.g, sp, i, p, x, 0, z, S.res + (long long)n * A.nrec, S.W, f, u, S.G, p,
+                                   A.gscale);
+            else
+                inject_point<false>(C.g, sp, i, p, x, 0, z, S.wavelet + n, S.W, f, nullptr, nullptr, p, 0.0);
         }
-        __syncthreads();
-        if (row >= 0)
-            for (int r = tid; r < A.nrec; r += 256) S.dsim[(long long)row * A.nrec + r] = gather_point(S.rec, r, f);
-        __syncthreads();
     });
 }
 
-// One workgroup per shot: residual injection of row k into lam with the gradient term.
-__device__ __forceinline__ void phase_inject_res(const BatchCtx &C, int k, int lam, int uk)
+// One workgroup per shot: the receivers of `gin` into data row `grow`.
+__device__ __forceinline__ void phase_gather(const BatchCtx &C, int gin, int grow)
 {
     const BatchArgs &A = C.A;
-    const int tid = threadIdx.x;
     for_items(A, 1, [&](const BatchShot &S, int) {
-        float *f = batch_buf(S, lam, A.slot_elems, C.P);
-        const float *u = batch_buf(S, uk, A.slot_elems, C.P);
-        for (int i = tid; i < S.rec.npts; i += 256) {
-            const int p = S.rec.s_pts[i];
-            const int z = p / C.g.nx, x = p - (p / C.g.nx) * C.g.nx;
-            inject_point<true>(C.g, S.rec, i, p, x, 0, z, S.res + (long long)k * A.nrec, S.W, f, u, S.G, p, A.gscale);
-        }
+        const float *f = batch_buf(S, gin, A.slot_elems, C.P);
+        for (int r = threadIdx.x; r < A.nrec; r += 256) S.dsim[(long long)grow * A.nrec + r] = gather_point(S.rec, r, f);
     });
 }
 
@@ -434,22 +453,26 @@ __global__ __launch_bounds__(256) void batch2d_kernel(BatchArgs A)
         const BatchOp op = A.ops[oi];
         switch (op.kind) {
         case kOpFwd: {
-            int fin = op.a, prev = op.b;
+            // step n writes u^{n+1}; its gather (n >= op.e) runs in the next step's phase,
+            // or in a phase of its own after the last step
+            int fin = op.a, prev = op.b, grow = -1, gin = kBufNone;
             for (int n = op.n; n < op.d; ++n) {
                 const int out = fin == kBufU0 ? kBufU1 : kBufU0;
-                phase_stencil<K, false>(C, fin, prev, out, kBufNone, s_row);
+                phase_step<K, false>(C, fin, prev, out, kBufNone, n, gin, grow, s_row);
                 barrier();
-                phase_inject_src(C, n, out, n >= op.e ? n + 1 : -1);
-                barrier();
+                grow = n >= op.e ? n + 1 : -1;
+                gin = out;
                 prev = fin;
                 fin = out;
+            }
+            if (grow >= 0) {
+                phase_gather(C, gin, grow);
+                barrier();
             }
             break;
         }
         case kOpAdj:
-            phase_stencil<K, true>(C, op.a, op.b, op.b, op.c, s_row);
-            barrier();
-            phase_inject_res(C, op.n, op.b, op.c);
+            phase_step<K, true>(C, op.a, op.b, op.b, op.c, op.n, kBufNone, -1, s_row);
             barrier();
             break;
         case kOpEncCount:

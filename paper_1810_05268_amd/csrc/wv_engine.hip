@@ -262,9 +262,10 @@ struct wv_engine {
                     return true;
                 });
                 if (batch.empty()) return;   // stopping
+                const Clock::time_point t0 = Clock::now();   // one start time per batch
                 for (Request *r : batch) {
                     queue.erase(std::find(queue.begin(), queue.end(), r));
-                    r->t_start = Clock::now();
+                    r->t_start = t0;
                 }
                 active += (int)batch.size();
             }

@@ -1494,7 +1494,7 @@ int wv_misfit_gradient(const wv_model *m, const wv_geom *geo, const float *d_obs
 // ------------------------------------------------------------------ batched 2-D shots
 namespace {
 
-constexpr size_t kBatchHdr = 4096;   // barrier words of the persistent launch
+constexpr size_t kBatchHdr = 16384;   // barrier counters of the persistent launch, bytes
 
 // program steps for the schedule acts, with the solo executor's bookkeeping (which
 // buffer holds each level, when the second level is decoded, which data rows the first
@@ -1757,10 +1757,26 @@ int wv_batch_misfit_gradient(int nshots, const wv_model *models, const wv_geom *
     }
     A.nrec = geoms[0].nrec;
     A.nt = N;
-    A.zlen = 16;
+    // Launch shape.  Every workgroup takes part in every grid barrier, whose cost grows
+    // with the number of arrivals, so the grid is no larger than the widest phase needs:
+    // a step phase takes one item per z-chunk of a 256-column tile (16 rows, halved down
+    // to 4 while the batch has fewer chunks than twice the CU count) plus one gather item
+    // per shot, and the codec phases one item per 256-block chunk and field.  Phases
+    // with more items loop over them.
+    {
+        int cus = 0, dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const long long tiles_x = (g.nx + 255) / 256;
+        auto chunks = [&](int zl) { return (long long)nshots * tiles_x * ((g.nz + zl - 1) / zl); };
+        int zl = 16;
+        while (zl > 4 && chunks(zl) < 2LL * cus) zl /= 2;
+        A.zlen = zl;
+        const long long widest = std::max(chunks(zl) + nshots, (long long)nshots * 2 * cd.nchunks);
+        A.nwg = (int)std::min<long long>(nwg, std::max<long long>(widest, 8));
+    }
     A.slot_elems = (long long)su[0].Pf * 2;
     A.bar = reinterpret_cast<unsigned *>(base + B.hdr);
-    A.nwg = nwg;
     for (int i = 0; i < nshots; ++i) {
         A.src_pts = std::max(A.src_pts, shots[i].src.npts);
         A.rec_pts = std::max(A.rec_pts, shots[i].rec.npts);
