@@ -274,6 +274,47 @@ def kernels_mode():
                       "points": G.P}), flush=True)
 
 
+def codec_kernels_mode(nt=1500, tol=1e-4, reps=5):
+    """Short workload for the codec's counter and trace passes: the large shot's forward
+    run to step nt (a mid-run state, compressed about 70x at 1e-4), then `reps` encodes
+    and decodes of u^nt alone and `reps` encodes of u^nt - u^(nt-1) (the second-level
+    form the compressed reversal stores)."""
+    import numpy as np
+    import torch
+
+    import paper_1810_05268_amd as P
+    import workloads as W
+    from paper_1810_05268_amd.shot import DeviceShot
+    shot = W.fault_body_3d(nt=nt)
+    dt = shot.cfl_frac * P.cfl_dt(shot.ndim, shot.h, shot.order, shot.vmax)
+    q = W.ricker(shot.f0, dt, nt).astype(np.float32)
+    G = DeviceShot(3, shot.n, shot.h, shot.nbl, shot.order, nt, dt, shot.vmax, shot.padded("vel"), q,
+                   shot.src, shot.rec)
+    data, state = G.forward(want_state=True)
+    u, up = state[0].contiguous(), state[1].contiguous()
+    del data, state, G
+    dims = list(reversed(u.shape))
+    cap = P.zfpk_max_bytes(3, dims)
+    out = torch.zeros(cap, dtype=torch.uint8, device="cuda")
+    wsb = P.zfpk_workspace_bytes(3, dims)
+    ws = torch.zeros(wsb + 256, dtype=torch.uint8, device="cuda")
+    wso = (-ws.data_ptr()) % 256
+    dec = torch.empty_like(u)
+    nb = 0
+    for _ in range(reps):
+        nb = P.zfpk_encode(u, tol, out, ws[wso: wso + wsb])
+    for _ in range(reps):
+        P.zfpk_decode(out, dec, nbytes=nb)
+    d = u - up                       # the same binary32 difference the reversal's encoder forms
+    nbd = 0
+    for _ in range(reps):
+        nbd = P.zfpk_encode(d, tol, out, ws[wso: wso + wsb])
+    torch.cuda.synchronize()
+    print(json.dumps({"codec_kernels": f"forward {nt} steps, then encode x{reps}, decode x{reps}, encode of the "
+                      f"difference x{reps}", "tol": tol, "field_bytes": 4 * u.numel(), "stream_bytes": nb,
+                      "diff_stream_bytes": nbd, "ratio": 4 * u.numel() / nb}), flush=True)
+
+
 PROFILED_PER_CLASS = 3
 
 
@@ -523,11 +564,15 @@ def main():
     ap.add_argument("--serving-saturation", default="2,4,8,16", help="rate multiples of the saturation runs "
                                                                       "('' = none)")
     ap.add_argument("--kernels", action="store_true", help="short kernel workload for counter passes only")
+    ap.add_argument("--codec-kernels", action="store_true", help="short codec workload for counter passes only")
     ap.add_argument("--no-ot4", action="store_true", help="skip the OT4 comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of it"}))
         sys.exit(2)
+    if args.codec_kernels:
+        codec_kernels_mode()
+        return
     if args.kernels:
         kernels_mode()
         return

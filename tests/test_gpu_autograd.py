@@ -105,16 +105,22 @@ def test_smooth_random_full_size_against_oracle_and_finite_differences():
         the call planned, replayed by the oracle's compressed reversal on the same schedule
         for the same residual; the codec's share of the gradient matches
         (check_codec_parity).
-    Finite differences, per direction (the normalised gradient and 10 seeded smooth unit
-    directions, white noise filtered by a Gaussian of 10 cells): a Richardson-extrapolated
-    central difference of the GPU misfit, R = (4 D(eps/2) - D(eps)) / 3 with
-    D(e) = (phi(v + e dv) - phi(v - e dv)) / (2 e) and eps = 1e-3 ||v|| (truncation
-    O(eps^4)), against the GPU adjoint's directional derivative <g, dv> (the same misfit
-    function); the oracle's is reported beside it.  The binary32 floor of R is
-    3 dphi / eps, dphi = |phi_gpu - phi_oracle| (each of the four misfits is within dphi of
-    exact and R weighs them by 4/(3 eps) and 1/(6 eps)); every direction whose derivative
-    exceeds 10 times that floor must agree to 1e-3 relative plus the floor, and the others
-    are reported."""
+    Finite differences, per direction (the normalised gradient and 20 seeded smooth unit
+    directions, white noise filtered by a Gaussian of 10 cells): the GPU misfit at
+    v + s eps dv for s = 0, +-1/8, ..., +-1 (eps = 1e-3 ||v||) and a least-squares
+    polynomial of degree 7 in s through the 17 values; its linear coefficient / eps is the
+    derivative (truncation O(eps^8): along these directions a 1e-3 ||v|| step shifts the
+    waveforms by a sizeable fraction of a period, and a Richardson central difference,
+    printed beside it, keeps an O(eps^4) term of the size of the small derivatives).  The
+    fit's residuals along the random directions measure the misfit's binary32 rounding
+    noise sigma (pooled, 180 degrees of freedom); the fitted derivative then has std
+    2.77 sigma / eps, and the floor is three of those.  In every direction whose exact
+    derivative (the oracle's <g, dv>) exceeds 10 times the floor, the fitted derivative
+    must agree with it to 1e-3 relative plus the floor; along the gradient it must also
+    agree so with the GPU adjoint's <g, dv>.  (In the random directions the GPU
+    gradient's own error, the residual's rounding e_r mapped by the adjoint, is of the
+    size of these small derivatives' floor; it is reported per direction, and the adjoint
+    itself is checked above on the oracle's residual.)"""
     import torch
     import paper_1810_05268_amd.autograd as A
     from paper_1810_05268_amd.autograd import WaveProblem
@@ -184,7 +190,9 @@ def test_smooth_random_full_size_against_oracle_and_finite_differences():
     phim, gmm, _ = Gm.misfit_gradient(torch.as_tensor(d_obs, device="cuda"), 20 * Sb)
     assert phim == phi0
     del Gm
-    assert rel_l2(g0, pad_adjoint(-2.0 * gmm.cpu().numpy() / vp ** 3, shot.nbl)) <= 1e-12
+    # vel.grad is stored in vel's dtype (float32): each element is rounded once, so the
+    # relative L2 difference is at most the unit roundoff 2^-24 (plus the FP64 rounding)
+    assert rel_l2(g0, pad_adjoint(-2.0 * gmm.cpu().numpy() / vp ** 3, shot.nbl)) <= 2.0 ** -24 + 1e-12
     pbc = problem(20 * Sb, 1e-5)
     phic, gc, stc = run(pbc)
     e_gc = rel_l2(gc, g0)
@@ -200,33 +208,45 @@ def test_smooth_random_full_size_against_oracle_and_finite_differences():
         with torch.no_grad():
             return float(A.wave_misfit(v.float(), pbc))
 
-    def richardson(dv, eps):
-        def D(e):
-            return (misfit_at(v0 + e * dv) - misfit_at(v0 - e * dv)) / (2 * e)
-        return (4.0 * D(eps / 2) - D(eps)) / 3.0
-
     dphi = abs(phic - phi_or)
     eps = 1e-3 * vnorm
-    floor = 3.0 * dphi / eps
+    sg = np.arange(-8, 9) / 8.0                   # t = s eps, s = 0, +-1/8, ..., +-1
+    X = np.stack([sg ** k for k in range(8)], 1)
+    XtXi = np.linalg.inv(X.T @ X)
     gvo = torch.as_tensor(gv_or, device="cuda")
     dirs = [gvo / torch.linalg.vector_norm(gvo)]
-    for seed in range(30, 40):
+    for seed in range(30, 50):
         noise = np.random.default_rng(seed).standard_normal(tuple(shot.vel.shape))
         dv = torch.as_tensor(gaussian_filter(noise, sigma=10.0, mode="reflect"), device="cuda")
         dirs.append(dv / torch.linalg.vector_norm(dv))
-    checked = 0
+    rows, rss = [], 0.0
     for j, dv in enumerate(dirs):
-        ad_or = float(torch.sum(gvo * dv))
-        ad = float(torch.sum(gcd * dv))
-        fd = richardson(dv, eps)
-        big = abs(ad) >= 10.0 * floor
-        print(f"direction {j}: fd {fd:+.6e} adjoint {ad:+.6e} oracle {ad_or:+.6e}  |fd-ad|/|ad| "
-              f"{abs(fd - ad) / abs(ad):.2e}  |ad-or|/|or| {abs(ad - ad_or) / abs(ad_or):.2e}  floor/|ad| "
-              f"{floor / abs(ad):.2e}{'' if big else '  (below 10x the floor: reported only)'}")
+        ph = np.array([phic if s_ == 0.0 else misfit_at(v0 + (s_ * eps) * dv) for s_ in sg])
+        coef = XtXi @ (X.T @ ph)                  # least-squares degree-7 polynomial in s
+        fd = coef[1] / eps
+        rich = (4.0 * (ph[12] - ph[4]) / eps - (ph[16] - ph[0]) / (2 * eps)) / 3.0
+        if j > 0:
+            rss += float(np.sum((ph - X @ coef) ** 2))
+        rows.append((j, fd, rich, float(torch.sum(gcd * dv)), float(torch.sum(gvo * dv))))
+    dof = (len(sg) - 8) * (len(dirs) - 1)
+    sigma = (rss / dof) ** 0.5
+    se = np.sqrt(XtXi[1, 1]) * sigma / eps       # std of the fitted derivative: 2.77 sigma / eps
+    floor = 3.0 * se
+    print(f"misfit rounding noise: sigma {sigma:.3e} ({dof} dof; |phi - oracle| at v0: {dphi:.3e}); "
+          f"FD std {se:.3e}, floor {floor:.3e}")
+    checked = 0
+    for j, fd, rich, ad, ad_or in rows:
+        big = abs(ad_or) >= 10.0 * floor
+        print(f"direction {j}: fd {fd:+.6e} (Richardson {rich:+.6e}) adjoint {ad:+.6e} oracle {ad_or:+.6e}  "
+              f"|fd-or|/|or| {abs(fd - ad_or) / abs(ad_or):.2e}  |fd-ad|/|ad| {abs(fd - ad) / abs(ad):.2e}  "
+              f"|ad-or|/|or| {abs(ad - ad_or) / abs(ad_or):.2e}  floor/|or| {floor / abs(ad_or):.2e}"
+              f"{'' if big else '  (below 10x the floor: reported only)'}")
         if big:
             checked += 1
+            assert abs(fd - ad_or) <= 1e-3 * abs(ad_or) + floor
+        if j == 0:
             assert abs(fd - ad) <= 1e-3 * abs(ad) + floor
-    assert checked >= 6
+    assert checked >= 8
     # along the gradient a plain central difference converges quadratically
     gn = float(torch.sum(gcd * dirs[0]))
 
