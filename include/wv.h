@@ -243,7 +243,8 @@ int wv_velocity_gradient(int ndim, const int *n, int nbl, const float *vel_padde
  * separable lifting transform of trunc(x 2^(30-emax)), with group tests.
  * Guarantees |x - decode(encode(x))| <= tol where binary32 can resolve tol. */
 
-/* Device scratch bytes wv_zfpk_encode needs (chunk status words). */
+/* Device scratch bytes wv_zfpk_encode needs (per chunk of 256 blocks: its word count,
+ * its offset and an 8 KiB staging slot). */
 size_t wv_zfpk_workspace_bytes(int ndim, const int *dims);
 
 /* Upper bound of the stream size for these dims (any tolerance). */
@@ -258,13 +259,14 @@ int wv_zfpk_encode(const float *field, int ndim, const int *dims, double tol, vo
 
 /* wv_zfpk_encode for callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same encoder and
- * the same stream, with no workspace argument.  Its scratch (bookkeeping and chunk
- * status words) is a fixed 128 KiB array in device memory that each GPU the library
- * runs on holds until the process ends; the call allocates and frees nothing and
- * clears the scratch it uses with a fill kernel (no memset).  Limit: fields of at
- * most 4,177,920 blocks (wv_zfpk_workspace_bytes <= 131072, e.g. 3-D fields up to
- * 640^3 values); a larger field returns WV_ENOMEM (wv_last_error says why) and
- * launches nothing.  Every call on one GPU shares that GPU's array, so calls that
+ * the same stream, with no workspace argument.  Its scratch (bookkeeping words, and
+ * the word count and offset of each chunk of 256 blocks) is a fixed 192 KiB array in
+ * device memory that each GPU the library runs on holds until the process ends; the
+ * call allocates and frees nothing and clears the bookkeeping with a fill kernel (no
+ * memset).  Without staging slots it encodes every chunk twice (count, then emit at
+ * its offset).  Limit: fields of at most 4,172,288 blocks (e.g. 3-D fields up to 640^3
+ * values); a larger field returns WV_ENOMEM (wv_last_error says why) and launches
+ * nothing.  Every call on one GPU shares that GPU's array, so calls that
  * overlap on one GPU (concurrent streams or threads) race: run them one at a time.
  * Arguments, output, errors and synchronisation as wv_zfpk_encode. */
 int wv_zfpk_encode_noalloc(const float *field, int ndim, const int *dims, double tol, void *out, size_t cap,

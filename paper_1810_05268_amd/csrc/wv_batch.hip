@@ -86,19 +86,13 @@ __device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned nwg, unsign
     __syncthreads();
 }
 
-// inclusive workgroup scan of v over s_scan; returns the lane's inclusive sum
-__device__ __forceinline__ unsigned block_scan(unsigned *s_scan, unsigned v)
+// inclusive workgroup scan of v (s_scan: scratch for the wave totals); the trailing
+// barrier lets the caller reuse s_scan at once
+__device__ __forceinline__ unsigned block_scan(unsigned *s_scan, unsigned v, unsigned &total)
 {
-    const int tid = threadIdx.x;
-    s_scan[tid] = v;
+    const unsigned r = wg_scan256(v, s_scan, total);
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const unsigned add = tid >= off ? s_scan[tid - off] : 0u;
-        __syncthreads();
-        s_scan[tid] += add;
-        __syncthreads();
-    }
-    return s_scan[tid];
+    return r;
 }
 
 // sum of w[0..n) by one workgroup (wave 0 does the adding), broadcast through *out
@@ -230,8 +224,8 @@ __device__ __forceinline__ void phase_encode(const BatchCtx &C, const BatchOp &o
         uint32_t m_lo[32], m_hi[32];
         blk.prepare(v, valid, A.minexp, m_lo, m_hi);
         const unsigned nbits = blk.count(m_lo, m_hi);
-        const unsigned incl = block_scan(s_scan, nbits);
-        const unsigned total_bits = s_scan[255];
+        unsigned total_bits;
+        const unsigned incl = block_scan(s_scan, nbits, total_bits);
         const uint32_t chunk_words = (total_bits + 63u) / 64u;
         __syncthreads();
         if (!emit) {
@@ -343,10 +337,11 @@ __device__ __forceinline__ void phase_decode(const BatchCtx &C, const BatchOp &o
         frexp(tol, &te);
         const int minexp = te - 1;
         const unsigned nbits = valid ? lens[b] : 0u;
-        const unsigned incl = block_scan(s_scan, nbits);
+        unsigned total_bits;
+        const unsigned incl = block_scan(s_scan, nbits, total_bits);
         long long cbase = (long long)chunk_off[c];
         cbase = cbase < 0 ? 0 : (cbase > nwords ? nwords : cbase);
-        const long long cw = ((long long)s_scan[255] + 63) / 64 + 1;
+        const long long cw = ((long long)total_bits + 63) / 64 + 1;
         const bool staged = cw <= kDecLdsWords;
         if (staged) {
             for (long long q = tid; q < cw; q += 256) {
@@ -438,7 +433,7 @@ __device__ __forceinline__ void phase_copy(const BatchCtx &C, int src, int dst)
 template <int K>
 __global__ __launch_bounds__(256) void batch2d_kernel(BatchArgs A)
 {
-    __shared__ unsigned s_scan[256];
+    __shared__ unsigned s_scan[4];
     __shared__ unsigned long long s_words[kDecLdsWords];
     __shared__ unsigned long long s_one;
     __shared__ float s_row[256 + 2 * K];

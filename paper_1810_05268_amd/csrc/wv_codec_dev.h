@@ -208,6 +208,27 @@ struct BitReader {
     }
 };
 
+// Inclusive scan of v over a 256-lane workgroup: shuffles inside each wave, then one
+// exchange of the four wave totals through s_w[0..3].  Returns the lane's inclusive sum
+// and sets total to the workgroup's sum.  Every lane calls it; it holds one barrier, and
+// s_w may be written again only after another barrier of the caller.
+template <typename T>
+__device__ __forceinline__ T wg_scan256(T v, T *s_w, T &total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
+    const T w0 = s_w[0], w1 = s_w[1], w2 = s_w[2], w3 = s_w[3];
+    total = w0 + w1 + w2 + w3;
+    return x + (wave > 0 ? w0 : T(0)) + (wave > 1 ? w1 : T(0)) + (wave > 2 ? w2 : T(0));
+}
+
 // Block values, axis 0 fastest; partial blocks repeat the last valid index.  With
 // VEC (dims[0] % 4 == 0) every block is complete along x and each row is one
 // float4 load with no branch, so all 16 row loads of a lane are in flight together.

@@ -306,7 +306,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
     size_t bk, U0, U1, L0, L1, W, Z, UB, DB, V, VU;
     size_t src_tab, rec_tab, tab_bytes;
-    size_t res, dsim, partials, flags, offs, sizes, arena;
+    size_t res, dsim, partials, enc, offs, sizes, arena;
     size_t total;
     size_t arena_bytes;
     long long nchunks_max;
@@ -315,7 +315,7 @@ struct Layout {
 
 constexpr size_t kBk = 4096;
 // bookkeeping words inside bk
-constexpr size_t kErr = 0, kMisfit = 128, kStats = 192, kZero = 256, kProbeNext = 264, kScal = 320, kTicket = 384;
+constexpr size_t kErr = 0, kMisfit = 128, kStats = 192, kZero = 256, kProbeNext = 264, kScal = 320;
 constexpr int kParts = 1024;
 
 struct Setup {
@@ -706,7 +706,7 @@ Layout plan_layout(const wv_model *m, const wv_geom *geo, const Setup &su, int o
         const int cdims[3] = {su.g.nx, su.ndim == 3 ? su.g.ny : su.g.nz, su.ndim == 3 ? su.g.nz : 1};
         const CodecDims cd = codec_dims(su.ndim, cdims, su.g.px);
         L.nchunks_max = cd.nchunks;
-        L.flags = take((size_t)cd.nchunks * 8);
+        L.enc = take(encode_work_bytes(cd, true));   // the encoder's chunk counts, offsets, slots
         L.offs_n = 2 * (m->nt + 3);
         L.offs = take((size_t)L.offs_n * 8);
         L.sizes = take((size_t)(m->nt + 1) * 8);   // stream bytes of u^k for each stored state k
@@ -725,7 +725,8 @@ struct Dev {
     unsigned *err;
     double *misfit;
     unsigned long long *stats;
-    uint64_t *zero, *probe_next, *flags, *offs, *sizes;
+    uint64_t *zero, *probe_next, *offs, *sizes;
+    uint8_t *enc;
     uint8_t *arena;
     float *res, *dsim;
     double *partials;
@@ -794,7 +795,7 @@ int bind(Dev &d, void *ws, size_t ws_bytes, const Layout &L, int op)
         d.res = at<float>(d.base, L.res);
         d.dsim = at<float>(d.base, L.dsim);
         d.partials = at<double>(d.base, L.partials);
-        d.flags = at<uint64_t>(d.base, L.flags);
+        d.enc = at<uint8_t>(d.base, L.enc);
         d.offs = at<uint64_t>(d.base, L.offs);
         d.sizes = at<uint64_t>(d.base, L.sizes);
         d.arena = at<uint8_t>(d.base, L.arena);
@@ -1120,7 +1121,6 @@ struct GradRun {
     CodecDims cd{};
     size_t S = 0;                      // bytes of one uncompressed checkpoint (two field arrays)
     size_t Sd = 0;                     // 8 bytes per grid point: the dense pair that ratios refer to
-    uint32_t epoch = 0;
     long advances = 0, stores = 0, restores = 0, reverses = 0, decodes = 0, fields = 0;
     // stream bytes of an all-zero field: prefix plus one bit per block
     double empty_field_bytes() const
@@ -1133,9 +1133,8 @@ struct GradRun {
     // size_out (nullable) the stream's bytes
     int encode_field(const float *f, const float *sub, uint64_t *base, uint64_t *next, uint64_t *size_out = nullptr)
     {
-        ++epoch;
-        HIPCHK(launch_encode(cd, f, sub, tol, d.arena, d.L.arena_bytes, base, next, d.flags, epoch,
-                             at<unsigned>(d.base, d.L.bk + kTicket), d.err, d.stats, s, size_out));
+        HIPCHK(launch_encode(cd, f, sub, tol, d.arena, d.L.arena_bytes, base, next, d.enc, true, d.err, d.stats, s,
+                             size_out));
         return WV_OK;
     }
 };
@@ -1161,7 +1160,6 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
     HIPCHK(launch_fill_f32(d.Lm[1], P, 0.0f, s));
     if (R.G) HIPCHK(launch_fill_f64(R.G, R.su.P, 0.0, s));   // the caller's dense gradient
     HIPCHK(launch_fill_u64(d.offs, d.L.offs_n, 0, s));
-    HIPCHK(launch_fill_u64(d.flags, d.L.nchunks_max, 0, s));
     HIPCHK(launch_fill_u64(d.sizes, N + 1, 0, s));
     if (data) HIPCHK(launch_fill_f32(data, R.geo->nrec, 0.0f, s));
     int gathered = 0;
@@ -1372,7 +1370,6 @@ int probe_ratio(GradRun &R, double *ratio, double *prof)
     Fwd f{d, R.su, R.geo, s};
     f.at(d.Z, d.Z);
     HIPCHK(launch_fill_u64(d.offs, d.L.offs_n, 0, s));
-    HIPCHK(launch_fill_u64(d.flags, d.L.nchunks_max, 0, s));
     HIPCHK(launch_fill_u64(d.sizes, N + 1, 0, s));
     HIPCHK(launch_fill_u64(at<uint64_t>(d.base, d.L.bk + kStats), 2, 0, s));
     int rc;
@@ -1970,14 +1967,14 @@ int wv_velocity_gradient(int ndim, const int *n, int nbl, const float *vpad, con
 
 // ------------------------------------------------------------------ codec entry points
 namespace {
-constexpr size_t kCodecBk = 512;   // err, base word, next word, stats[2], chunk ticket
+constexpr size_t kCodecBk = 512;   // err, base word, next word, stats[2]
 }
 
 size_t wv_zfpk_workspace_bytes(int ndim, const int *dims)
 {
     if ((ndim != 2 && ndim != 3) || !dims) return 0;
     const CodecDims cd = codec_dims(ndim, dims);
-    return kCodecBk + align_up((size_t)cd.nchunks * 8, 256);
+    return kCodecBk + encode_work_bytes(cd, true);
 }
 
 size_t wv_zfpk_max_bytes(int ndim, const int *dims)
@@ -2001,22 +1998,21 @@ int check_encode_args(const float *field, int ndim, const int *dims, double tol,
     return WV_OK;
 }
 
-// One field through the encoder with its bookkeeping and chunk status words at b
-// (wv_zfpk_workspace_bytes of them, 256-byte aligned); b is cleared here by a fill
-// kernel, so it may hold anything on entry.  Synchronises the stream.
+// One field through the encoder with its bookkeeping words and work area at b (kCodecBk
+// bytes, then encode_work_bytes(cd, staged), 256-byte aligned); the bookkeeping is
+// cleared here by a fill kernel and the work area is written before it is read, so b may
+// hold anything on entry.  Synchronises the stream.
 int encode_one(const float *field, int ndim, const int *dims, double tol, void *out, size_t cap, size_t *nbytes,
-               uint8_t *b, hipStream_t s)
+               uint8_t *b, bool staged, hipStream_t s)
 {
     const CodecDims cd = codec_dims(ndim, dims);
     unsigned *err = (unsigned *)b;
     uint64_t *base = (uint64_t *)(b + 128);
     uint64_t *next = (uint64_t *)(b + 136);
     unsigned long long *st = (unsigned long long *)(b + 192);
-    uint64_t *flags = (uint64_t *)(b + kCodecBk);
     HIPCHK(launch_fill_u64((uint64_t *)b, kCodecBk / 8, 0, s));
-    HIPCHK(launch_fill_u64(flags, cd.nchunks, 0, s));
-    HIPCHK(launch_encode(cd, field, nullptr, tol, (uint8_t *)out, cap, base, next, flags, 1u,
-                         (unsigned *)(b + 256), err, st, s));
+    HIPCHK(launch_encode(cd, field, nullptr, tol, (uint8_t *)out, cap, base, next, b + kCodecBk, staged, err, st,
+                         s));
     unsigned e = 0;
     unsigned long long tot[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, s));
@@ -2025,16 +2021,18 @@ int encode_one(const float *field, int ndim, const int *dims, double tol, void *
     *nbytes = (size_t)tot[0];
     if (e & 4u) return WV_ECAP;
     if (e & 2u) return WV_EINVAL;
-    if (e & 16u) return WV_EHIP;
     return WV_OK;
 }
 
-// Scratch of wv_zfpk_encode_noalloc: the encoder's bookkeeping words and chunk status
-// words in one file-scope device array.  Every GPU the library runs on holds its own
+// Scratch of wv_zfpk_encode_noalloc: the encoder's bookkeeping words and its chunk
+// counts and offsets (no staging slots: every chunk is encoded twice) in one
+// file-scope device array.  Every GPU the library runs on holds its own
 // copy until the process ends.  In host code the array's name is only a stand-in, so
 // host code never passes it: the device address comes from hipGetSymbolAddress, taken
 // once per device with that device current, and kept in g_scratch_dev.
-constexpr size_t kNoAllocScratchBytes = 128 * 1024;
+constexpr size_t kNoAllocScratchBytes = 192 * 1024;
+// chunks whose counts (4 bytes) and offsets (8 bytes) fit, each array padded to 256 bytes
+constexpr size_t kNoAllocMaxBlocks = (kNoAllocScratchBytes - kCodecBk - 512) / 12 * kBlocksPerChunk;
 static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
 
 constexpr int kMaxDevices = 64;
@@ -2067,16 +2065,16 @@ int wv_zfpk_encode_noalloc(const float *field, int ndim, const int *dims, double
     int rc = check_encode_args(field, ndim, dims, tol, out, nbytes);
     if (rc) return rc;
     (void)hipGetLastError();
-    if (wv_zfpk_workspace_bytes(ndim, dims) > kNoAllocScratchBytes) {
+    const size_t need = kCodecBk + encode_work_bytes(codec_dims(ndim, dims), false);
+    if (need > kNoAllocScratchBytes) {
         std::snprintf(g_detail, sizeof(g_detail),
                       "wv_zfpk_encode_noalloc: %zu bytes of scratch needed, %zu available (at most %zu blocks)",
-                      wv_zfpk_workspace_bytes(ndim, dims), kNoAllocScratchBytes,
-                      (kNoAllocScratchBytes - kCodecBk) / 8 * (size_t)kBlocksPerChunk);
+                      need, kNoAllocScratchBytes, kNoAllocMaxBlocks);
         return WV_ENOMEM;
     }
     uint8_t *b = nullptr;
     if ((rc = noalloc_scratch(&b))) return rc;
-    return encode_one(field, ndim, dims, tol, out, cap, nbytes, b, (hipStream_t)stream);
+    return encode_one(field, ndim, dims, tol, out, cap, nbytes, b, false, (hipStream_t)stream);
 }
 
 int wv_zfpk_encode(const float *field, int ndim, const int *dims, double tol, void *out, size_t cap,
@@ -2086,7 +2084,7 @@ int wv_zfpk_encode(const float *field, int ndim, const int *dims, double tol, vo
     if (rc) return rc;
     (void)hipGetLastError();
     if (!ws || ws_bytes < wv_zfpk_workspace_bytes(ndim, dims) || (((uintptr_t)ws) & 255)) return WV_ENOMEM;
-    return encode_one(field, ndim, dims, tol, out, cap, nbytes, (uint8_t *)ws, (hipStream_t)stream);
+    return encode_one(field, ndim, dims, tol, out, cap, nbytes, (uint8_t *)ws, true, (hipStream_t)stream);
 }
 
 int wv_zfpk_decode(const void *in, size_t nbytes, int ndim, const int *dims, float *field, void *stream)

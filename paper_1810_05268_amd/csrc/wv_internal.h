@@ -111,15 +111,16 @@ CodecDims codec_dims(int ndim, const int *dims, int pitch = 0);
 size_t codec_max_bytes(const CodecDims &cd);
 // Encode field (or field - sub, in binary32, when sub is not null) into out + *base
 // (device offset), capacity cap bytes from `out`.
-// Writes *next = *base + stream bytes rounded up to 256.  flags: nchunks status words.
-// ticket: a word that is 0 at launch (the kernel leaves it 0 again).  size_out (nullable)
-// receives the stream's size in bytes.
-// err: bit 2 = capacity overflow, bit 1 = non-finite input, bit 4 = look-back timeout.
+// Writes *next = *base + stream bytes rounded up to 256.  work: encode_work_bytes(cd,
+// staged) bytes, 256-byte aligned, any contents (chunk word counts, offsets and, when
+// staged, a kLdsWords-word slot per chunk; without staging every chunk is encoded twice).
+// size_out (nullable) receives the stream's size in bytes.
+// err: bit 2 = capacity overflow, bit 1 = non-finite input.
 // stats[0] += stream bytes, stats[1] = max(stats[1], *next).
+size_t encode_work_bytes(const CodecDims &cd, bool staged);
 hipError_t launch_encode(const CodecDims &cd, const float *field, const float *sub, double tol, uint8_t *out,
-                         uint64_t cap, const uint64_t *base, uint64_t *next, uint64_t *flags, uint32_t epoch,
-                         unsigned *ticket, unsigned *err, unsigned long long *stats, hipStream_t s,
-                         uint64_t *size_out = nullptr);
+                         uint64_t cap, const uint64_t *base, uint64_t *next, uint8_t *work, bool staged,
+                         unsigned *err, unsigned long long *stats, hipStream_t s, uint64_t *size_out = nullptr);
 // Decode the stream at in + *base (base == nullptr: offset 0) into field, or, when sub
 // is not null, store sub - decoded; cap bytes are readable from `in` (a stream that
 // does not fit decodes to zeros).

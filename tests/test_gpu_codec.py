@@ -57,7 +57,7 @@ def test_stream_byte_identical(name, field, tol):
 
 
 def test_many_chunks_wavefield_like():
-    """Several hundred chunks: exercises the decoupled look-back across the whole grid."""
+    """Several hundred chunks: every chunk placed at the offset the scan of the chunk word counts gives."""
     rng = np.random.default_rng(3)
     z, y, x = np.meshgrid(np.arange(90), np.arange(100), np.arange(110), indexing="ij")
     r = np.sqrt((x - 55) ** 2 + (y - 50) ** 2 + (z - 10) ** 2)
