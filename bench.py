@@ -371,7 +371,7 @@ def serving_leg(nreq, rate, pool_bytes, max_active, tol, cap, max_batch, saturat
     torch.cuda.synchronize()
     eng = Engine(pool_bytes=pool_bytes, max_active=max_active, max_batch=max_batch)
     log(f"serving: replaying {nreq} requests at {rate}/s ...")
-    res, wall = replay(eng, items, time_scale=1.0)
+    res, wall = replay(eng, items, time_scale=1.0, timeout_s=150.0)
     eng.close()
     del eng
     torch.cuda.empty_cache()
@@ -395,17 +395,20 @@ def serving_leg(nreq, rate, pool_bytes, max_active, tol, cap, max_batch, saturat
     sat = []
     half = items[: max(1, nreq // 2)]
     for mult in saturation:
+        log(f"saturation x{mult}: replaying {len(half)} requests at {rate * mult:g}/s ...")
         eng = Engine(pool_bytes=pool_bytes, max_active=max_active, max_batch=max_batch)
-        rs, w = replay(eng, half, time_scale=1.0 / mult)
+        rs, w = replay(eng, half, time_scale=1.0 / mult, timeout_s=150.0)
         eng.close()
         del eng
         torch.cuda.empty_cache()
         ls = sorted(r["latency_ms"] for r in rs)
         sat.append({"offered_per_s": rate * mult, "req_per_s": len(half) / w, "p50_ms": pct(ls, 0.5),
                     "p99_ms": pct(ls, 0.99), "failed": sum(1 for r in rs if r["status"] != 0),
-                    "queue_p50_ms": pct(sorted(r["queue_ms"] for r in rs), 0.5)})
+                    "queue_p50_ms": pct(sorted(r["queue_ms"] for r in rs), 0.5),
+                    "retried": sum(1 for r in rs if r["stats"]["retries"])})
         log(f"saturation x{mult}: offered {rate * mult:.0f}/s -> {len(half) / w:.2f} req/s, p50 "
-            f"{sat[-1]['p50_ms']:.0f} ms, p99 {sat[-1]['p99_ms']:.0f} ms")
+            f"{sat[-1]['p50_ms']:.0f} ms, p99 {sat[-1]['p99_ms']:.0f} ms, failed {sat[-1]['failed']}, "
+            f"retried {sat[-1]['retried']}")
         if len(sat) >= 2 and sat[-1]["req_per_s"] < 1.1 * sat[-2]["req_per_s"]:
             break   # throughput no longer grows with the load: the engine is saturated
     return {"requests": nreq, "rate_per_s": rate, "failed": len(bad), "wall_s": wall,

@@ -297,19 +297,26 @@ int wv_zfpk_decode(const void *in, size_t nbytes, int ndim, const int *dims, flo
  * plans, unless ratio_hint > 0 plans it), and one kernel launch executes the whole
  * reversal: the host turns the schedule into a program of phases (stencil steps, source
  * and residual injections, checkpoint encodes and decodes, the misfit), and every phase
- * runs for all shots, with a device-wide barrier between phases (a cooperative launch,
- * every workgroup resident).  Each shot's arithmetic is the solo call's, in the same
- * order, so its misfit, gradient and d_sim are bit-identical to wv_misfit_gradient's for
- * that shot alone, whatever else is in the batch.
+ * runs for all shots, with a device-wide barrier between phases (a plain launch of at
+ * most as many workgroups as the device holds at once).  Each shot's arithmetic is the
+ * solo call's, in the same order, so its misfit, gradient and d_sim are bit-identical to
+ * wv_misfit_gradient's for that shot alone, whatever else is in the batch.  If a barrier
+ * cannot complete within a fraction of a second (other streams' kernels keep some of
+ * the launch's workgroups off the device), the launch ends early and every shot runs
+ * alone, through wv_misfit_gradient in its part of ws: the same results, with
+ * stats.retries one higher.  (The environment variable WV_BATCH_SPIN_LIMIT, read at each
+ * call, sets that bound in polls; 0 makes every launch end at its first barrier, for
+ * tests of this path.)
  *   models, geoms       host [nshots]
  *   d_obs               host [nshots] of device [nt+1][nrec] float
  *   misfits             host [nshots], receives phi of each shot
  *   grad_m              host [nshots] of device [P] double, overwritten
  *   d_sim               host [nshots] of device [nt+1][nrec] float, or NULL (entries nullable)
- *   stats               host [nshots] or NULL (retries: repeats of the whole batch)
+ *   stats               host [nshots] or NULL (retries: repeats of the whole batch, and
+ *                       1 for a launch that ended early)
  *   ws                  wv_batch_workspace_bytes(...) bytes, 256-byte aligned
- * Errors as wv_misfit_gradient, plus WV_EINVAL for shots that do not share the above and
- * WV_EHIP if the device-wide barrier timed out.  Synchronises the stream. */
+ * Errors as wv_misfit_gradient, plus WV_EINVAL for shots that do not share the above.
+ * Synchronises the stream. */
 size_t wv_batch_workspace_bytes(int nshots, const wv_model *models, const wv_geom *geoms, size_t mem_budget);
 int wv_batch_misfit_gradient(int nshots, const wv_model *models, const wv_geom *geoms, const float *const *d_obs,
                              size_t mem_budget, double tol, double ratio_hint, double *misfits,

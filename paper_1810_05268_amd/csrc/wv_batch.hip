@@ -39,28 +39,31 @@ __device__ __forceinline__ float *batch_buf(const BatchShot &S, int id, long lon
     }
 }
 
-// Device-wide barrier of the persistent launch (all workgroups resident).  Two levels:
-// workgroup b arrives at the counter of its group b % 8 (the XCD it runs on under
-// round-robin dispatch), the last arrival of a group at the top counter, and the last of
-// those resets it and advances the generation; everyone else waits for the generation
-// to move, with a bounded spin (past the bound: err bit 16, and the kernel runs on to its
-// end).  Counters, top and generation sit 1 KB apart so that arrivals of different
-// groups and the polling do not meet on one line.  Memory order: a release fence before
-// each arrival, acquire + release fences around the group's and the top's last arrival,
-// relaxed polling (an acquire poll would invalidate the L2 on every spin) and one acquire
-// fence after the wait, so every write of the phase is visible to every workgroup of the
-// next.
-__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned nwg, unsigned *err)
+// Device-wide barrier of the persistent launch.  Two levels: workgroup b arrives at the
+// counter of its group b % 8 (the XCD it runs on under round-robin dispatch), the last
+// arrival of a group at the top counter, and the last of those resets it and advances the
+// generation; everyone else waits for the generation to move.  Counters, top, generation
+// and the abort word sit 1 KB apart so that arrivals of different groups and the polling
+// do not meet on one line.  Memory order: a release fence before each arrival, acquire +
+// release fences around the group's and the top's last arrival, relaxed polling (an
+// acquire poll would invalidate the L2 on every spin) and one acquire fence after the
+// wait, so every write of the phase is visible to every workgroup of the next.
+// The barrier needs every workgroup resident.  The spin is bounded (spin_limit polls, 2^18
+// by default: a fraction of a second, where a phase takes microseconds): past the bound, or when another
+// workgroup has given up, it sets err bit 16 and the abort word and returns false, and the
+// kernel ends at once; the host then runs the batch's shots one by one.
+__device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned nwg, unsigned spin_limit, unsigned *err,
+                                             unsigned *s_flag)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned ng = nwg < 8u ? nwg : 8u;
         const unsigned grp = blockIdx.x & 7u;
         const unsigned in_grp = (nwg - grp + 7u) / 8u;
-        unsigned *sub = bar + 256u * grp, *top = bar + 2048, *gen = bar + 3072;
+        unsigned *sub = bar + 256u * grp, *top = bar + 2048, *gen = bar + 3072, *abort = bar + 3584;
         const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        bool waiting = true;
+        bool waiting = true, ok = true;
         if (__hip_atomic_fetch_add(sub, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == in_grp - 1u) {
             __hip_atomic_store(sub, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
@@ -74,16 +77,20 @@ __device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned nwg, unsign
         if (waiting) {
             unsigned spins = 0;
             while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
-                if (++spins > (1u << 24)) {
+                if (++spins > spin_limit || __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     atomicOr(err, 16u);
+                    __hip_atomic_store(abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = false;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(2);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_flag = ok ? 1u : 0u;
     }
     __syncthreads();
+    return *s_flag != 0u;
 }
 
 // inclusive workgroup scan of v (s_scan: scratch for the wave totals); the trailing
@@ -441,8 +448,9 @@ __global__ __launch_bounds__(256) void batch2d_kernel(BatchArgs A)
     const int tiles_x = (A.g.nx + 255) / 256;
     const BatchCtx C{A, A.g, A.cd, A.g.P, tiles_x, tiles_x * ((A.g.nz + A.zlen - 1) / A.zlen),
                      A.cd.dims[0] % 4 == 0 && A.cd.pitch % 4 == 0, A.cd.nchunks};
+    __shared__ unsigned s_flag;
     unsigned *err0 = A.shots[0].err;
-    auto barrier = [&]() { grid_barrier(A.bar, (unsigned)A.nwg, err0); };
+    auto barrier = [&]() { return grid_barrier(A.bar, (unsigned)A.nwg, A.spin_limit, err0, &s_flag); };
 
     for (int oi = 0; oi < A.nops; ++oi) {
         const BatchOp op = A.ops[oi];
@@ -454,7 +462,7 @@ __global__ __launch_bounds__(256) void batch2d_kernel(BatchArgs A)
             for (int n = op.n; n < op.d; ++n) {
                 const int out = fin == kBufU0 ? kBufU1 : kBufU0;
                 phase_step<K, false>(C, fin, prev, out, kBufNone, n, gin, grow, s_row);
-                barrier();
+                if (!barrier()) return;
                 grow = n >= op.e ? n + 1 : -1;
                 gin = out;
                 prev = fin;
@@ -462,37 +470,37 @@ __global__ __launch_bounds__(256) void batch2d_kernel(BatchArgs A)
             }
             if (grow >= 0) {
                 phase_gather(C, gin, grow);
-                barrier();
+                if (!barrier()) return;
             }
             break;
         }
         case kOpAdj:
             phase_step<K, true>(C, op.a, op.b, op.b, op.c, op.n, kBufNone, -1, s_row);
-            barrier();
+            if (!barrier()) return;
             break;
         case kOpEncCount:
             phase_encode(C, op, false, s_scan, s_words, &s_one);
-            barrier();
+            if (!barrier()) return;
             break;
         case kOpEncEmit:
             phase_encode(C, op, true, s_scan, s_words, &s_one);
-            barrier();
+            if (!barrier()) return;
             break;
         case kOpDec:
             phase_decode(C, op, s_scan, s_words);
-            barrier();
+            if (!barrier()) return;
             break;
         case kOpCopy:
             phase_copy(C, op.a, op.b);
-            barrier();
+            if (!barrier()) return;
             break;
         case kOpResid:
             phase_residual(C, op.a, s_red);
-            barrier();
+            if (!barrier()) return;
             break;
         case kOpMisfit:
             phase_misfit(C, s_red);
-            barrier();
+            if (!barrier()) return;
             break;
         default:
             break;
@@ -510,13 +518,13 @@ int resident_of()
     return cus * per_cu;
 }
 
+// A plain launch: the grid is at most what the device holds at once, and a barrier that
+// does not complete (workgroups kept out by other streams' kernels) aborts the launch.
 template <int K>
 hipError_t launch_of(const BatchArgs &A, hipStream_t s)
 {
-    BatchArgs a = A;
-    void *args[] = {&a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(batch2d_kernel<K>), dim3(A.nwg), dim3(256), args,
-                                      0, s);
+    hipLaunchKernelGGL(batch2d_kernel<K>, dim3(A.nwg), dim3(256), 0, s, A);
+    return hipGetLastError();
 }
 
 }  // namespace

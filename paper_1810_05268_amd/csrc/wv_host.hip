@@ -8,6 +8,7 @@
 // separate checkpoint memory, a restore copies it back (eq. (4)); with a
 // tolerance the copies pass through the codec (eq. (6)) and the slot count grows
 // by the compression ratio.
+#include <cstdlib>
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -1774,6 +1775,9 @@ int wv_batch_misfit_gradient(int nshots, const wv_model *models, const wv_geom *
     }
     A.slot_elems = (long long)su[0].Pf * 2;
     A.bar = reinterpret_cast<unsigned *>(base + B.hdr);
+    // WV_BATCH_SPIN_LIMIT (for tests of the fallback) lowers the barrier's poll bound
+    A.spin_limit = 1u << 18;
+    if (const char *sl = std::getenv("WV_BATCH_SPIN_LIMIT")) A.spin_limit = (unsigned)std::strtoul(sl, nullptr, 10);
     for (int i = 0; i < nshots; ++i) {
         A.src_pts = std::max(A.src_pts, shots[i].src.npts);
         A.rec_pts = std::max(A.rec_pts, shots[i].rec.npts);
@@ -1855,7 +1859,23 @@ int wv_batch_misfit_gradient(int nshots, const wv_model *models, const wv_geom *
                 }
             }
         }
-        if (timeout) return hip_fail(hipErrorLaunchFailure, "batch2d device-wide barrier timed out", __LINE__);
+        if (timeout) {
+            // a barrier of the persistent launch did not complete (its workgroups could not
+            // all be resident beside other streams' work): each shot runs alone instead, in
+            // its own region of the workspace, with the same arithmetic and so the same bits
+            for (int i = 0; i < nshots; ++i) {
+                wv_stats st{};
+                if (stats) st.timing = stats[i].timing;
+                uint8_t *sb = base + B.shot0 + (size_t)i * B.shot_bytes;
+                const int r = wv_misfit_gradient(&models[i], &geoms[i], d_obs[i], mem_budget, tol, ratio_hint,
+                                                 &misfits[i], grad_m[i], d_sim ? d_sim[i] : nullptr, &st, sb,
+                                                 B.shot_bytes, stream);
+                if (r) return r;
+                st.retries += 1;   // the aborted batch launch
+                if (stats) stats[i] = st;
+            }
+            return WV_OK;
+        }
         if (overflow && tol > 0 && F > 1.0 && attempt < kArenaRetries) {
             F = attempt + 1 == kArenaRetries ? 1.0 : std::max(1.0, F / 2);
             for (int i = 0; i < nshots; ++i) HIPCHK(launch_fill_u64(at<uint64_t>(dv[i].base, dv[i].L.bk), kBk / 8, 0, s));

@@ -188,12 +188,13 @@ struct BatchArgs {
     int nt;
     int zlen;                 // rows per stencil work item
     long long slot_elems;     // elements of one uncompressed checkpoint slot (two fields)
-    unsigned *bar;            // device-wide barrier: [0] arrivals, [64] generation (zero at launch)
-    int nwg;                  // workgroups of the launch (all resident)
+    unsigned *bar;            // device-wide barrier words: group counters, top, generation, abort (zero at launch)
+    int nwg;                  // workgroups of the launch (at most what the device holds at once)
+    unsigned spin_limit;      // polls before a barrier gives up and the launch aborts
 };
 // Workgroups the persistent kernel can keep resident for space order 2K (0 on error).
 int batch2d_resident_workgroups(int K);
-// Cooperative launch of the persistent kernel with A.nwg workgroups.
+// Launch of the persistent kernel with A.nwg workgroups.
 hipError_t launch_batch2d(const BatchArgs &A, int K, hipStream_t s);
 
 }  // namespace wv

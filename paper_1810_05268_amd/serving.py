@@ -73,10 +73,11 @@ class Engine:
             pass
 
 
-def replay(engine: Engine, items, time_scale: float = 1.0):
+def replay(engine: Engine, items, time_scale: float = 1.0, timeout_s: float | None = None):
     """Submit (arrival_s, shot, d_obs, mem_budget, tol, hint) items at their arrival times
     (scaled by time_scale) and wait for all.  Returns per-request results with latency
-    measured from arrival (submission) to completion."""
+    measured from arrival (submission) to completion.  With timeout_s, a request not done
+    that many seconds after the last submission raises TimeoutError."""
     t0 = time.perf_counter()
     ids = []
     for arrival, shot, d_obs, budget, tol, hint in items:
@@ -84,9 +85,13 @@ def replay(engine: Engine, items, time_scale: float = 1.0):
         if dt > 0:
             time.sleep(dt)
         ids.append(engine.submit(shot, d_obs, budget, tol, hint))
+    deadline = None if timeout_s is None else time.perf_counter() + timeout_s
     out = []
     for rid in ids:
-        r = engine.wait(rid)
+        left = -1.0 if deadline is None else max(0.0, deadline - time.perf_counter()) * 1e3
+        r = engine.wait(rid, left)
+        if r is None:
+            raise TimeoutError(f"serving request {rid} not done {timeout_s} s after the last arrival")
         r["latency_ms"] = r["t_end_ms"] - r["t_submit_ms"]
         r["queue_ms"] = r["t_start_ms"] - r["t_submit_ms"]
         out.append(r)

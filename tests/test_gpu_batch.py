@@ -121,3 +121,27 @@ def test_batch_gradient_against_oracle():
         e = rel_l2(grads[i].cpu().numpy(), g_or)
         print(f"shot {i}: misfit rel err {abs(phis[i] - phi_or) / phi_or:.2e} gradient rel-L2 {e:.2e}")
         assert abs(phis[i] - phi_or) <= 1e-4 * phi_or and e <= 1e-4
+
+
+def test_batch_launch_that_ends_early_falls_back_to_solo(monkeypatch):
+    """A barrier that cannot complete ends the launch and every shot runs alone.  The
+    condition is forced from the host: a poll bound of 0 makes the first workgroup that
+    has to wait at the first barrier give up.  Results stay bit-identical to solo calls,
+    and each shot's stats count the aborted launch."""
+    import torch
+    shots = _shots((97, 90), 160, 8, 3, seed=91)
+    devs, dobs, _ = _device(shots)
+    S = devs[0].slot_bytes
+    budget, tol, hint = int(8 * 1.05 * S), 1e-4, 1.0
+    monkeypatch.setenv("WV_BATCH_SPIN_LIMIT", "0")
+    phis, grads, dsims, sts = _batch(devs, dobs, budget, tol, hint)
+    monkeypatch.delenv("WV_BATCH_SPIN_LIMIT")
+    for i, d in enumerate(devs):
+        phi, g, st, ds = d.misfit_gradient(dobs[i], budget, tol, ratio_hint=hint, want_dsim=True)
+        assert sts[i]["retries"] == st["retries"] + 1
+        assert phis[i] == phi
+        assert torch.equal(grads[i], g) and torch.equal(dsims[i], ds)
+    # and the next batch, with the default bound, runs in one launch again
+    phis2, grads2, _, sts2 = _batch(devs, dobs, budget, tol, hint)
+    assert all(st["retries"] == 0 for st in sts2)
+    assert phis2 == phis and all(torch.equal(a, b) for a, b in zip(grads2, grads))
