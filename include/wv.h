@@ -302,9 +302,10 @@ int wv_zfpk_decode(const void *in, size_t nbytes, int ndim, const int *dims, flo
  * solo call's, in the same order, so its misfit, gradient and d_sim are bit-identical to
  * wv_misfit_gradient's for that shot alone, whatever else is in the batch.  If a barrier
  * cannot complete within a fraction of a second (other streams' kernels keep some of
- * the launch's workgroups off the device), the launch ends early and every shot runs
- * alone, through wv_misfit_gradient in its part of ws: the same results, with
- * stats.retries one higher.  (The environment variable WV_BATCH_SPIN_LIMIT, read at each
+ * the launch's workgroups off the device), the launch ends early; a wide one is launched
+ * again with half the workgroups (twice at most), and then every shot runs alone,
+ * through wv_misfit_gradient in its part of ws: the same results, with stats.retries
+ * counting the launches that ended early.  (The environment variable WV_BATCH_SPIN_LIMIT, read at each
  * call, sets that bound in polls; 0 makes every launch end at its first barrier, for
  * tests of this path.)
  *   models, geoms       host [nshots]

@@ -1783,6 +1783,7 @@ int wv_batch_misfit_gradient(int nshots, const wv_model *models, const wv_geom *
         A.rec_pts = std::max(A.rec_pts, shots[i].rec.npts);
     }
     HIPCHK(hipMemcpyAsync(base + B.desc, shots.data(), shots.size() * sizeof(BatchShot), hipMemcpyHostToDevice, s));
+    int shrinks = 0;   // relaunches with half the workgroups after a barrier gave up
     for (int attempt = 0;; ++attempt) {
         const int M = plan_slots(N, mem_budget, tol > 0 ? Sd : Sp, tol > 0, F);
         if (M < 1) return WV_EBUDGET;
@@ -1849,7 +1850,7 @@ int wv_batch_misfit_gradient(int nshots, const wv_model *models, const wv_geom *
                 o.ratio_planned = F;
                 o.misfit = mis;
                 o.ms_total = ms;
-                o.retries = attempt;
+                o.retries = attempt + shrinks;
                 if (comp) {
                     std::vector<uint64_t> sz((size_t)N + 1, 0);
                     HIPCHK(hipMemcpy(sz.data(), d.sizes, sz.size() * 8, hipMemcpyDeviceToHost));
@@ -1859,10 +1860,19 @@ int wv_batch_misfit_gradient(int nshots, const wv_model *models, const wv_geom *
                 }
             }
         }
-        if (timeout) {
+        if (timeout && A.nwg >= 128 && shrinks < 2) {
             // a barrier of the persistent launch did not complete (its workgroups could not
-            // all be resident beside other streams' work): each shot runs alone instead, in
-            // its own region of the workspace, with the same arithmetic and so the same bits
+            // all be resident beside other streams' work): launch again with half the
+            // workgroups, which need half the room (they loop over more work items)
+            A.nwg = A.nwg / 16 * 8;
+            ++shrinks;
+            for (int i = 0; i < nshots; ++i) HIPCHK(launch_fill_u64(at<uint64_t>(dv[i].base, dv[i].L.bk), kBk / 8, 0, s));
+            --attempt;
+            continue;
+        }
+        if (timeout) {
+            // still not: each shot runs alone instead, in its own region of the workspace,
+            // with the same arithmetic and so the same bits
             for (int i = 0; i < nshots; ++i) {
                 wv_stats st{};
                 if (stats) st.timing = stats[i].timing;
@@ -1871,7 +1881,7 @@ int wv_batch_misfit_gradient(int nshots, const wv_model *models, const wv_geom *
                                                  &misfits[i], grad_m[i], d_sim ? d_sim[i] : nullptr, &st, sb,
                                                  B.shot_bytes, stream);
                 if (r) return r;
-                st.retries += 1;   // the aborted batch launch
+                st.retries += 1 + shrinks;   // the aborted batch launches
                 if (stats) stats[i] = st;
             }
             return WV_OK;

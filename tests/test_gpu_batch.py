@@ -126,8 +126,9 @@ def test_batch_gradient_against_oracle():
 def test_batch_launch_that_ends_early_falls_back_to_solo(monkeypatch):
     """A barrier that cannot complete ends the launch and every shot runs alone.  The
     condition is forced from the host: a poll bound of 0 makes the first workgroup that
-    has to wait at the first barrier give up.  Results stay bit-identical to solo calls,
-    and each shot's stats count the aborted launch."""
+    has to wait at the first barrier give up (a wide batch is first relaunched with half
+    the workgroups).  Results stay bit-identical to solo calls, and each shot's stats
+    count the aborted launches."""
     import torch
     shots = _shots((97, 90), 160, 8, 3, seed=91)
     devs, dobs, _ = _device(shots)
@@ -138,7 +139,7 @@ def test_batch_launch_that_ends_early_falls_back_to_solo(monkeypatch):
     monkeypatch.delenv("WV_BATCH_SPIN_LIMIT")
     for i, d in enumerate(devs):
         phi, g, st, ds = d.misfit_gradient(dobs[i], budget, tol, ratio_hint=hint, want_dsim=True)
-        assert sts[i]["retries"] == st["retries"] + 1
+        assert sts[i]["retries"] >= st["retries"] + 1
         assert phis[i] == phi
         assert torch.equal(grads[i], g) and torch.equal(dsims[i], ds)
     # and the next batch, with the default bound, runs in one launch again
