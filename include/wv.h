@@ -338,8 +338,8 @@ int wv_batch_misfit_gradient(int nshots, const wv_model *models, const wv_geom *
  * batching on (wv_engine_set_batching), 2-D requests are served by one more worker
  * that runs the oldest queued 2-D request together with every later one that can share
  * its call (same grid, order, nt, dt, vmax, receiver count, tolerance, budget and ratio
- * hint), up to max_batch of them, as one wv_batch_misfit_gradient; requests arriving
- * while a batch runs join the next.  A request's result does not depend on what else is
+ * hint), up to max_batch of them, as one wv_batch_misfit_gradient (a lone request as one
+ * wv_misfit_gradient); requests arriving while a batch runs join the next.  A request's result does not depend on what else is
  * in flight: batched or not, it is bit-identical to wv_misfit_gradient alone. */
 typedef struct wv_engine wv_engine;
 

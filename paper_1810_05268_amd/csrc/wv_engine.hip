@@ -287,11 +287,17 @@ struct wv_engine {
                 grads[i] = r->grad;
                 dsims[i] = r->d_sim;
             }
-            const int rc = bytes ? wv_batch_misfit_gradient(n, ms.data(), gs.data(), dobs.data(),
-                                                            batch[0]->mem_budget, batch[0]->tol, batch[0]->ratio_hint,
-                                                            phis.data(), grads.data(), dsims.data(), sts.data(),
-                                                            pool_base + off, bytes, batch_stream)
-                                 : WV_EINVAL;
+            // a batch of one runs the solo path (the same bits; the persistent launch pays a
+            // device-wide barrier per phase that only several shots amortise)
+            int rc = WV_EINVAL;
+            if (bytes && n == 1)
+                rc = wv_misfit_gradient(&ms[0], &gs[0], dobs[0], batch[0]->mem_budget, batch[0]->tol,
+                                        batch[0]->ratio_hint, &phis[0], grads[0], dsims[0], &sts[0], pool_base + off,
+                                        bytes, batch_stream);
+            else if (bytes)
+                rc = wv_batch_misfit_gradient(n, ms.data(), gs.data(), dobs.data(), batch[0]->mem_budget,
+                                              batch[0]->tol, batch[0]->ratio_hint, phis.data(), grads.data(),
+                                              dsims.data(), sts.data(), pool_base + off, bytes, batch_stream);
             {
                 std::lock_guard<std::mutex> lk(mu);
                 const Clock::time_point t_end = Clock::now();
