@@ -219,7 +219,22 @@ def performance_model(nt, points, slot_bytes, budget, st_plain, st_comp, hint, s
     # compressed call's compressibility profile), against which run measured faster
     ch = P.choose(nt, points, budget, cp, cc, profile=st_comp["profile"], slot_bytes=slot_bytes)
     ch["measured_faster"] = "compressed" if phases(st_comp) < phases(st_plain) else "plain"
-    return {"costs_plain": cp, "costs_compressed": cc, "full_storage_ms": full, "runs": rows, "choice": ch}
+    # the paper's predicted speed-up against memory (its Fig. 5): the same costs and
+    # profile over budgets from 0.5 GB to 4 TB; compressed storage of the whole trajectory
+    # and plain full storage mark the two regime boundaries
+    curve = []
+    for gb in (0.5, 1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 1536, 2048, 4096):
+        b = int(gb * 1e9)
+        c = P.choose(nt, points, b, cp, cc, profile=st_comp["profile"], slot_bytes=slot_bytes)
+        pp = P.predict(nt, points, b, False, cp["c_f"], cp["c_r"], t_copy=cp["t_store"], slot_bytes=slot_bytes)
+        mc, _ = P.plan(nt, points, b, st_comp["profile"])
+        curve.append({"budget_gb": gb, "ms_plain": c["ms_plain"], "ms_compressed": c["ms_compressed"],
+                      "speedup": c["ms_plain"] / c["ms_compressed"], "slots_plain": pp["slots"],
+                      "slots_compressed": mc})
+    regimes = {"compressed_trajectory_gb": full_trajectory_bytes(st_comp, nt) / 1e9,
+               "plain_full_storage_gb": (nt + 1) * slot_bytes / 1e9}
+    return {"costs_plain": cp, "costs_compressed": cc, "full_storage_ms": full, "runs": rows, "choice": ch,
+            "speedup_vs_memory": curve, "regimes": regimes}
 
 
 def traffic_per_launch():
