@@ -233,8 +233,24 @@ def performance_model(nt, points, slot_bytes, budget, st_plain, st_comp, hint, s
                       "slots_compressed": mc})
     regimes = {"compressed_trajectory_gb": full_trajectory_bytes(st_comp, nt) / 1e9,
                "plain_full_storage_gb": (nt + 1) * slot_bytes / 1e9}
+    # and against the number of steps and the cost of a step (its Fig. 6), at this budget:
+    # the profile read as a function of relative time; the stencil costs scaled, the codec
+    # costs kept (a costlier physics per step with the same fields)
+    steps_curve = []
+    for n in (500, 1000, 2000, 3000, 6000, 12000):
+        c = P.choose(n, points, budget, cp, cc, profile=st_comp["profile"], slot_bytes=slot_bytes)
+        steps_curve.append({"nt": n, "ms_plain": c["ms_plain"], "ms_compressed": c["ms_compressed"],
+                            "speedup": c["ms_plain"] / c["ms_compressed"]})
+    cost_curve = []
+    for f in (0.25, 0.5, 1.0, 2.0, 4.0, 8.0):
+        cpf = dict(cp, c_f=cp["c_f"] * f, c_r=cp["c_r"] * f)
+        ccf = dict(cc, c_f=cc["c_f"] * f, c_r=cc["c_r"] * f)
+        c = P.choose(nt, points, budget, cpf, ccf, profile=st_comp["profile"], slot_bytes=slot_bytes)
+        cost_curve.append({"step_cost_factor": f, "ms_plain": c["ms_plain"], "ms_compressed": c["ms_compressed"],
+                           "speedup": c["ms_plain"] / c["ms_compressed"]})
     return {"costs_plain": cp, "costs_compressed": cc, "full_storage_ms": full, "runs": rows, "choice": ch,
-            "speedup_vs_memory": curve, "regimes": regimes}
+            "speedup_vs_memory": curve, "regimes": regimes, "speedup_vs_steps": steps_curve,
+            "speedup_vs_step_cost": cost_curve}
 
 
 def traffic_per_launch():
