@@ -653,9 +653,8 @@ def main():
     _, st_plain_ph, _ = timed(0.0, 0.0, g_plain, 1, TIMING_ACTIONS)   # per-phase times (untimed call)
     log(f"plain: {statistics.mean(w_plain):.3f} s  M={st_plain[0]['slots']} advances={st_plain[0]['advances']}")
 
-    # compressed: the first (warm-up) call plans with the ratio of the final state; later
-    # calls plan with what it measured, as an optimisation loop would carry it from one
-    # iteration to the next
+    # compressed: the first (warm-up) call has no hint; later calls plan with the profile
+    # it measured, as an optimisation loop would carry it from one iteration to the next
     log("compressed ...")
     w_cold, st0, _ = timed(args.tol, 0.0, g_comp, max(1, args.warmup))
     hint = plan_hint(st0[-1], Pn, shot.nt, budget)
@@ -723,7 +722,7 @@ def main():
                                                          zip(compressibility["steps"], compressibility["ratio"])))
 
     # optional: plain against compressed at other checkpoint budgets (each run once; the
-    # compressed call plans from the profile a first compressed call measured)
+    # compressed call plans from the profile a first (cold, unhinted) compressed call measured)
     budget_sweep = []
     for bb in [int(float(x)) for x in args.budget_sweep.split(",") if x.strip()]:
         def once(tol, hint, out):
@@ -733,7 +732,7 @@ def main():
             torch.cuda.synchronize()
             return time.perf_counter() - t0, st_
         wp_, sp_ = once(0.0, 0.0, g_plain)
-        _, s0_ = once(args.tol, 0.0, g_comp)
+        wcold_, s0_ = once(args.tol, 0.0, g_comp)
         h_ = plan_hint(s0_, Pn, shot.nt, bb)
         wc_, sc_ = once(args.tol, h_, g_comp)
         ch_ = P.choose(shot.nt, Pn, bb, P.costs_from_stats(st_plain_ph[0]), P.costs_from_stats(st_comp_ph[0]),
@@ -742,12 +741,14 @@ def main():
         budget_sweep.append({"budget": bb, "plain_s": wp_, "plain_slots": sp_["slots"],
                              "plain_advances": sp_["advances"], "compressed_s": wc_,
                              "compressed_slots": sc_["slots"], "compressed_advances": sc_["advances"],
+                             "compressed_cold_s": wcold_,
                              "retries": sc_["retries"], "speedup_vs_plain": wp_ / wc_,
                              "grad_rel_err_vs_plain": e_,
                              "model_choice": "compressed" if ch_["compressed"] else "plain",
                              "model_ms": {"plain": ch_["ms_plain"], "compressed": ch_["ms_compressed"]}})
         log(f"budget {bb:.3g} B: plain {wp_:.3f} s (M={sp_['slots']}, {sp_['advances']} advances), compressed "
-            f"{wc_:.3f} s (M={sc_['slots']}, {sc_['advances']} advances), {wp_ / wc_:.2f}x, err {e_:.2e}")
+            f"{wc_:.3f} s (M={sc_['slots']}, {sc_['advances']} advances; cold {wcold_:.3f} s), {wp_ / wc_:.2f}x, "
+            f"err {e_:.2e}")
 
     ms_step = 1e3 * statistics.mean(w_comp)
     value = Pn * 2 * shot.nt / (ms_step * 1e-3) / 1e9
@@ -762,9 +763,10 @@ def main():
                    "points": Pn, "nt": shot.nt, "mem_budget": budget, "tol": args.tol},
         "shot_gradient_s": {"compressed": round(ms_step / 1e3, 4), "plain": round(statistics.mean(w_plain), 4),
                             "compressed_cold": round(w_cold[0], 4),
-                            "cold_note": "first compressed call, no ratio hint: its compressibility probe (a "
-                                         "forward run with 16 encodes) is included; the timed calls plan from "
-                                         "the profile it measured"},
+                            "cold_note": "first compressed call, no ratio hint: it stores every state when "
+                                         "they all fit the budget (as here), else it first measures their stream "
+                                         "sizes in a forward run that stops before the reversal; the timed calls "
+                                         "plan from the profile it measured"},
         "speedup_vs_plain": round(statistics.mean(w_plain) * 1e3 / ms_step, 4),
         "grad_rel_err_vs_plain": err,
         "plain_gpts": round(Pn * 2 * shot.nt / statistics.mean(w_plain) / 1e9, 3),

@@ -183,11 +183,15 @@ int wv_forward(const wv_model *model, const wv_geom *geom, float *data, float *s
  *               compressed (two 256-byte aligned streams), S = 8 P bytes per
  *               uncompressed checkpoint (u^k and u^{k-1}; compressed, the pair is
  *               stored as u^k and the increment u^k - u^{k-1}),
- *               F = 1 if tol == 0, else ratio_hint if > 0; without a hint a probe
- *               forward run measures the compressibility profile (stream sizes over
- *               time; the paper notes that late states compress worst) and M is the
+ *               F = 1 if tol == 0, else ratio_hint if > 0.  Without a hint the call
+ *               first stores every state (M = nt): if they all fit, that attempt is
+ *               the run.  Otherwise it stops before the reversal with the stream size
+ *               of every state it stored (once the arena is full, only the profile's
+ *               16 sample states are still encoded): the compressibility profile
+ *               (late states compress worst, as the paper notes), and M is the
  *               largest slot count whose peak arena use, simulated over the exact
- *               schedule with those sizes, fits (as wv_plan);
+ *               schedule with those sizes, fits (as wv_plan).  That first attempt is
+ *               not counted in stats->retries;
  *   tol         0: checkpoints are exact copies; > 0: absolute error bound of the codec
  *   grad_m      device [P] double, overwritten (layer cells included)
  *   stats       host, may be NULL

@@ -423,6 +423,15 @@ constexpr int kProfile = WV_PROFILE;
 
 long long profile_step(int N, int j) { return (j * (long long)N + kProfile - 2) / (kProfile - 1); }
 
+// whether a run that stores states 1..N-1 must store state k for the compressibility
+// profile: a sample step, or the nearest stored state to one (N - 1 for k = N)
+bool profile_sample(int N, long long k)
+{
+    for (int j = 1; j < kProfile; ++j)
+        if (std::min<long long>(std::max<long long>(profile_step(N, j), 1), N - 1) == k) return true;
+    return false;
+}
+
 void profile_from_sizes(const std::vector<uint64_t> &sz, int N, double empty_bytes, double *prof)
 {
     prof[0] = empty_bytes;
@@ -1123,6 +1132,10 @@ struct GradRun {
     size_t S = 0;                      // bytes of one uncompressed checkpoint (two field arrays)
     size_t Sd = 0;                     // 8 bytes per grid point: the dense pair that ratios refer to
     long advances = 0, stores = 0, restores = 0, reverses = 0, decodes = 0, fields = 0;
+    // a first attempt that stores every state without a plan: it stops before the reversal
+    // if the arena overflowed, and once it is full encodes only the profile's sample states
+    bool optimistic = false, arena_full = false;
+    long opt_stores = 0;
     // stream bytes of an all-zero field: prefix plus one bit per block
     double empty_field_bytes() const
     {
@@ -1224,13 +1237,22 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
             if (comp) {
                 // u^k at offs[2b]; with both levels the increment u^k - u^{k-1} follows at
                 // offs[2b+1]; the next slot starts at offs[2b+2]
-                if (need2[i]) {
+                const bool skip = R.optimistic && R.arena_full && !profile_sample(N, a);
+                if (skip) {
+                    // the arena is full: this attempt will stop, and only the profile's
+                    // samples are still measured
+                } else if (need2[i]) {
                     if ((rc = R.encode_field(f.u, nullptr, d.offs + 2 * b, d.offs + 2 * b + 1, d.sizes + a))) break;
                     if ((rc = R.encode_field(f.u, f.up, d.offs + 2 * b + 1, d.offs + 2 * b + 2))) break;
                 } else {
                     if ((rc = R.encode_field(f.u, nullptr, d.offs + 2 * b, d.offs + 2 * b + 2, d.sizes + a))) break;
                 }
                 if (hot_slot == b) hot_slot = -1;
+                if (R.optimistic && !R.arena_full && ++R.opt_stores % 128 == 0) {
+                    unsigned e = 0;
+                    if ((rc = read_err(d, s, &e))) break;
+                    if (e & 4u) R.arena_full = true;
+                }
             } else {
                 uint8_t *slot = d.arena + (size_t)(b - 1) * R.S;
                 HIPCHK(hipMemcpyAsync(slot, f.u, fb, hipMemcpyDeviceToDevice, s));
@@ -1265,6 +1287,14 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
         case FREE:
             break;
         case REVERSE: {
+            if (R.optimistic && R.reverses == 0) {
+                unsigned e = 0;
+                if ((rc = read_err(d, s, &e))) break;
+                if (e & 4u) {   // not every state fits: the caller plans from the sizes
+                    rc = WV_EARENA;
+                    break;
+                }
+            }
             if (!residual_ready) {
                 HIPCHK(launch_check_finite(f.u, P, d.err, s));
                 HIPCHK(launch_residual_misfit(data, R.dobs, d.res, (long long)(N + 1) * R.geo->nrec, R.geo->nrec,
@@ -1302,7 +1332,11 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
         }
         if (rc == WV_OK && op != FREE) rc = timer.end();
     }
-    if (rc) return rc;
+    if (rc) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return rc;
+    }
     HIPCHK(hipEventRecord(e1, s));
     unsigned e = 0;
     unsigned long long st[2] = {0, 0};
@@ -1436,10 +1470,24 @@ int gradient_common(const wv_model *m, const wv_geom *geo, const float *residual
         if (ratio_hint > 0) {
             F = ratio_hint;
         } else {
-            // probe the compressibility, then take the largest slot count whose peak
-            // arena use, simulated over the exact schedule with the measured sizes, fits
+            // First store every state (the compression-only mode): when the arena holds
+            // them all this is the run, and no plan is needed.  Otherwise the attempt
+            // stops before the reversal, having measured the states' stream sizes (once
+            // the arena is full, only the profile's samples), and the call takes the
+            // largest slot count whose peak arena use, simulated over the exact schedule
+            // with those sizes, fits.
+            R.optimistic = true;
+            const double Fall = ratio_for_slots(N, mem_budget, R.Sd, N);
+            rc = run_gradient(R, N, Fall > 0 ? Fall : 1.0, stats, misfit);
+            R.optimistic = false;
+            if (rc != WV_EARENA) return rc;
+            std::vector<uint64_t> sz((size_t)N + 1, 0);
+            HIPCHK(hipMemcpy(sz.data(), d.sizes, sz.size() * 8, hipMemcpyDeviceToHost));
             double prof[kProfile];
-            if ((rc = probe_ratio(R, &F, prof))) return rc;
+            profile_from_sizes(sz, N, R.empty_field_bytes(), prof);
+            HIPCHK(launch_fill_u64(at<uint64_t>(d.base, d.L.bk), kBk / 8, 0, s));
+            R.advances = R.stores = R.restores = R.reverses = R.decodes = R.fields = 0;
+            R.max_depth = 0;
             if (profile_valid(prof)) {
                 const int Mp = plan_slots_profile(N, mem_budget, prof);
                 if (Mp > 1) F = ratio_for_slots(N, mem_budget, R.Sd, Mp);

@@ -140,7 +140,7 @@ def test_fault_body_ot4_all_3000_steps_properties():
     """The same properties for the OT4 kernel on the large shot (its own CFL step, 3000
     steps): plain Revolve bit-identical at 31 and 61 slots with the binomial number of
     forward steps, the misfit independent of the checkpoint strategy, the compressed
-    gradient (planned from the probed profile, no retry) within 10 tol of the plain one."""
+    gradient (no ratio hint, no retry) within 10 tol of the plain one."""
     import torch
     shot = W.fault_body_3d()
     Gt, _ = gpu_side(shot, "true", time_order=4)

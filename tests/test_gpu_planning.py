@@ -50,15 +50,46 @@ def test_profile_plan_fits_without_retry(tol):
         assert M >= m_final
 
 
+def test_cold_call_stores_every_state_when_it_fits():
+    """Without a hint, a budget that holds every compressed state is used on the first
+    attempt: every state is stored, with no plan and no repeat, and the gradient is the
+    one a hinted call with the same slots computes."""
+    import paper_1810_05268_amd as P
+    shot = small_3d(nt=240)
+    Gt, _ = gpu_side(shot, "true")
+    d_obs = Gt.forward()
+    G, _ = gpu_side(shot)
+    budget = 8 * G.P * (shot.nt + 1)
+    phi, g, st = G.misfit_gradient(d_obs, budget, 1e-4)
+    assert st["retries"] == 0 and st["slots"] == shot.nt
+    assert st["stores"] == shot.nt - 1 and st["advances"] == shot.nt
+    assert st["peak_bytes"] <= budget
+    M, h = P.plan(shot.nt, G.P, budget, st["profile"])
+    assert M == shot.nt
+    phi2, g2, st2 = G.misfit_gradient(d_obs, budget, 1e-4, ratio_hint=h)
+    assert st2["slots"] == shot.nt and st2["retries"] == 0
+    assert phi2 == phi
+    assert np.array_equal(g.cpu().numpy(), g2.cpu().numpy())
+
+
 def test_no_hint_plans_from_a_probe():
-    """Without a hint the library probes the shot's profile first and plans from it."""
+    """Without a hint, a budget too small for every state: the first attempt stops before
+    the reversal with the states' stream sizes measured, and the call plans from them the
+    slots wv_plan gives for the same profile, with no repeat of the planned run."""
+    import paper_1810_05268_amd as P
     shot = small_3d(nt=240)
     Gt, _ = gpu_side(shot, "true")
     d_obs = Gt.forward()
     G, _ = gpu_side(shot)
     _, _, st0 = G.misfit_gradient(d_obs, 8 * G.P * (shot.nt + 1), 1e-4)
     budget = int(0.25 * _trajectory_bytes(st0["profile"], shot.nt))
-    _, _, st = G.misfit_gradient(d_obs, budget, 1e-4)
+    phi, g, st = G.misfit_gradient(d_obs, budget, 1e-4)
     assert st["retries"] == 0
     assert st["peak_bytes"] <= budget
-    assert st["slots"] > 1
+    M, h = P.plan(shot.nt, G.P, budget, st0["profile"])
+    assert 1 < st["slots"] == M < shot.nt
+    # the hinted call with that plan computes the same gradient
+    phi2, g2, st2 = G.misfit_gradient(d_obs, budget, 1e-4, ratio_hint=h)
+    assert st2["slots"] == M
+    assert phi2 == phi
+    assert np.array_equal(g.cpu().numpy(), g2.cpu().numpy())
