@@ -305,7 +305,7 @@ int hip_fail(hipError_t e, const char *what, int line)
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-    size_t bk, U0, U1, L0, L1, W, Z, UB, DB, V, VU;
+    size_t bk, U0, U1, L0, L1, W, Z, UB, DB, V, VU, CR;
     size_t src_tab, rec_tab, tab_bytes;
     size_t res, dsim, partials, enc, offs, sizes, arena;
     size_t total;
@@ -710,6 +710,8 @@ Layout plan_layout(const wv_model *m, const wv_geom *geo, const Setup &su, int o
         L.UB = take(fb);
         L.DB = take(fb);
         if (ot4) L.VU = take(fb);               // OT4 adjoint: w lap u^k for the gradient term
+        // 3-D OT2 adjoint: the gradient term an even step carries to the next one
+        if (!ot4 && su.ndim == 3) L.CR = take(fb);
         L.res = take(data_bytes);
         L.dsim = take(data_bytes);
         L.partials = take(kParts * 8);
@@ -731,7 +733,7 @@ struct Dev {
     uint8_t *base;
     Layout L;
     Sparse src, rec;
-    float *U[2], *Lm[2], *W, *Z, *UB, *DB, *V = nullptr, *VU = nullptr;
+    float *U[2], *Lm[2], *W, *Z, *UB, *DB, *V = nullptr, *VU = nullptr, *CR = nullptr;
     unsigned *err;
     double *misfit;
     unsigned long long *stats;
@@ -800,6 +802,7 @@ int bind(Dev &d, void *ws, size_t ws_bytes, const Layout &L, int op)
         d.Lm[0] = at<float>(d.base, L.L0);
         d.Lm[1] = at<float>(d.base, L.L1);
         if (L.VU) d.VU = at<float>(d.base, L.VU);
+        if (L.CR) d.CR = at<float>(d.base, L.CR);
         d.UB = at<float>(d.base, L.UB);
         d.DB = at<float>(d.base, L.DB);
         d.res = at<float>(d.base, L.res);
@@ -1318,7 +1321,12 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
                 HIPCHK(launch_ot4_update(R.su.g, d.V, d.Lm[lc], d.Lm[lc ^ 1], d.Lm[lc ^ 1], d.W, uk, uk ? d.VU : nullptr,
                                          R.G, gscale, s, le));
             } else {
-                HIPCHK(launch_adj_step(R.su.g, d.Lm[lc], d.Lm[lc ^ 1], d.Lm[lc ^ 1], d.W, uk, R.G, gscale, s, le));
+                // 3-D: the steps k = 2j and 2j - 1 update G once between them (the even
+                // step carries its term); an odd first step k = N adds its own
+                int gm = kGAdd;
+                if (uk && d.CR) gm = a % 2 == 0 ? kGCarryOut : (a < N ? kGCarryIn : kGAdd);
+                HIPCHK(launch_adj_step(R.su.g, d.Lm[lc], d.Lm[lc ^ 1], d.Lm[lc ^ 1], d.W, uk, R.G, gscale, s, le,
+                                       d.CR, gm));
             }
             HIPCHK(launch_inject_res(R.su.g, d.rec, res + (size_t)a * R.geo->nrec, d.W, d.Lm[lc ^ 1], uk, R.G,
                                      gscale, s));

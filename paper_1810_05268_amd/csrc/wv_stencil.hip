@@ -86,14 +86,23 @@ __device__ __forceinline__ void ntstore4(float *p, float a, float b, float c, fl
 //          GRAD adds both OT4 gradient terms in one update,
 //          gscale [u^k (v + (w/12) L) + v vu / 12], where vu = w lap u^k comes pointwise
 //          from xtra2 (the second is the term of the m inside the OT4 operator).
-template <int K, bool GRAD, bool VEC, int MODE>
+// GM selects how the gradient term t = u^k (w L) of an OT2 step reaches G:
+//   kGNone: no gradient;  kGAdd: G += gscale t;
+//   kGCarryOut: cr = t rounded to binary32, G untouched;
+//   kGCarryIn:  G += gscale (t + cr), cr from the kGCarryOut step before.
+// A pair of adjoint steps thus reads and writes the binary64 gradient once.
+template <int K, int GM, bool VEC, int MODE>
 __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *__restrict__ fin,
                                                  const float *prev, float *fout, const float *__restrict__ w,
                                                  const float *__restrict__ uk, const float *__restrict__ xtra,
                                                  const float *__restrict__ xtra2, double *__restrict__ G,
-                                                 double gscale, int tiles_x, int tiles_y, int zchunks, int zlen)
+                                                 float *__restrict__ cr, double gscale, int tiles_x, int tiles_y,
+                                                 int zchunks, int zlen)
 {
+    constexpr bool GRAD = GM != kGNone;                    // u^k is read
+    constexpr bool GRW = GM == kGAdd || GM == kGCarryIn;    // G is read and written
     static_assert(!(GRAD && MODE == kLapW), "the w lap pass carries no gradient term");
+    static_assert(MODE == kOT2 || GM == kGNone || GM == kGAdd, "carried gradient terms are OT2 only");
     constexpr int TX = 32, TY = 32;
     constexpr int HX = (K + 3) / 4 * 4;          // x halo columns (>= K, multiple of 4)
     constexpr int LX = TX + 2 * HX, LY = TY + 2 * K;
@@ -174,8 +183,8 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
     };
 
     struct Stage {
-        float4 p, w, u, c, h, f;
-        double g[GRAD ? 4 : 1];
+        float4 p, w, u, c, h, f, t;
+        double g[GRW ? 4 : 1];
     };
     // loads that computing plane z needs: its point operands (with GRAD also u^k and
     // the gradient), the halo of plane z+1+K and the queue front of plane z+1+K
@@ -192,8 +201,9 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
         if constexpr (MODE != kLapW) S.p = load4p(prev, z, x0);
         S.w = load4p(w, z, x0);
         if constexpr (MODE == kOT4) S.c = load4p(xtra, z, x0);
-        if constexpr (GRAD) {
-            S.u = load4p(uk, z, x0);
+        if constexpr (GRAD) S.u = load4p(uk, z, x0);
+        if constexpr (GM == kGCarryIn) S.t = load4p(cr, z, x0);
+        if constexpr (GRW) {
             const long long pg = ((long long)min(z, nz - 1) * ny + min(y, ny - 1)) * nx;   // dense
             if constexpr (VEC) {
                 // two 16-byte loads per lane, normally cached: the line a lane pair shares
@@ -233,7 +243,7 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
         // the binary64 gradient of this plane arrived with the stage (clamped address,
         // no branch; only in-range lanes store the update)
         double gold[4] = {0.0, 0.0, 0.0, 0.0};
-        if constexpr (GRAD) {
+        if constexpr (GRW) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) gold[i] = S.g[i];
         }
@@ -331,13 +341,28 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
                 for (int i = 0; i < 4; ++i)
                     if (x0 + i < nx) fout[p0 + i] = on[i];
             }
-            if constexpr (GRAD) {
+            if constexpr (GM == kGCarryOut) {
+                float t[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) t[i] = uin[i] * wl[i];
+                if constexpr (VEC) {
+                    ntstore4(cr + p0, t[0], t[1], t[2], t[3]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (x0 + i < nx) cr[p0 + i] = t[i];
+                }
+            }
+            if constexpr (GRW) {
+                const float tin[4] = {S.t.x, S.t.y, S.t.z, S.t.w};
                 double gn[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     if constexpr (MODE == kOT4)   // v vu / 12 rounded once in binary32
                         gn[i] = gold[i] + gscale * ((double)uin[i] * (double)wl[i] +
                                                     (double)(q[i][K] * c2in[i] * (1.0f / 12.0f)));
+                    else if constexpr (GM == kGCarryIn)
+                        gn[i] = gold[i] + gscale * ((double)uin[i] * (double)wl[i] + (double)tin[i]);
                     else
                         gn[i] = gold[i] + gscale * (double)uin[i] * (double)wl[i];
                 }
@@ -364,10 +389,10 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
         q[0][2 * K] = S.f.x; q[1][2 * K] = S.f.y; q[2][2 * K] = S.f.z; q[3][2 * K] = S.f.w;
     };
     // AHEAD = 2: three stages in rotation, six planes per trip; otherwise without the
-    // gradient two stages, four planes per trip (the wait pass drains outstanding loads
-    // at the back-edge); with the gradient, whose stage also carries u^k and the
-    // binary64 gradient, one plane per trip and the stage handed over by copy, which
-    // keeps it within 256 registers without spilling
+    // binary64 gradient two stages, four planes per trip (the wait pass drains
+    // outstanding loads at the back-edge); with it, whose stage also carries u^k and
+    // the gradient, one plane per trip and the stage handed over by copy, which keeps
+    // it within 256 registers without spilling
     int z = z0;
     if constexpr (AHEAD == 2) {
         for (; z + 5 < z1; z += 6) {
@@ -385,7 +410,7 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
         }
         if (z < z1) step(z, A, C);
         if (z + 1 < z1) step(z + 1, B, A);
-    } else if constexpr (!GRAD) {
+    } else if constexpr (!GRW) {
         (void)C;
         for (; z + 3 < z1; z += 4) {
             step(z, A, B);
@@ -626,33 +651,36 @@ void launch_timed(Kern kern, dim3 grid, hipStream_t s, LaunchEvents ev, Args... 
         hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, args...);
 }
 
-template <int K, bool GRAD, bool VEC, int MODE>
+template <int K, int GM, bool VEC, int MODE>
 hipError_t launch3d(const Grid &g, const float *fin, const float *prev, float *fout, const float *w,
-                    const float *uk, const float *xtra, const float *xtra2, double *G, double gscale, hipStream_t s,
-                    LaunchEvents ev)
+                    const float *uk, const float *xtra, const float *xtra2, double *G, float *cr, double gscale,
+                    hipStream_t s, LaunchEvents ev)
 {
-    auto kern = stencil3d<K, GRAD, VEC, MODE>;
+    auto kern = stencil3d<K, GM, VEC, MODE>;
     const int tiles_x = (g.nx + 31) / 32, tiles_y = (g.ny + 31) / 32;
     // one resident round of workgroups: z chunks as long as possible (the 2K-plane
     // warm-up of each chunk re-reads the field), but enough of them to fill the GPU
     int zchunks, zlen;
     choose_chunks((long long)tiles_x * tiles_y, g.nz, 4 * K, resident_workgroups(kern), zchunks, zlen);
     const int nwg = tiles_x * tiles_y * zchunks;
-    launch_timed(kern, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, tiles_x, tiles_y,
+    launch_timed(kern, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, tiles_x, tiles_y,
                  zchunks, zlen);
     return hipGetLastError();
 }
 
-template <int K, bool GRAD, int MODE>
+template <int K, int GM, int MODE>
 hipError_t launch_k(const Grid &g, const float *fin, const float *prev, float *fout, const float *w,
-                    const float *uk, const float *xtra, const float *xtra2, double *G, double gscale, hipStream_t s,
-                    LaunchEvents ev)
+                    const float *uk, const float *xtra, const float *xtra2, double *G, float *cr, double gscale,
+                    hipStream_t s, LaunchEvents ev)
 {
     if (g.ndim == 3) {
         if (g.nx % 4 == 0)
-            return launch3d<K, GRAD, true, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
-        return launch3d<K, GRAD, false, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
+            return launch3d<K, GM, true, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
+        return launch3d<K, GM, false, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
     }
+    if constexpr (GM == kGCarryOut || GM == kGCarryIn) {
+        return hipErrorInvalidValue;   // 2-D steps add their gradient term directly
+    } else {
     // 2-D grids are small (a few MB): a step is bound by the latency of each workgroup's
     // plane-by-plane march, not by bandwidth, so chunks are short (down to K planes, whose
     // 2K-plane warm-up loads are issued together) and the workgroups many
@@ -660,25 +688,26 @@ hipError_t launch_k(const Grid &g, const float *fin, const float *prev, float *f
     int zchunks, zlen;
     choose_chunks(tiles_x, g.nz, K, 2048, zchunks, zlen);
     const int nwg = tiles_x * zchunks;
-    launch_timed(stencil2d<K, GRAD, MODE>, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale,
-                 tiles_x, zchunks, zlen);
+    launch_timed(stencil2d<K, GM == kGAdd, MODE>, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, xtra, xtra2, G,
+                 gscale, tiles_x, zchunks, zlen);
     return hipGetLastError();
+    }
 }
 
-template <bool GRAD, int MODE>
+template <int GM, int MODE>
 hipError_t launch_any(const Grid &g, const float *fin, const float *prev, float *fout, const float *w,
                       const float *uk, const float *xtra, const float *xtra2, double *G, double gscale, hipStream_t s,
-                      LaunchEvents ev)
+                      LaunchEvents ev, float *cr = nullptr)
 {
     switch (g.K) {
-    case 1: return launch_k<1, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
-    case 2: return launch_k<2, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
-    case 3: return launch_k<3, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
-    case 4: return launch_k<4, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
-    case 5: return launch_k<5, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
-    case 6: return launch_k<6, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
-    case 7: return launch_k<7, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
-    case 8: return launch_k<8, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, s, ev);
+    case 1: return launch_k<1, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
+    case 2: return launch_k<2, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
+    case 3: return launch_k<3, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
+    case 4: return launch_k<4, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
+    case 5: return launch_k<5, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
+    case 6: return launch_k<6, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
+    case 7: return launch_k<7, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
+    case 8: return launch_k<8, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
     default: return hipErrorInvalidValue;
     }
 }
@@ -688,28 +717,40 @@ hipError_t launch_any(const Grid &g, const float *fin, const float *prev, float 
 hipError_t launch_fwd_step(const Grid &g, const float *u_in, const float *u_prev, float *u_out, const float *w,
                            hipStream_t s, LaunchEvents ev)
 {
-    return launch_any<false, kOT2>(g, u_in, u_prev, u_out, w, nullptr, nullptr, nullptr, nullptr, 0.0, s, ev);
+    return launch_any<kGNone, kOT2>(g, u_in, u_prev, u_out, w, nullptr, nullptr, nullptr, nullptr, 0.0, s, ev);
 }
 
 hipError_t launch_adj_step(const Grid &g, const float *lam_in, const float *lam_next, float *lam_out,
                            const float *w, const float *uk, double *G, double gscale, hipStream_t s,
-                           LaunchEvents ev)
+                           LaunchEvents ev, float *carry, int gmode)
 {
-    if (G) return launch_any<true, kOT2>(g, lam_in, lam_next, lam_out, w, uk, nullptr, nullptr, G, gscale, s, ev);
-    return launch_any<false, kOT2>(g, lam_in, lam_next, lam_out, w, nullptr, nullptr, nullptr, nullptr, 0.0, s, ev);
+    if (!G) return launch_any<kGNone, kOT2>(g, lam_in, lam_next, lam_out, w, nullptr, nullptr, nullptr, nullptr, 0.0,
+                                            s, ev);
+    if (gmode != kGAdd && (g.ndim != 3 || !carry)) return hipErrorInvalidValue;
+    switch (gmode) {
+    case kGAdd:
+        return launch_any<kGAdd, kOT2>(g, lam_in, lam_next, lam_out, w, uk, nullptr, nullptr, G, gscale, s, ev);
+    case kGCarryOut:
+        return launch_any<kGCarryOut, kOT2>(g, lam_in, lam_next, lam_out, w, uk, nullptr, nullptr, G, gscale, s, ev,
+                                            carry);
+    case kGCarryIn:
+        return launch_any<kGCarryIn, kOT2>(g, lam_in, lam_next, lam_out, w, uk, nullptr, nullptr, G, gscale, s, ev,
+                                           carry);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_lapw(const Grid &g, const float *f, float *v_out, const float *w, hipStream_t s, LaunchEvents ev)
 {
-    return launch_any<false, kLapW>(g, f, nullptr, v_out, w, nullptr, nullptr, nullptr, nullptr, 0.0, s, ev);
+    return launch_any<kGNone, kLapW>(g, f, nullptr, v_out, w, nullptr, nullptr, nullptr, nullptr, 0.0, s, ev);
 }
 
 hipError_t launch_ot4_update(const Grid &g, const float *v, const float *u_in, const float *u_prev, float *u_out,
                              const float *w, const float *uk, const float *vu, double *G, double gscale, hipStream_t s,
                              LaunchEvents ev)
 {
-    if (G) return launch_any<true, kOT4>(g, v, u_prev, u_out, w, uk, u_in, vu, G, gscale, s, ev);
-    return launch_any<false, kOT4>(g, v, u_prev, u_out, w, nullptr, u_in, nullptr, nullptr, 0.0, s, ev);
+    if (G) return launch_any<kGAdd, kOT4>(g, v, u_prev, u_out, w, uk, u_in, vu, G, gscale, s, ev);
+    return launch_any<kGNone, kOT4>(g, v, u_prev, u_out, w, nullptr, u_in, nullptr, nullptr, 0.0, s, ev);
 }
 
 hipError_t launch_inject_src(const Grid &g, const Sparse &sp, const float *q, int n, const float *w,
