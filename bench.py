@@ -169,9 +169,11 @@ def full_trajectory_bytes(st, nt):
 
 
 def stream_ceilings(stream_bytes=256 * 1000 * 1000, reps=10):
-    """Measured HBM ceilings in this process (wv_stream_ceiling): nontemporal streams of
-    3 reads + 1 write (the forward stencil's mix) and 4 reads + 1 write, 256 MB each (the
-    large grid's field size), GB/s of bytes read plus written; the best of reps."""
+    """Measured HBM ceilings in this process (wv_stream_ceiling): streams of 3 reads + 1
+    write (the forward stencil's mix) and 4 reads + 1 write, 256 MB each (the large grid's
+    field size), the first read through the caches and the others and the write
+    nontemporal, as the stencils access their arrays; GB/s of bytes read plus written,
+    the best of reps."""
     import torch
     import paper_1810_05268_amd as P
     ws = torch.empty(5 * stream_bytes + 256, dtype=torch.uint8, device="cuda")
@@ -706,8 +708,9 @@ def main():
     # algorithmic rate of "achieved"
     roof["hbm_gbs"] = roof["adjoint_step" if dom == "adjoint" else "forward_step"]["hbm_gbs"]
     roof["ceiling"] = stream_ceilings()
-    roof["ceiling_note"] = ("hand-written nontemporal streams (wv_stream_ceiling), 256 MB per array, bytes read "
-                            "plus written per second: the measured ceiling for the stencils' access mix")
+    roof["ceiling_note"] = ("hand-written streams (wv_stream_ceiling), 256 MB per array, one read through the "
+                            "caches and the others and the write nontemporal, bytes read plus written per second: "
+                            "the measured ceiling for the stencils' access mix")
     st = st_comp_ph[0]
     ms_per_store = st["ms_store"] / st["stores"] if st["stores"] else None
     ms_per_decode = st["ms_restore"] / st["decodes"] if st["decodes"] else None

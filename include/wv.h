@@ -483,8 +483,10 @@ int wv_choose(int nt, long long points, size_t mem_budget, const wv_costs *plain
               const double *profile, int nprofile, wv_choice *out);
 
 /* Measurement hook: the HBM ceiling of this device for a streaming kernel that reads
- * `reads` (1..4) arrays and writes one, each stream_bytes long, with nontemporal
- * accesses, four 16-byte loads per lane in flight, over ws (at least (reads + 1)
+ * `reads` (1..4) arrays and writes one, each stream_bytes long, four 16-byte loads per
+ * lane in flight: the first array is read through the caches and the others and the
+ * written one with nontemporal accesses, the stencils' mix (their marched field cached,
+ * their pointwise operands and output nontemporal), over ws (at least (reads + 1)
  * stream_bytes, 256-byte aligned; overwritten).  *gbs receives the best of reps timed
  * launches, in GB/s (bytes read plus written).  Synchronises the stream. */
 int wv_stream_ceiling(int reads, size_t stream_bytes, void *ws, size_t ws_bytes, int reps, double *gbs, void *stream);
