@@ -926,9 +926,10 @@ struct Fwd {
         u = cur;
         up = prev;
     }
-    int step(int n, float *data_row)
+    // dest (nullable): where u^{n+1} goes instead of a work level (a checkpoint slot)
+    int step(int n, float *data_row, float *dest = nullptr)
     {
-        float *out = (u == d.U[0]) ? d.U[1] : d.U[0];
+        float *out = dest ? dest : ((u == d.U[0]) ? d.U[1] : d.U[0]);
         int rc;
         LaunchEvents le;
         if (kt && (rc = kt->pair(0, &le))) return rc;
@@ -1224,10 +1225,24 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
                 f.up = d.DB;
                 up_pending = false;
             }
-            for (int n = a; n < b; ++n) {
-                float *row = (data && n + 1 > gathered) ? data + (size_t)(n + 1) * R.geo->nrec : nullptr;
-                if ((rc = f.step(n, row))) break;
-                if (row) gathered = n + 1;
+            {
+                // Uncompressed, an advance that ends in the state the next action stores
+                // writes that state straight into its slot (and, when the slot keeps both
+                // levels and the advance has two steps or more, u^{b-1} too): the store
+                // then copies nothing.  Slots are only read afterwards, as after a restore.
+                float *dst_last = nullptr, *dst_prev = nullptr;
+                if (!comp && i + 1 < nact && acts[3 * (i + 1)] == STORE && acts[3 * (i + 1) + 1] == b &&
+                    acts[3 * (i + 1) + 2] >= 1) {
+                    float *slot = reinterpret_cast<float *>(d.arena + (size_t)(acts[3 * (i + 1) + 2] - 1) * R.S);
+                    dst_last = slot;
+                    if (need2[i + 1] && b - a >= 2) dst_prev = slot + P;
+                }
+                for (int n = a; n < b && rc == WV_OK; ++n) {
+                    float *row = (data && n + 1 > gathered) ? data + (size_t)(n + 1) * R.geo->nrec : nullptr;
+                    float *dest = n == b - 1 ? dst_last : (n == b - 2 ? dst_prev : nullptr);
+                    if ((rc = f.step(n, row, dest))) break;
+                    if (row) gathered = n + 1;
+                }
             }
             R.advances += b - a;
             break;
@@ -1257,9 +1272,12 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
                     if (e & 4u) R.arena_full = true;
                 }
             } else {
+                // copy only the levels the advance before did not write in place
                 uint8_t *slot = d.arena + (size_t)(b - 1) * R.S;
-                HIPCHK(hipMemcpyAsync(slot, f.u, fb, hipMemcpyDeviceToDevice, s));
-                if (need2[i]) HIPCHK(hipMemcpyAsync(slot + fb, f.up, fb, hipMemcpyDeviceToDevice, s));
+                if ((const void *)f.u != (const void *)slot)
+                    HIPCHK(hipMemcpyAsync(slot, f.u, fb, hipMemcpyDeviceToDevice, s));
+                if (need2[i] && (const void *)f.up != (const void *)(slot + fb))
+                    HIPCHK(hipMemcpyAsync(slot + fb, f.up, fb, hipMemcpyDeviceToDevice, s));
             }
             R.stores++;
             R.fields += need2[i] ? 2 : 1;
