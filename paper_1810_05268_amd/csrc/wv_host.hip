@@ -1234,8 +1234,13 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
                 if (!comp && i + 1 < nact && acts[3 * (i + 1)] == STORE && acts[3 * (i + 1) + 1] == b &&
                     acts[3 * (i + 1) + 2] >= 1) {
                     float *slot = reinterpret_cast<float *>(d.arena + (size_t)(acts[3 * (i + 1) + 2] - 1) * R.S);
-                    dst_last = slot;
-                    if (need2[i + 1] && b - a >= 2) dst_prev = slot + P;
+                    // never into the levels the advance starts from (a slot restored and
+                    // stored again): those are read while the steps write
+                    const bool clash = f.u == slot || f.u == slot + P || f.up == slot || f.up == slot + P;
+                    if (!clash) {
+                        dst_last = slot;
+                        if (need2[i + 1] && b - a >= 2) dst_prev = slot + P;
+                    }
                 }
                 for (int n = a; n < b && rc == WV_OK; ++n) {
                     float *row = (data && n + 1 > gathered) ? data + (size_t)(n + 1) * R.geo->nrec : nullptr;
