@@ -44,7 +44,8 @@ class WaveMisfit(torch.autograd.Function):
                                                    problem.ratio_hint)
         problem.last_stats = st
         if problem.tol > 0 and problem.ratio_hint <= 0 and all(x > 0 for x in st["profile"]):
-            # plan later calls from the compressibility this one measured (no probe run)
+            # plan later calls from the compressibility this one measured (they skip the
+            # unhinted first attempt that stores every state)
             _, h = B.plan(problem.shot.nt, problem.shot.P, problem.mem_budget, st["profile"])
             problem.ratio_hint = h if h > 0 else 0.95 * st["ratio_planned"]
         gv = torch.empty(v.shape, dtype=torch.float64, device=v.device)
