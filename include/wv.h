@@ -248,7 +248,7 @@ int wv_velocity_gradient(int ndim, const int *n, int nbl, const float *vel_padde
  * Guarantees |x - decode(encode(x))| <= tol where binary32 can resolve tol. */
 
 /* Device scratch bytes wv_zfpk_encode needs (per chunk of 256 blocks: its word count,
- * its offset and an 8 KiB staging slot). */
+ * its offset and a 16 KiB staging slot). */
 size_t wv_zfpk_workspace_bytes(int ndim, const int *dims);
 
 /* Upper bound of the stream size for these dims (any tolerance). */

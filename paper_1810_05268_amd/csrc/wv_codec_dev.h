@@ -534,7 +534,7 @@ __device__ __forceinline__ void store_block(float *field, const float *sub, cons
     }
 }
 
-constexpr int kLdsWords = 1024;      // chunk bitstreams up to 8 KB are assembled in LDS
+constexpr int kLdsWords = 2048;      // chunk bitstreams up to 16 KB are assembled in LDS
 constexpr int kDecLdsWords = 2048;   // and chunks up to 16 KB are staged in LDS for decoding
 
 }  // namespace
