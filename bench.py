@@ -309,7 +309,8 @@ def kernels_mode():
 
 def codec_kernels_mode(nt=1500, tol=1e-4, reps=5):
     """Short workload for the codec's counter and trace passes: the large shot's forward
-    run to step nt (a mid-run state, compressed about 70x at 1e-4), then `reps` encodes
+    run to step nt (1500: a mid-run state, compressed about 70x at 1e-4; 2900: a late
+    one, about 20x), then `reps` encodes
     and decodes of u^nt alone and `reps` encodes of u^nt - u^(nt-1) (the second-level
     form the compressed reversal stores)."""
     import numpy as np
@@ -601,13 +602,14 @@ def main():
                                                                       "('' = none)")
     ap.add_argument("--kernels", action="store_true", help="short kernel workload for counter passes only")
     ap.add_argument("--codec-kernels", action="store_true", help="short codec workload for counter passes only")
+    ap.add_argument("--codec-nt", type=int, default=1500, help="state the codec workload encodes (its step)")
     ap.add_argument("--no-ot4", action="store_true", help="skip the OT4 comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of it"}))
         sys.exit(2)
     if args.codec_kernels:
-        codec_kernels_mode()
+        codec_kernels_mode(nt=args.codec_nt)
         return
     if args.kernels:
         kernels_mode()
