@@ -324,7 +324,7 @@ struct Setup {
     long long P = 0;        // grid points (the caller's dense arrays)
     long long Pf = 0;       // elements of one solver field array (rows pitched, see Grid)
     int ndim = 0, N[3] = {1, 1, 1};
-    int nc = 4;
+    int src_nc = 4, rec_nc = 4;   // corners per source / receiver in the gather tables
     // host tables, packed
     std::vector<int> src_gidx, rec_gidx, src_pts, src_start, src_col, rec_pts, rec_start, rec_col;
     std::vector<float> src_gwt, rec_gwt, src_swt, rec_swt;
@@ -615,21 +615,47 @@ int point_weights(const wv_model *m, const Setup &su, const double *xyz, int *id
 // gather tables plus the transposed (scatter) table with unique points
 int build_sparse(const wv_model *m, const Setup &su, int npt, const double *xyz, bool shared_col,
                  std::vector<int> &gidx, std::vector<float> &gwt, std::vector<int> &pts, std::vector<int> &start,
-                 std::vector<int> &col, std::vector<float> &swt)
+                 std::vector<int> &col, std::vector<float> &swt, int &nc_out)
 {
-    const int nc = m->ndim == 3 ? 8 : 4;
+    const int nc_all = m->ndim == 3 ? 8 : 4;
+    std::vector<int> gi((size_t)npt * nc_all, 0);
+    std::vector<float> gw((size_t)npt * nc_all, 0.0f);
+    for (int r = 0; r < npt; ++r) {
+        const int rc = point_weights(m, su, xyz + (size_t)r * m->ndim, &gi[(size_t)r * nc_all], &gw[(size_t)r * nc_all]);
+        if (rc) return rc;
+    }
+    // A corner of weight zero (a point on a grid line or node) adds nothing to a gather
+    // or a scatter: the tables keep the others, in corner order, each point padded to the
+    // largest count with zero weights at its first corner (so a sum takes the same
+    // values in the same order, without the zero terms).
+    int nc = 1;
+    for (int r = 0; r < npt; ++r) {
+        int k = 0;
+        for (int c = 0; c < nc_all; ++c) k += gw[(size_t)r * nc_all + c] != 0.0f;
+        nc = std::max(nc, k);
+    }
     gidx.assign((size_t)npt * nc, 0);
     gwt.assign((size_t)npt * nc, 0.0f);
     for (int r = 0; r < npt; ++r) {
-        const int rc = point_weights(m, su, xyz + (size_t)r * m->ndim, &gidx[(size_t)r * nc], &gwt[(size_t)r * nc]);
-        if (rc) return rc;
+        int j = 0;
+        for (int c = 0; c < nc_all; ++c) {
+            const size_t a = (size_t)r * nc_all + c;
+            if (gw[a] == 0.0f) continue;
+            gidx[(size_t)r * nc + j] = gi[a];
+            gwt[(size_t)r * nc + j] = gw[a];
+            ++j;
+        }
+        for (; j < nc; ++j) gidx[(size_t)r * nc + j] = gi[(size_t)r * nc_all];
     }
+    nc_out = nc;
     // entries sorted by (point, column, corner) for a fixed summation order
     struct E { int p, col, c; float w; };
     std::vector<E> es;
     es.reserve((size_t)npt * nc);
     for (int r = 0; r < npt; ++r)
-        for (int c = 0; c < nc; ++c) es.push_back({gidx[(size_t)r * nc + c], shared_col ? 0 : r, c, gwt[(size_t)r * nc + c]});
+        for (int c = 0; c < nc; ++c)
+            if (gwt[(size_t)r * nc + c] != 0.0f)
+                es.push_back({gidx[(size_t)r * nc + c], shared_col ? 0 : r, c, gwt[(size_t)r * nc + c]});
     std::sort(es.begin(), es.end(), [](const E &a, const E &b) {
         if (a.p != b.p) return a.p < b.p;
         if (a.col != b.col) return a.col < b.col;
@@ -660,12 +686,11 @@ int prepare(const wv_model *m, const wv_geom *geo, Setup &su)
     if (rc) return rc;
     if (!geo || geo->nsrc < 1 || geo->nrec < 1 || !geo->src_xyz || !geo->rec_xyz || !geo->wavelet)
         return WV_EINVAL;
-    su.nc = m->ndim == 3 ? 8 : 4;
     rc = build_sparse(m, su, geo->nsrc, geo->src_xyz, true, su.src_gidx, su.src_gwt, su.src_pts, su.src_start,
-                      su.src_col, su.src_swt);
+                      su.src_col, su.src_swt, su.src_nc);
     if (rc) return rc;
     return build_sparse(m, su, geo->nrec, geo->rec_xyz, false, su.rec_gidx, su.rec_gwt, su.rec_pts, su.rec_start,
-                        su.rec_col, su.rec_swt);
+                        su.rec_col, su.rec_swt, su.rec_nc);
 }
 
 size_t tab_bytes(const Setup &su, bool rec)
@@ -765,8 +790,9 @@ int upload_tables(Dev &d, const Setup &su, hipStream_t s)
             o = align_up(o + bytes, 256);
             return d.base + d.L.src_tab + here;
         };
-        sp.n = (int)(gidx.size() / su.nc);
-        sp.nc = su.nc;
+        const int nc = rec ? su.rec_nc : su.src_nc;
+        sp.n = (int)(gidx.size() / nc);
+        sp.nc = nc;
         sp.g_idx = (const int *)put(gidx.data(), gidx.size() * 4);
         sp.g_wt = (const float *)put(gwt.data(), gwt.size() * 4);
         sp.npts = (int)pts.size();
