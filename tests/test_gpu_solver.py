@@ -42,6 +42,44 @@ def test_forward_3d_orders_ragged(order, nxi):
     assert e_d <= WAVEFIELD_TOL and e_u <= WAVEFIELD_TOL
 
 
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_receivers_on_nodes_lines_and_between(ndim):
+    """Sources and receivers with every mix of zero interpolation weights: on grid nodes
+    (one nonzero corner), on grid lines (two or four) and between them (all corners).  The
+    sparse tables keep only the nonzero corners, padded per point; data, final state and
+    the uncompressed gradient against the oracle."""
+    import dataclasses
+    import torch
+    base = W.near_anomaly_2d(n=(61, 57), nt=200) if ndim == 2 else small_3d(nt=80)
+    h = np.array(base.h)
+    rng = np.random.default_rng(11)
+    ext = (np.array(base.n) - 1) * h
+    pts = []
+    for kind in range(4):
+        for _ in range(6):
+            x = rng.uniform(0.1, 0.9, ndim) * ext
+            if kind == 0:
+                x = np.round(x / h) * h                      # a node
+            elif kind == 1:
+                x[0] = np.round(x[0] / h[0]) * h[0]          # on a line through x
+            elif kind == 2:
+                x[1:] = np.round(x[1:] / h[1:]) * h[1:]      # on lines through the other axes
+            pts.append(x)
+    rec = np.array(pts, dtype=np.float64)
+    src = np.array([np.round(ext * 0.5 / h) * h], dtype=np.float64)   # a node
+    shot = dataclasses.replace(base, src=src, rec=rec)
+    S, _ = oracle_side(shot)
+    G, _ = gpu_side(shot)
+    ref = S.forward(want_last=True, want_traj=True)
+    data, state = G.forward(want_state=True)
+    assert rel_l2(data.cpu().numpy(), ref["data"]) <= WAVEFIELD_TOL
+    assert rel_l2(state[0].cpu().numpy(), ref["last"][0]) <= WAVEFIELD_TOL
+    res = np.random.default_rng(12).standard_normal(ref["data"].shape) * 1e-3
+    gref = S.gradient_full(ref["traj"], res)
+    g, _ = G.gradient(torch.as_tensor(res.astype(np.float32), device="cuda"), G.slot_bytes * shot.nt)
+    assert rel_l2(g.cpu().numpy(), gref) <= GRAD_TOL
+
+
 def test_forward_3d_longer_run():
     shot = small_3d(n=(60, 52, 70), nbl=10, order=8, nt=400, f0=15.0)
     S, _ = oracle_side(shot)
