@@ -193,7 +193,9 @@ int wv_forward(const wv_model *model, const wv_geom *geom, float *data, float *s
  *               schedule with those sizes, fits (as wv_plan).  That first attempt is
  *               not counted in stats->retries;
  *   tol         0: checkpoints are exact copies; > 0: absolute error bound of the codec
- *   grad_m      device [P] double, overwritten (layer cells included)
+ *   grad_m      device [P] double, overwritten (layer cells included); the sum over the
+ *               adjoint steps is formed in binary64, in 3-D OT2 runs one update per pair of
+ *               steps k = 2j, 2j-1 (the term of step 2j rounded to binary32 first)
  *   stats       host, may be NULL
  * If the compressed checkpoints outgrow mem_budget, the call re-plans with half the
  * ratio and runs again (at most three times; the last plan uses the uncompressed
