@@ -399,8 +399,36 @@ def serving_leg(nreq, rate, pool_bytes, max_active, tol, cap, max_batch, saturat
         pmax = [max(p[2][j] for p in lst) for j in range(17)]
         budgets[c] = int(min(cap, 1.5 * full_trajectory_bytes({"profile": pmax}, nt)))
         _, hints[c] = P.plan(nt, pts, budgets[c], pmax)
+        profs[c] = pmax
+    # Per class, the run-time model (wv_choose, fed with the per-unit costs of one plain and
+    # one compressed call of the class's first request at its budget) decides whether
+    # compression pays at that budget; plain checkpoints are exact, so they meet the
+    # tolerance too.  The same calls, run again without events, check the choice.
+    choice, tols = {}, {}
+    for c in sorted(profs):
+        i0 = cls.index(c)
+        _, G, d_obs, _, _, _ = items[i0]
+        _, _, stp = G.misfit_gradient(d_obs, budgets[c], 0.0, timing=TIMING_ACTIONS)
+        _, _, stc = G.misfit_gradient(d_obs, budgets[c], tol, hints[c], timing=TIMING_ACTIONS)
+        ch = P.choose(G.nt, G.P, budgets[c], P.costs_from_stats(stp), P.costs_from_stats(stc), profile=profs[c],
+                      slot_bytes=G.slot_bytes)
+        walls = {}
+        for name, t_, h_ in (("plain", 0.0, 0.0), ("compressed", tol, hints[c])):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            G.misfit_gradient(d_obs, budgets[c], t_, h_)
+            torch.cuda.synchronize()
+            walls[name] = (time.perf_counter() - t0) * 1e3
+        G._ws = None
+        torch.cuda.empty_cache()
+        tols[c] = tol if ch["compressed"] else 0.0
+        choice[str(c)] = {"choice": "compressed" if ch["compressed"] else "plain",
+                          "model_ms": {"plain": ch["ms_plain"], "compressed": ch["ms_compressed"]},
+                          "measured_ms": walls}
+        log(f"serving class {c}: model {ch['ms_plain']:.1f} ms plain, {ch['ms_compressed']:.1f} ms compressed -> "
+            f"{choice[str(c)]['choice']}; measured {walls['plain']:.1f} / {walls['compressed']:.1f} ms")
     for it, c in zip(items, cls):
-        it[3], it[5] = budgets[c], hints[c]
+        it[3], it[4], it[5] = budgets[c], tols[c], (hints[c] if tols[c] > 0 else 0.0)
     items = [tuple(it) for it in items]
     torch.cuda.synchronize()
     eng = Engine(pool_bytes=pool_bytes, max_active=max_active, max_batch=max_batch)
@@ -453,7 +481,7 @@ def serving_leg(nreq, rate, pool_bytes, max_active, tol, cap, max_batch, saturat
             "retried": sum(1 for r in res if r["stats"]["retries"]),
             "p50_ms": pct(lat, 0.5), "p99_ms": pct(lat, 0.99), "req_per_s": nreq / wall,
             "gpts": pts / wall / 1e9, "per_class": per_class, "pool_bytes": pool_bytes, "max_active": max_active,
-            "tol": tol, "ratio_hints": hints, "budgets": budgets,
+            "tol": tol, "ratio_hints": hints, "budgets": budgets, "class_choice": choice,
             "classes": "0: 2-D 512^2 order 8 1500 steps; 1: 3-D 160^3 order 8 1200 steps; "
                        "2: 3-D 256^3 order 12 2000 steps (interior; 20-cell layer; h = 10 m)"}
 
