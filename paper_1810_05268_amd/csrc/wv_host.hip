@@ -963,10 +963,14 @@ struct Fwd {
             HIPCHK(launch_lapw(su.g, u, d.V, d.W, s, le));
             if (kt && (rc = kt->pair(0, &le))) return rc;
             HIPCHK(launch_ot4_update(su.g, d.V, u, up, out, d.W, nullptr, nullptr, nullptr, 0.0, s, le));
+            HIPCHK(launch_inject_src(su.g, d.src, geo->wavelet, n, d.W, out, s));
+        } else if (su.ndim == 2) {
+            // the step's own launch injects the source sample
+            HIPCHK(launch_fwd_step(su.g, u, up, out, d.W, s, le, &d.src, geo->wavelet + n));
         } else {
             HIPCHK(launch_fwd_step(su.g, u, up, out, d.W, s, le));
+            HIPCHK(launch_inject_src(su.g, d.src, geo->wavelet, n, d.W, out, s));
         }
-        HIPCHK(launch_inject_src(su.g, d.src, geo->wavelet, n, d.W, out, s));
         up = u;
         u = out;
         if (data_row) HIPCHK(launch_gather(d.rec, u, data_row, s));
@@ -1374,11 +1378,15 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
                 // step carries its term); an odd first step k = N adds its own
                 int gm = kGAdd;
                 if (uk && d.CR) gm = a % 2 == 0 ? kGCarryOut : (a < N ? kGCarryIn : kGAdd);
+                // 2-D: the step's own launch injects the residual row
+                const bool fused = R.su.ndim == 2;
                 HIPCHK(launch_adj_step(R.su.g, d.Lm[lc], d.Lm[lc ^ 1], d.Lm[lc ^ 1], d.W, uk, R.G, gscale, s, le,
-                                       d.CR, gm));
+                                       d.CR, gm, fused ? &d.rec : nullptr,
+                                       fused ? res + (size_t)a * R.geo->nrec : nullptr));
             }
-            HIPCHK(launch_inject_res(R.su.g, d.rec, res + (size_t)a * R.geo->nrec, d.W, d.Lm[lc ^ 1], uk, R.G,
-                                     gscale, s));
+            if (R.su.g.time_order == 4 || R.su.ndim == 3)
+                HIPCHK(launch_inject_res(R.su.g, d.rec, res + (size_t)a * R.geo->nrec, d.W, d.Lm[lc ^ 1], uk, R.G,
+                                         gscale, s));
             lc ^= 1;
             if (R.src_adj) HIPCHK(launch_gather_sum(d.src, d.Lm[lc], R.src_adj + (a - 1), s));
             R.reverses++;

@@ -54,9 +54,12 @@ struct LaunchEvents {
     hipEvent_t start = nullptr, stop = nullptr;
 };
 // Forward step: u_out = u_in + ((1-a)(u_in - u_prev) + w lap u_in)/(1+a).
-// u_out may equal u_prev (in place); it must differ from u_in.
+// u_out may equal u_prev (in place); it must differ from u_in.  2-D only: with src, the
+// same launch then injects sample q_n (a device pointer) at the table's points, as
+// launch_inject_src would.
 hipError_t launch_fwd_step(const Grid &g, const float *u_in, const float *u_prev, float *u_out, const float *w,
-                           hipStream_t s, LaunchEvents ev = {});
+                           hipStream_t s, LaunchEvents ev = {}, const Sparse *src = nullptr,
+                           const float *q_n = nullptr);
 // How an adjoint step's gradient term t = uk * (w lap lam_in) reaches G.  The carried
 // forms are for 3-D grids: a step with kGCarryOut leaves t, rounded to binary32, in a
 // field-sized array, and the next adjoint step (kGCarryIn) adds it with its own term,
@@ -65,9 +68,12 @@ constexpr int kGNone = 0, kGAdd = 1, kGCarryOut = 2, kGCarryIn = 3;
 // Adjoint step (lam_in = lam^k, lam_next = lam^{k+1}, lam_out = lam^{k-1}, may equal
 // lam_next): the same update, and (if G) G += gscale * uk * (w lap lam_in), or the
 // carried form gmode selects with the array carry (pitched like a field).
+// 2-D only: with rec, the same launch then injects the residual row r_row at the
+// receivers (and their gradient term), as launch_inject_res would.
 hipError_t launch_adj_step(const Grid &g, const float *lam_in, const float *lam_next, float *lam_out,
                            const float *w, const float *uk, double *G, double gscale, hipStream_t s,
-                           LaunchEvents ev = {}, float *carry = nullptr, int gmode = kGAdd);
+                           LaunchEvents ev = {}, float *carry = nullptr, int gmode = kGAdd,
+                           const Sparse *rec = nullptr, const float *r_row = nullptr);
 // OT4, first pass: v_out = w lap f.
 hipError_t launch_lapw(const Grid &g, const float *f, float *v_out, const float *w, hipStream_t s,
                        LaunchEvents ev = {});

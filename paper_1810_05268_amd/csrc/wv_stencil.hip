@@ -435,12 +435,17 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
 // 2-D: a workgroup owns 256 consecutive x and marches down z (the second axis).
 // `prev` and `fout` may be the same array (read, then written, by the same lane).
 // MODE as for the 3-D kernel.
+// With inj_vals set (an OT2 step), the workgroup then injects the scatter table's points
+// inside its strip and rows into the level it has just written, as the separate injection
+// kernel would after the step (the same arithmetic in the same order): a 2-D step is
+// short, and a launch saved is a good part of it.
 template <int K, bool GRAD, int MODE>
 __global__ __launch_bounds__(256) void stencil2d(Grid g, const float *__restrict__ fin, const float *prev,
                                                  float *fout, const float *__restrict__ w,
                                                  const float *__restrict__ uk, const float *__restrict__ xtra,
                                                  const float *__restrict__ xtra2, double *__restrict__ G,
-                                                 double gscale, int tiles_x, int zchunks, int zlen)
+                                                 double gscale, int tiles_x, int zchunks, int zlen, Sparse sp,
+                                                 const float *__restrict__ inj_vals)
 {
     static_assert(!(GRAD && MODE == kLapW), "the w lap pass carries no gradient term");
     __shared__ float row[256 + 2 * K];
@@ -449,6 +454,18 @@ __global__ __launch_bounds__(256) void stencil2d(Grid g, const float *__restrict
     const int tix = lid % tiles_x, zc = lid / tiles_x;
     const int z0 = zc * zlen, z1 = min(z0 + zlen, g.nz);
     march2d<K, GRAD, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, gscale, tix, z0, z1, row);
+    if constexpr (MODE == kOT2) {
+        if (inj_vals) {
+            __syncthreads();
+            const int nx = g.nx, x0 = tix * 256, x1 = min(x0 + 256, nx);
+            for (int i = threadIdx.x; i < sp.npts; i += 256) {
+                const int p = sp.s_pts[i];
+                const int z = p / nx, x = p - z * nx;
+                if (z < z0 || z >= z1 || x < x0 || x >= x1) continue;
+                inject_point<GRAD>(g, sp, i, p, x, 0, z, inj_vals, w, fout, uk, G, p, gscale);
+            }
+        }
+    }
 }
 
 // Adds w s / (1+a) at the source (or receiver) points of the level just written.
@@ -671,7 +688,7 @@ hipError_t launch3d(const Grid &g, const float *fin, const float *prev, float *f
 template <int K, int GM, int MODE>
 hipError_t launch_k(const Grid &g, const float *fin, const float *prev, float *fout, const float *w,
                     const float *uk, const float *xtra, const float *xtra2, double *G, float *cr, double gscale,
-                    hipStream_t s, LaunchEvents ev)
+                    hipStream_t s, LaunchEvents ev, const Sparse *inj, const float *inj_vals)
 {
     if (g.ndim == 3) {
         if (g.nx % 4 == 0)
@@ -688,8 +705,9 @@ hipError_t launch_k(const Grid &g, const float *fin, const float *prev, float *f
     int zchunks, zlen;
     choose_chunks(tiles_x, g.nz, K, 2048, zchunks, zlen);
     const int nwg = tiles_x * zchunks;
+    const Sparse spv = inj ? *inj : Sparse{};
     launch_timed(stencil2d<K, GM == kGAdd, MODE>, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, xtra, xtra2, G,
-                 gscale, tiles_x, zchunks, zlen);
+                 gscale, tiles_x, zchunks, zlen, spv, inj ? inj_vals : (const float *)nullptr);
     return hipGetLastError();
     }
 }
@@ -697,17 +715,19 @@ hipError_t launch_k(const Grid &g, const float *fin, const float *prev, float *f
 template <int GM, int MODE>
 hipError_t launch_any(const Grid &g, const float *fin, const float *prev, float *fout, const float *w,
                       const float *uk, const float *xtra, const float *xtra2, double *G, double gscale, hipStream_t s,
-                      LaunchEvents ev, float *cr = nullptr)
+                      LaunchEvents ev, float *cr = nullptr, const Sparse *inj = nullptr,
+                      const float *inj_vals = nullptr)
 {
+    if (inj && g.ndim != 2) return hipErrorInvalidValue;   // 3-D steps inject in a launch of their own
     switch (g.K) {
-    case 1: return launch_k<1, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
-    case 2: return launch_k<2, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
-    case 3: return launch_k<3, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
-    case 4: return launch_k<4, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
-    case 5: return launch_k<5, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
-    case 6: return launch_k<6, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
-    case 7: return launch_k<7, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
-    case 8: return launch_k<8, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev);
+    case 1: return launch_k<1, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals);
+    case 2: return launch_k<2, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals);
+    case 3: return launch_k<3, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals);
+    case 4: return launch_k<4, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals);
+    case 5: return launch_k<5, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals);
+    case 6: return launch_k<6, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals);
+    case 7: return launch_k<7, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals);
+    case 8: return launch_k<8, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals);
     default: return hipErrorInvalidValue;
     }
 }
@@ -715,21 +735,23 @@ hipError_t launch_any(const Grid &g, const float *fin, const float *prev, float 
 }  // namespace
 
 hipError_t launch_fwd_step(const Grid &g, const float *u_in, const float *u_prev, float *u_out, const float *w,
-                           hipStream_t s, LaunchEvents ev)
+                           hipStream_t s, LaunchEvents ev, const Sparse *src, const float *q_n)
 {
-    return launch_any<kGNone, kOT2>(g, u_in, u_prev, u_out, w, nullptr, nullptr, nullptr, nullptr, 0.0, s, ev);
+    return launch_any<kGNone, kOT2>(g, u_in, u_prev, u_out, w, nullptr, nullptr, nullptr, nullptr, 0.0, s, ev,
+                                    nullptr, src, q_n);
 }
 
 hipError_t launch_adj_step(const Grid &g, const float *lam_in, const float *lam_next, float *lam_out,
                            const float *w, const float *uk, double *G, double gscale, hipStream_t s,
-                           LaunchEvents ev, float *carry, int gmode)
+                           LaunchEvents ev, float *carry, int gmode, const Sparse *rec, const float *r_row)
 {
     if (!G) return launch_any<kGNone, kOT2>(g, lam_in, lam_next, lam_out, w, nullptr, nullptr, nullptr, nullptr, 0.0,
-                                            s, ev);
+                                            s, ev, nullptr, rec, r_row);
     if (gmode != kGAdd && (g.ndim != 3 || !carry)) return hipErrorInvalidValue;
     switch (gmode) {
     case kGAdd:
-        return launch_any<kGAdd, kOT2>(g, lam_in, lam_next, lam_out, w, uk, nullptr, nullptr, G, gscale, s, ev);
+        return launch_any<kGAdd, kOT2>(g, lam_in, lam_next, lam_out, w, uk, nullptr, nullptr, G, gscale, s, ev,
+                                       nullptr, rec, r_row);
     case kGCarryOut:
         return launch_any<kGCarryOut, kOT2>(g, lam_in, lam_next, lam_out, w, uk, nullptr, nullptr, G, gscale, s, ev,
                                             carry);
