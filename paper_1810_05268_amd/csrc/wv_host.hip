@@ -947,6 +947,9 @@ struct Fwd {
     hipStream_t s;
     const float *u = nullptr, *up = nullptr;   // u^n, u^{n-1}
     ActionTimer *kt = nullptr;                  // optional per-launch timing of the stencil (kind 0)
+    // 2-D: the data row of u^n not gathered yet; the next step's launch gathers it, or
+    // flush() after the last step of a run of steps
+    float *pend = nullptr;
     void at(const float *cur, const float *prev)
     {
         u = cur;
@@ -965,15 +968,28 @@ struct Fwd {
             HIPCHK(launch_ot4_update(su.g, d.V, u, up, out, d.W, nullptr, nullptr, nullptr, 0.0, s, le));
             HIPCHK(launch_inject_src(su.g, d.src, geo->wavelet, n, d.W, out, s));
         } else if (su.ndim == 2) {
-            // the step's own launch injects the source sample
-            HIPCHK(launch_fwd_step(su.g, u, up, out, d.W, s, le, &d.src, geo->wavelet + n));
+            // the step's own launch injects the source sample and gathers the previous
+            // step's receivers
+            HIPCHK(launch_fwd_step(su.g, u, up, out, d.W, s, le, &d.src, geo->wavelet + n, pend ? &d.rec : nullptr,
+                                   pend));
+            pend = nullptr;
         } else {
             HIPCHK(launch_fwd_step(su.g, u, up, out, d.W, s, le));
             HIPCHK(launch_inject_src(su.g, d.src, geo->wavelet, n, d.W, out, s));
         }
         up = u;
         u = out;
-        if (data_row) HIPCHK(launch_gather(d.rec, u, data_row, s));
+        if (data_row) {
+            if (su.ndim == 2 && su.g.time_order != 4) pend = data_row;
+            else HIPCHK(launch_gather(d.rec, u, data_row, s));
+        }
+        return WV_OK;
+    }
+    // gathers the pending data row of the current level
+    int flush()
+    {
+        if (pend) HIPCHK(launch_gather(d.rec, u, pend, s));
+        pend = nullptr;
         return WV_OK;
     }
 };
@@ -1132,6 +1148,7 @@ int wv_forward(const wv_model *m, const wv_geom *geo, float *data, float *state_
     f.at(d.Z, d.Z);
     for (int n = 0; n < m->nt; ++n)
         if ((rc = f.step(n, data + (size_t)(n + 1) * geo->nrec))) return rc;
+    if ((rc = f.flush())) return rc;
     if (state_out) {
         // pitched solver rows to the caller's dense layout
         const size_t row = (size_t)su.g.nx * 4, pitch = (size_t)su.g.px * 4, rows = (size_t)su.g.ny * su.g.nz;
@@ -1278,6 +1295,7 @@ int run_gradient(GradRun &R, int M, double ratio_planned, wv_stats *stats, doubl
                     if ((rc = f.step(n, row, dest))) break;
                     if (row) gathered = n + 1;
                 }
+                if (rc == WV_OK) rc = f.flush();
             }
             R.advances += b - a;
             break;

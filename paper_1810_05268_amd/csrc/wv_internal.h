@@ -56,10 +56,11 @@ struct LaunchEvents {
 // Forward step: u_out = u_in + ((1-a)(u_in - u_prev) + w lap u_in)/(1+a).
 // u_out may equal u_prev (in place); it must differ from u_in.  2-D only: with src, the
 // same launch then injects sample q_n (a device pointer) at the table's points, as
-// launch_inject_src would.
+// launch_inject_src would; with rec and row_prev, it also gathers the receivers of u_in
+// (the previous step's level) into row_prev, as launch_gather would.
 hipError_t launch_fwd_step(const Grid &g, const float *u_in, const float *u_prev, float *u_out, const float *w,
                            hipStream_t s, LaunchEvents ev = {}, const Sparse *src = nullptr,
-                           const float *q_n = nullptr);
+                           const float *q_n = nullptr, const Sparse *rec = nullptr, float *row_prev = nullptr);
 // How an adjoint step's gradient term t = uk * (w lap lam_in) reaches G.  The carried
 // forms are for 3-D grids: a step with kGCarryOut leaves t, rounded to binary32, in a
 // field-sized array, and the next adjoint step (kGCarryIn) adds it with its own term,

@@ -438,18 +438,24 @@ __global__ __launch_bounds__(256, 2) void stencil3d(const Grid g, const float *_
 // With inj_vals set (an OT2 step), the workgroup then injects the scatter table's points
 // inside its strip and rows into the level it has just written, as the separate injection
 // kernel would after the step (the same arithmetic in the same order): a 2-D step is
-// short, and a launch saved is a good part of it.
+// short, and a launch saved is a good part of it.  With gout set, one workgroup more
+// gathers the receivers of gin (the level the previous step wrote) into gout.
 template <int K, bool GRAD, int MODE>
 __global__ __launch_bounds__(256) void stencil2d(Grid g, const float *__restrict__ fin, const float *prev,
                                                  float *fout, const float *__restrict__ w,
                                                  const float *__restrict__ uk, const float *__restrict__ xtra,
                                                  const float *__restrict__ xtra2, double *__restrict__ G,
                                                  double gscale, int tiles_x, int zchunks, int zlen, Sparse sp,
-                                                 const float *__restrict__ inj_vals)
+                                                 const float *__restrict__ inj_vals, Sparse gsp,
+                                                 const float *__restrict__ gin, float *__restrict__ gout)
 {
     static_assert(!(GRAD && MODE == kLapW), "the w lap pass carries no gradient term");
     __shared__ float row[256 + 2 * K];
     const int nwg = tiles_x * zchunks;
+    if (gout && (int)blockIdx.x == nwg) {
+        for (int r = threadIdx.x; r < gsp.n; r += 256) gout[r] = gather_point(gsp, r, gin);
+        return;
+    }
     const int lid = xcd_remap(blockIdx.x, nwg);
     const int tix = lid % tiles_x, zc = lid / tiles_x;
     const int z0 = zc * zlen, z1 = min(z0 + zlen, g.nz);
@@ -688,7 +694,8 @@ hipError_t launch3d(const Grid &g, const float *fin, const float *prev, float *f
 template <int K, int GM, int MODE>
 hipError_t launch_k(const Grid &g, const float *fin, const float *prev, float *fout, const float *w,
                     const float *uk, const float *xtra, const float *xtra2, double *G, float *cr, double gscale,
-                    hipStream_t s, LaunchEvents ev, const Sparse *inj, const float *inj_vals)
+                    hipStream_t s, LaunchEvents ev, const Sparse *inj, const float *inj_vals, const Sparse *gsp,
+                    const float *gin, float *gout)
 {
     if (g.ndim == 3) {
         if (g.nx % 4 == 0)
@@ -706,8 +713,10 @@ hipError_t launch_k(const Grid &g, const float *fin, const float *prev, float *f
     choose_chunks(tiles_x, g.nz, K, 2048, zchunks, zlen);
     const int nwg = tiles_x * zchunks;
     const Sparse spv = inj ? *inj : Sparse{};
-    launch_timed(stencil2d<K, GM == kGAdd, MODE>, dim3(nwg), s, ev, g, fin, prev, fout, w, uk, xtra, xtra2, G,
-                 gscale, tiles_x, zchunks, zlen, spv, inj ? inj_vals : (const float *)nullptr);
+    const Sparse gv = (gsp && gout) ? *gsp : Sparse{};
+    float *go = (gsp && gout) ? gout : nullptr;
+    launch_timed(stencil2d<K, GM == kGAdd, MODE>, dim3(nwg + (go ? 1 : 0)), s, ev, g, fin, prev, fout, w, uk, xtra,
+                 xtra2, G, gscale, tiles_x, zchunks, zlen, spv, inj ? inj_vals : (const float *)nullptr, gv, gin, go);
     return hipGetLastError();
     }
 }
@@ -716,18 +725,36 @@ template <int GM, int MODE>
 hipError_t launch_any(const Grid &g, const float *fin, const float *prev, float *fout, const float *w,
                       const float *uk, const float *xtra, const float *xtra2, double *G, double gscale, hipStream_t s,
                       LaunchEvents ev, float *cr = nullptr, const Sparse *inj = nullptr,
-                      const float *inj_vals = nullptr)
+                      const float *inj_vals = nullptr, const Sparse *gsp = nullptr, const float *gin = nullptr,
+                      float *gout = nullptr)
 {
+    if (gout && g.ndim != 2) return hipErrorInvalidValue;
     if (inj && g.ndim != 2) return hipErrorInvalidValue;   // 3-D steps inject in a launch of their own
     switch (g.K) {
-    case 1: return launch_k<1, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals);
-    case 2: return launch_k<2, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals);
-    case 3: return launch_k<3, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals);
-    case 4: return launch_k<4, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals);
-    case 5: return launch_k<5, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals);
-    case 6: return launch_k<6, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals);
-    case 7: return launch_k<7, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals);
-    case 8: return launch_k<8, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals);
+    case 1:
+        return launch_k<1, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals, gsp,
+                                       gin, gout);
+    case 2:
+        return launch_k<2, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals, gsp,
+                                       gin, gout);
+    case 3:
+        return launch_k<3, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals, gsp,
+                                       gin, gout);
+    case 4:
+        return launch_k<4, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals, gsp,
+                                       gin, gout);
+    case 5:
+        return launch_k<5, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals, gsp,
+                                       gin, gout);
+    case 6:
+        return launch_k<6, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals, gsp,
+                                       gin, gout);
+    case 7:
+        return launch_k<7, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals, gsp,
+                                       gin, gout);
+    case 8:
+        return launch_k<8, GM, MODE>(g, fin, prev, fout, w, uk, xtra, xtra2, G, cr, gscale, s, ev, inj, inj_vals, gsp,
+                                       gin, gout);
     default: return hipErrorInvalidValue;
     }
 }
@@ -735,10 +762,11 @@ hipError_t launch_any(const Grid &g, const float *fin, const float *prev, float 
 }  // namespace
 
 hipError_t launch_fwd_step(const Grid &g, const float *u_in, const float *u_prev, float *u_out, const float *w,
-                           hipStream_t s, LaunchEvents ev, const Sparse *src, const float *q_n)
+                           hipStream_t s, LaunchEvents ev, const Sparse *src, const float *q_n, const Sparse *rec,
+                           float *row_prev)
 {
     return launch_any<kGNone, kOT2>(g, u_in, u_prev, u_out, w, nullptr, nullptr, nullptr, nullptr, 0.0, s, ev,
-                                    nullptr, src, q_n);
+                                    nullptr, src, q_n, rec, u_in, row_prev);
 }
 
 hipError_t launch_adj_step(const Grid &g, const float *lam_in, const float *lam_next, float *lam_out,
